@@ -1,0 +1,191 @@
+"""Seeded synthetic snapshots for the extraction path (inputs only).
+
+This module plays the role of the solver that hands snapshots to the in situ
+stage (the paper's section 3: a mesh plus point arrays at the GLL nodes of
+each element).  It holds none of the extraction arithmetic: it places mesh
+nodes and samples closed-form or random-mode velocity fields there.  Both the
+CPU oracle and the HIP library consume exactly the arrays produced here.
+
+Layout: arrays of shape (E, N+1, N+1, N+1), index [e, k, j, i], i fastest;
+elements of a box mesh are numbered e = ex + Ex (ey + Ey ez).
+
+Node placement: GLL points of order N on every element edge, taken from
+numpy's Legendre root finder (a library routine; the oracle and the library
+each compute the nodes independently).  Coordinates come from per-axis 1-D
+global lattices, X[ex N + i], so nodes shared by neighbouring elements are
+bitwise identical.
+
+Arrays are numpy float64 by default; pass ``device=`` (a torch device) to
+build them with torch on that device (used for the large channel snapshot,
+whose random-mode sum is too slow for a single host core).
+"""
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "gll_points", "axis_lattice", "box_mesh", "element_axes", "tgv_velocity",
+    "channel_modes", "channel_velocity", "warp", "tgv_config", "channel_config",
+    "CHANNEL_SHAPE", "TGV_SHAPE",
+]
+
+TGV_SHAPE = (8, 8, 8)          # Taylor-Green box [0, 2 pi]^3, 512 elements
+CHANNEL_SHAPE = (64, 32, 32)   # channel [0, 4 pi] x [-1, 1] x [0, 2 pi]
+CHANNEL_SEED = 2312
+
+
+def gll_points(n):
+    """GLL points of order n on [-1, 1] (numpy Legendre roots of P_n')."""
+    if n < 1:
+        raise ValueError("order must be >= 1")
+    inner = np.sort(np.polynomial.legendre.Legendre.basis(n).deriv().roots().real) \
+        if n > 1 else np.zeros(0)
+    return np.concatenate(([-1.0], inner, [1.0]))
+
+
+def axis_lattice(n_el, n, lo, hi, stretch=None):
+    """1-D global lattice of n_el * n + 1 points on [lo, hi].
+
+    Elements are uniform in the computational coordinate eta in [-1, 1];
+    ``stretch`` = beta applies y = tanh(beta eta) / tanh(beta) pointwise
+    (wall-normal channel clustering), then the result is mapped to [lo, hi].
+    """
+    xi = gll_points(n)
+    g = np.empty(n_el * n + 1)
+    for e in range(n_el):
+        g[e * n:e * n + n + 1] = -1.0 + (2.0 * e + (xi + 1.0)) / n_el
+    g[0], g[-1] = -1.0, 1.0
+    if stretch is not None:
+        g = np.tanh(stretch * g) / math.tanh(stretch)
+    return lo + (hi - lo) * 0.5 * (g + 1.0)
+
+
+def element_axes(shape, elements=None):
+    """(ex, ey, ez) index arrays for the selected elements (default: all)."""
+    ex_n, ey_n, ez_n = shape
+    e = np.arange(ex_n * ey_n * ez_n) if elements is None else np.asarray(elements)
+    return e % ex_n, (e // ex_n) % ey_n, e // (ex_n * ey_n)
+
+
+def box_mesh(shape, n, bounds, stretch=(None, None, None), elements=None,
+             device=None):
+    """Coordinates (x, y, z) of a tensor-product box mesh of order n."""
+    lat = [axis_lattice(shape[a], n, bounds[a][0], bounds[a][1], stretch[a])
+           for a in range(3)]
+    ex, ey, ez = element_axes(shape, elements)
+    p = n + 1
+    loc = np.arange(p)
+    xs = lat[0][ex[:, None] * n + loc[None, :]]      # (E, P) along i
+    ys = lat[1][ey[:, None] * n + loc[None, :]]      # along j
+    zs = lat[2][ez[:, None] * n + loc[None, :]]      # along k
+    e_cnt = xs.shape[0]
+    x = np.broadcast_to(xs[:, None, None, :], (e_cnt, p, p, p))
+    y = np.broadcast_to(ys[:, None, :, None], (e_cnt, p, p, p))
+    z = np.broadcast_to(zs[:, :, None, None], (e_cnt, p, p, p))
+    out = [np.ascontiguousarray(c) for c in (x, y, z)]
+    if device is not None:
+        import torch
+        out = [torch.from_numpy(c).to(device) for c in out]
+    return tuple(out)
+
+
+def _lib(a):
+    if isinstance(a, np.ndarray):
+        return np
+    import torch
+    return torch
+
+
+def tgv_velocity(x, y, z):
+    """Taylor-Green vortex u = sin x cos y cos z, v = -cos x sin y cos z, w = 0."""
+    xp = _lib(x)
+    u = xp.sin(x) * xp.cos(y) * xp.cos(z)
+    v = -xp.cos(x) * xp.sin(y) * xp.cos(z)
+    w = xp.zeros_like(x)
+    return u, v, w
+
+
+def warp(x, y, z, amp=0.05):
+    """Smooth non-affine warp of a box mesh (exercises every Jacobian entry).
+
+    x' = x + a sin(y) sin(z), y' = y + a sin(z) sin(x), z' = z + a sin(x) sin(y)
+    with a small enough that the map stays orientation preserving.
+    """
+    xp = _lib(x)
+    return (x + amp * xp.sin(y) * xp.sin(z),
+            y + amp * xp.sin(z) * xp.sin(x),
+            z + amp * xp.sin(x) * xp.sin(y))
+
+
+def channel_modes(seed=CHANNEL_SEED, shells=32, per_shell=8, rms=0.1):
+    """Random solenoidal Fourier modes with a k^-5/3 shell spectrum.
+
+    Shell n = 1..shells has wavenumber magnitude k = n and ``per_shell``
+    random unit directions d; each mode gets a random unit polarisation
+    sigma orthogonal to d (so the field is divergence free), a random phase
+    and an amplitude proportional to sqrt(E(k) / per_shell) with
+    E(k) = k^-5/3; all amplitudes are then scaled so that the mean square of
+    one velocity component is rms^2.  Returns (kvec (M,3), sigma (M,3),
+    phase (M,), amp (M,)).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kv, sg, ph, am = [], [], [], []
+    for n in range(1, shells + 1):
+        for _ in range(per_shell):
+            d = rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            r = rng.normal(size=3)
+            s = r - np.dot(r, d) * d
+            s /= np.linalg.norm(s)
+            kv.append(n * d)
+            sg.append(s)
+            ph.append(rng.uniform(0.0, 2.0 * np.pi))
+            am.append(math.sqrt(n ** (-5.0 / 3.0) / per_shell))
+    kv, sg, ph, am = map(np.asarray, (kv, sg, ph, am))
+    # mean square of one component of sum a sigma cos(.) is sum a^2 |sigma_c|^2 / 2
+    ms = np.sum(am ** 2) / 2.0 / 3.0
+    am = am * (rms / math.sqrt(ms))
+    return kv, sg, ph, am
+
+
+def channel_velocity(x, y, z, modes=None):
+    """Parabolic mean (1 - y^2, 0, 0) plus the random-mode fluctuation."""
+    xp = _lib(x)
+    kv, sg, ph, am = channel_modes() if modes is None else modes
+    u = 1.0 - y * y
+    v = xp.zeros_like(x)
+    w = xp.zeros_like(x)
+    for m in range(kv.shape[0]):
+        arg = kv[m, 0] * x + kv[m, 1] * y + kv[m, 2] * z + ph[m]
+        c = am[m] * xp.cos(arg)
+        u = u + sg[m, 0] * c
+        v = v + sg[m, 1] * c
+        w = w + sg[m, 2] * c
+    return u, v, w
+
+
+def tgv_config(n=7, shape=TGV_SHAPE, elements=None, device=None):
+    """Taylor-Green snapshot on the uniform [0, 2 pi]^3 box: (x, y, z, u, v, w)."""
+    b = ((0.0, 2 * np.pi),) * 3
+    x, y, z = box_mesh(shape, n, b, elements=elements, device=device)
+    return (x, y, z) + tgv_velocity(x, y, z)
+
+
+def channel_config(n=7, shape=CHANNEL_SHAPE, elements=None, device=None,
+                   beta=2.0, seed=CHANNEL_SEED, dtype=None):
+    """Turbulent-channel-like snapshot: (x, y, z, u, v, w).
+
+    Domain [0, 4 pi] x [-1, 1] x [0, 2 pi], tanh wall-normal stretching
+    (beta = 2) applied pointwise to the GLL node coordinates, so the
+    Jacobian varies from node to node.
+    """
+    b = ((0.0, 4 * np.pi), (-1.0, 1.0), (0.0, 2 * np.pi))
+    x, y, z = box_mesh(shape, n, b, stretch=(None, beta, None),
+                       elements=elements, device=device)
+    vel = channel_velocity(x, y, z, channel_modes(seed))
+    out = (x, y, z) + tuple(vel)
+    if dtype is not None:
+        out = tuple(a.astype(dtype) if isinstance(a, np.ndarray) else a.to(dtype)
+                    for a in out)
+    return out
