@@ -1,0 +1,14 @@
+"""MI355X-native in situ extraction for spectral-element snapshots.
+
+Q-criterion / vorticity magnitude and marching-cubes isosurfaces of fields
+stored at the GLL nodes of order-N hexahedral elements, computed by
+hand-written HIP kernels (gfx950) behind the C ABI of ``include/sem.h``.
+This package is the thin ctypes binding (``_lib``) and the build script
+(``build``); it has no CPU fallback.
+"""
+
+from ._lib import (  # noqa: F401
+    SEM_F32, SEM_F64, SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_MAX_ORDER,
+    SEM_MIN_ORDER, SemError, derivs, gll, init, isosurface, isosurface_into, lib,
+    mc_table, qcrit, status_str, workspace_bytes,
+)

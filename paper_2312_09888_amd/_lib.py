@@ -1,0 +1,293 @@
+"""ctypes binding of libsem.so: the C ABI declared in include/sem.h.
+
+Argument marshalling only -- every step of the extraction runs in the HIP
+kernels behind these calls.  Device buffers are torch tensors (used for
+memory and streams); the library is launched on the current torch stream of
+the tensors' device.  There is no fallback: if libsem.so is missing or
+fails to load, every entry point raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsem.so")
+
+SEM_F64, SEM_F32 = 0, 1
+SEM_OK = 0
+SEM_ERR_ARG, SEM_ERR_ORDER, SEM_ERR_NOT_INIT = -1, -2, -3
+SEM_ERR_HIP, SEM_ERR_WORKSPACE, SEM_ERR_DTYPE = -4, -5, -6
+SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW = 1, 2
+SEM_MIN_ORDER, SEM_MAX_ORDER = 1, 9
+SEM_MAX_ISO = 64
+SEM_MC_MAX_TRI = 5
+
+EXPORTS = (
+    "sem_status_str", "sem_gll", "sem_mc_table", "sem_init", "sem_finalize",
+    "sem_derivs", "sem_qcrit", "sem_isosurface_workspace_bytes", "sem_isosurface",
+)
+
+
+class SemError(RuntimeError):
+    """A SEM_* error code returned by the library."""
+
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {status_str(code)} (code {code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libsem.so once; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"libsem.so not found at {LIB_PATH}; build it with "
+                "`python -m paper_2312_09888_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.sem_status_str.restype = ctypes.c_char_p
+        L.sem_status_str.argtypes = [i32]
+        L.sem_gll.restype = i32
+        L.sem_gll.argtypes = [i32, vp, vp, vp]
+        L.sem_mc_table.restype = i32
+        L.sem_mc_table.argtypes = [vp, vp]
+        L.sem_init.restype = i32
+        L.sem_init.argtypes = [i32]
+        L.sem_finalize.restype = None
+        L.sem_finalize.argtypes = []
+        L.sem_derivs.restype = i32
+        L.sem_derivs.argtypes = [i64, i32, i32] + [vp] * 7 + [vp, vp]
+        L.sem_qcrit.restype = i32
+        L.sem_qcrit.argtypes = [i64, i32, i32] + [vp] * 9 + [vp, vp]
+        L.sem_isosurface_workspace_bytes.restype = ctypes.c_size_t
+        L.sem_isosurface_workspace_bytes.argtypes = [i64, i32, i32]
+        L.sem_isosurface.restype = i32
+        L.sem_isosurface.argtypes = ([i64, i32, i32] + [vp] * 5 + [i32, vp, vp, i64]
+                                     + [vp] * 5 + [ctypes.c_size_t, vp, vp])
+        del dbl
+        _lib = L
+    return _lib
+
+
+def status_str(code):
+    return lib().sem_status_str(int(code)).decode()
+
+
+def _check(code, where):
+    if code != SEM_OK:
+        raise SemError(code, where)
+
+
+# ---------------------------------------------------------------------------
+# host-side queries
+# ---------------------------------------------------------------------------
+
+def gll(order):
+    """(nodes, weights, D) of order N as the library computes them."""
+    p = order + 1
+    nodes = np.zeros(p)
+    weights = np.zeros(p)
+    d = np.zeros((p, p))
+    _check(lib().sem_gll(order, nodes.ctypes.data, weights.ctypes.data, d.ctypes.data),
+           "sem_gll")
+    return nodes, weights, d
+
+
+def mc_table():
+    """(ntri[256] uint8, tri[256, 5, 3] int8) as the kernels use it."""
+    ntri = np.zeros(256, dtype=np.uint8)
+    tri = np.zeros((256, SEM_MC_MAX_TRI, 3), dtype=np.int8)
+    _check(lib().sem_mc_table(ntri.ctypes.data, tri.ctypes.data), "sem_mc_table")
+    return ntri, tri
+
+
+# ---------------------------------------------------------------------------
+# device calls (torch tensors)
+# ---------------------------------------------------------------------------
+
+_ready = set()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def init(device=None):
+    """sem_init for a device index (default: the current torch device)."""
+    torch = _torch()
+    if device is None:
+        device = torch.cuda.current_device()
+    device = int(device)
+    if device not in _ready:
+        _check(lib().sem_init(device), "sem_init")
+        _ready.add(device)
+    return device
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return SEM_F64
+    if t.dtype == torch.float32:
+        return SEM_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _field_check(ref, *ts):
+    """All tensors on ref's device, same dtype and shape, contiguous."""
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda or t.device != ref.device:
+            raise ValueError("all fields must be on the same GPU device")
+        if t.dtype != ref.dtype or t.shape != ref.shape:
+            raise ValueError("fields must share dtype and shape")
+        if not t.is_contiguous():
+            raise ValueError("fields must be contiguous")
+
+
+def _order_of(t):
+    if t.dim() != 4 or not (t.shape[1] == t.shape[2] == t.shape[3]):
+        raise ValueError("fields must have shape (E, N+1, N+1, N+1)")
+    return t.shape[1] - 1
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _status_check(status, ref):
+    torch = _torch()
+    if status is not None and (status.dtype != torch.int32 or status.numel() < 1
+                               or status.device != ref.device):
+        raise ValueError("status must be an int32 tensor on the fields' device")
+
+
+def _stream(t):
+    torch = _torch()
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def derivs(x, y, z, f, status=None):
+    """Physical gradient (df/dx, df/dy, df/dz) of one field."""
+    torch = _torch()
+    _field_check(x, y, z, f)
+    _status_check(status, x)
+    init(x.device.index)
+    _order_of(x)
+    out = [torch.empty_like(f) for _ in range(3)]
+    with torch.cuda.device(x.device):
+        _check(lib().sem_derivs(x.shape[0], _order_of(x), _dtype_code(x), _ptr(x), _ptr(y),
+                                _ptr(z), _ptr(f), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
+                                _ptr(status), _stream(x)), "sem_derivs")
+    return tuple(out)
+
+
+def qcrit(x, y, z, u, v, w, status=None, q=None, omega_mag=None, minmax=None,
+          want=("q", "omega", "minmax")):
+    """Q-criterion, vorticity magnitude and per-element (min, max) of Q."""
+    torch = _torch()
+    _field_check(x, y, z, u, v, w)
+    _field_check(x, q, omega_mag)
+    _status_check(status, x)
+    _order_of(x)
+    init(x.device.index)
+    e = x.shape[0]
+    if minmax is not None and (minmax.numel() < 2 * e or minmax.dtype != x.dtype
+                               or not minmax.is_contiguous() or minmax.device != x.device):
+        raise ValueError("minmax must be a contiguous (E, 2) tensor of the field dtype")
+    if q is None and "q" in want:
+        q = torch.empty_like(u)
+    if omega_mag is None and "omega" in want:
+        omega_mag = torch.empty_like(u)
+    if minmax is None and "minmax" in want:
+        minmax = torch.empty((e, 2), dtype=u.dtype, device=u.device)
+    with torch.cuda.device(x.device):
+        _check(lib().sem_qcrit(e, _order_of(x), _dtype_code(x), _ptr(x), _ptr(y), _ptr(z),
+                               _ptr(u), _ptr(v), _ptr(w), _ptr(q), _ptr(omega_mag),
+                               _ptr(minmax), _ptr(status), _stream(x)), "sem_qcrit")
+    return q, omega_mag, minmax
+
+
+def workspace_bytes(n_elem, order, n_iso):
+    return int(lib().sem_isosurface_workspace_bytes(n_elem, order, n_iso))
+
+
+def isosurface_into(x, y, z, field, isovalues, tri_xyz, tri_count, workspace,
+                    minmax=None, edge_keys=None, active=None, case_idx=None, status=None):
+    """Raw call: write into caller-provided buffers (no allocation, no sync)."""
+    torch = _torch()
+    _field_check(x, y, z, field)
+    _status_check(status, x)
+    _order_of(x)
+    init(x.device.index)
+    iso = np.ascontiguousarray(np.asarray(isovalues, dtype=np.float64))
+    cap = 0 if tri_xyz is None else tri_xyz.shape[0]
+    e, n, k = x.shape[0], _order_of(x), len(iso)
+
+    def need(t, numel, dtypes, what):
+        if t is None:
+            return
+        if not t.is_cuda or t.device != x.device or not t.is_contiguous():
+            raise ValueError(f"{what} must be a contiguous tensor on {x.device}")
+        if t.dtype not in dtypes:
+            raise ValueError(f"{what} has dtype {t.dtype}")
+        if t.numel() < numel:
+            raise ValueError(f"{what} holds {t.numel()} values, needs {numel}")
+
+    if tri_count is None:
+        raise ValueError("tri_count is required")
+    need(tri_count, k, (torch.int64,), "tri_count")
+    need(active, k, (torch.int64,), "active")
+    need(tri_xyz, cap * 9, (x.dtype,), "tri_xyz")
+    need(edge_keys, cap * 3, (torch.int64,), "edge_keys")
+    need(case_idx, k * e * n ** 3, (torch.uint8,), "case_idx")
+    need(minmax, 2 * e, (x.dtype,), "minmax")
+    if e > 0:
+        need(workspace, workspace_bytes(e, n, k), (torch.uint8,), "workspace")
+    with torch.cuda.device(x.device):
+        _check(lib().sem_isosurface(
+            x.shape[0], _order_of(x), _dtype_code(x), _ptr(x), _ptr(y), _ptr(z),
+            _ptr(field), _ptr(minmax), len(iso), iso.ctypes.data, _ptr(tri_xyz), cap,
+            _ptr(edge_keys), _ptr(tri_count), _ptr(active), _ptr(case_idx),
+            _ptr(workspace), 0 if workspace is None else workspace.numel(),
+            _ptr(status), _stream(x)), "sem_isosurface")
+
+
+def isosurface(x, y, z, field, isovalues, minmax=None, edge_keys=False, cases=False,
+               status=None):
+    """Two-phase extraction: count, synchronise, allocate exactly, emit.
+
+    Returns a dict with tri_xyz (T, 3, 3), tri_count (n_iso,), active
+    (n_iso,), and optionally edge_key (T, 3) and cases (n_iso, E, N^3).
+    """
+    torch = _torch()
+    dev = x.device
+    n_iso = len(isovalues)
+    e = x.shape[0]
+    n = _order_of(x)
+    ws = torch.empty(max(workspace_bytes(e, n, n_iso), 1), dtype=torch.uint8, device=dev)
+    tri_count = torch.zeros(n_iso, dtype=torch.int64, device=dev)
+    active = torch.zeros(n_iso, dtype=torch.int64, device=dev)
+    isosurface_into(x, y, z, field, isovalues, None, tri_count, ws, minmax=minmax,
+                    active=active, status=status)
+    total = int(tri_count.sum().item())
+    tri = torch.empty((total, 3, 3), dtype=x.dtype, device=dev)
+    keys = torch.empty((total, 3), dtype=torch.int64, device=dev) if edge_keys else None
+    cidx = (torch.empty((n_iso, e, n ** 3), dtype=torch.uint8, device=dev)
+            if cases else None)
+    isosurface_into(x, y, z, field, isovalues, tri if total else None, tri_count, ws,
+                    minmax=minmax, edge_keys=keys, active=active, case_idx=cidx,
+                    status=status)
+    out = {"tri_xyz": tri, "tri_count": tri_count, "active": active}
+    if edge_keys:
+        out["edge_key"] = keys
+    if cases:
+        out["cases"] = cidx
+    return out

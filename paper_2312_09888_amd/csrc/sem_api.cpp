@@ -1,0 +1,208 @@
+// C ABI of libsem: argument validation, per-device constant tables, launches.
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "sem_internal.h"
+
+namespace sem {
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct DeviceState {
+  bool ready = false;
+  void* buf = nullptr;
+  DeviceTables tab{};
+};
+
+std::mutex g_mutex;
+DeviceState g_dev[kMaxDevices];
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Tables of the current device, or nullptr when sem_init was not called.
+const DeviceTables* current_tables() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  return g_dev[dev].ready ? &g_dev[dev].tab : nullptr;
+}
+
+int check_common(int64_t n_elem, int order, sem_dtype dt) {
+  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+  if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+  if (n_elem < 0 || n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
+  return SEM_OK;
+}
+
+}  // namespace
+
+IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso) {
+  const int64_t count = (int64_t)n_iso * n_elem;
+  const size_t b_cnt = align256((size_t)count * sizeof(int32_t));
+  const size_t b_offs = align256((size_t)(count + 1) * sizeof(int64_t));
+  const size_t b_part = align256((size_t)(scan_blocks(count) + 1) * sizeof(int64_t));
+  IsoWorkspace ws;
+  char* p = static_cast<char*>(base);
+  ws.cnt = reinterpret_cast<int32_t*>(p);
+  ws.offs = reinterpret_cast<int64_t*>(p ? p + b_cnt : nullptr);
+  ws.partial = reinterpret_cast<int64_t*>(p ? p + b_cnt + b_offs : nullptr);
+  ws.bytes = b_cnt + b_offs + b_part;
+  return ws;
+}
+
+}  // namespace sem
+
+using namespace sem;
+
+extern "C" {
+
+const char* sem_status_str(int status) {
+  switch (status) {
+    case SEM_OK: return "ok";
+    case SEM_ERR_ARG: return "invalid argument (NULL pointer, negative size or bad count)";
+    case SEM_ERR_ORDER: return "polynomial order outside the supported range";
+    case SEM_ERR_NOT_INIT: return "sem_init was not called for the current device";
+    case SEM_ERR_HIP: return "HIP runtime call or kernel launch failed";
+    case SEM_ERR_WORKSPACE: return "isosurface workspace missing or too small";
+    case SEM_ERR_DTYPE: return "dtype must be SEM_F64 or SEM_F32";
+    default: return "unknown status";
+  }
+}
+
+int sem_gll(int order, double* nodes, double* weights, double* dmat) {
+  if (order < 1 || order > kMaxBasisOrder) return SEM_ERR_ORDER;
+  return gll_basis(order, nodes, weights, dmat) ? SEM_OK : SEM_ERR_ORDER;
+}
+
+int sem_mc_table(uint8_t* ntri, int8_t* tri) {
+  build_mc_table(ntri, tri);
+  return SEM_OK;
+}
+
+int sem_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return SEM_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  DeviceState& st = g_dev[device];
+  if (st.ready) return SEM_OK;
+  // host tables: D of every order in FP64 and FP32, then the case table
+  size_t off64[kMaxOrder + 1], off32[kMaxOrder + 1];
+  size_t bytes = 0;
+  for (int n = 1; n <= kMaxOrder; ++n) {
+    off64[n] = bytes;
+    bytes += align256(sizeof(double) * (n + 1) * (n + 1));
+  }
+  for (int n = 1; n <= kMaxOrder; ++n) {
+    off32[n] = bytes;
+    bytes += align256(sizeof(float) * (n + 1) * (n + 1));
+  }
+  const size_t off_ntri = bytes;
+  bytes += align256(256);
+  const size_t off_tri = bytes;
+  bytes += align256(256 * kMcMaxTri * 3);
+  std::vector<unsigned char> host(bytes, 0);
+  for (int n = 1; n <= kMaxOrder; ++n) {
+    double* d = reinterpret_cast<double*>(host.data() + off64[n]);
+    gll_basis(n, nullptr, nullptr, d);
+    float* f = reinterpret_cast<float*>(host.data() + off32[n]);
+    for (int q = 0; q < (n + 1) * (n + 1); ++q) f[q] = (float)d[q];
+  }
+  build_mc_table(host.data() + off_ntri, reinterpret_cast<int8_t*>(host.data() + off_tri));
+
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) return SEM_ERR_HIP;
+  if (hipSetDevice(device) != hipSuccess) return SEM_ERR_HIP;
+  void* buf = nullptr;
+  int rc = SEM_OK;
+  if (hipMalloc(&buf, bytes) != hipSuccess ||
+      hipMemcpy(buf, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    if (buf) (void)hipFree(buf);
+    rc = SEM_ERR_HIP;
+  } else {
+    st.buf = buf;
+    char* b = static_cast<char*>(buf);
+    for (int n = 0; n <= kMaxOrder; ++n) {
+      st.tab.d64[n] = n ? reinterpret_cast<const double*>(b + off64[n]) : nullptr;
+      st.tab.d32[n] = n ? reinterpret_cast<const float*>(b + off32[n]) : nullptr;
+    }
+    st.tab.ntri = reinterpret_cast<const uint8_t*>(b + off_ntri);
+    st.tab.tri = reinterpret_cast<const int8_t*>(b + off_tri);
+    st.ready = true;
+  }
+  (void)hipSetDevice(prev);
+  return rc;
+}
+
+void sem_finalize(void) {
+  std::lock_guard<std::mutex> lock(g_mutex);
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  for (int d = 0; d < kMaxDevices; ++d) {
+    if (!g_dev[d].ready) continue;
+    if (hipSetDevice(d) == hipSuccess) (void)hipFree(g_dev[d].buf);
+    g_dev[d] = DeviceState{};
+  }
+  if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+int sem_derivs(int64_t n_elem, int order, sem_dtype dt, const void* x, const void* y,
+               const void* z, const void* f, void* dfdx, void* dfdy, void* dfdz,
+               int32_t* status_word, void* stream) {
+  int rc = check_common(n_elem, order, dt);
+  if (rc) return rc;
+  if (n_elem == 0) return SEM_OK;
+  if (!x || !y || !z || !f || !dfdx || !dfdy || !dfdz) return SEM_ERR_ARG;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  hipError_t e = launch_derivs(order, dt, *tab, n_elem, x, y, z, f, dfdx, dfdy, dfdz,
+                               status_word, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+int sem_qcrit(int64_t n_elem, int order, sem_dtype dt, const void* x, const void* y,
+              const void* z, const void* u, const void* v, const void* w, void* q,
+              void* omega_mag, void* q_minmax, int32_t* status_word, void* stream) {
+  int rc = check_common(n_elem, order, dt);
+  if (rc) return rc;
+  if (n_elem == 0) return SEM_OK;
+  if (!x || !y || !z || !u || !v || !w) return SEM_ERR_ARG;
+  if (!q && !omega_mag && !q_minmax) return SEM_ERR_ARG;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  hipError_t e = launch_qcrit(order, dt, *tab, n_elem, x, y, z, u, v, w, q, omega_mag, q_minmax,
+                              status_word, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+size_t sem_isosurface_workspace_bytes(int64_t n_elem, int order, int n_iso) {
+  (void)order;
+  if (n_elem < 0 || n_iso < 1) return 0;
+  return iso_workspace_layout(nullptr, n_elem, n_iso).bytes;
+}
+
+int sem_isosurface(int64_t n_elem, int order, sem_dtype dt, const void* x, const void* y,
+                   const void* z, const void* field, const void* field_minmax, int n_iso,
+                   const double* iso_host, void* tri_xyz, int64_t tri_capacity,
+                   uint64_t* tri_edge_key, int64_t* tri_count, int64_t* active_cells,
+                   uint8_t* case_idx, void* workspace, size_t workspace_bytes,
+                   int32_t* status_word, void* stream) {
+  int rc = check_common(n_elem, order, dt);
+  if (rc) return rc;
+  if (n_iso < 1 || n_iso > SEM_MAX_ISO || !iso_host || !tri_count) return SEM_ERR_ARG;
+  if (n_elem > 0 && (!x || !y || !z || !field)) return SEM_ERR_ARG;
+  if (tri_capacity < 0 || (tri_capacity > 0 && !tri_xyz)) return SEM_ERR_ARG;
+  if ((int64_t)n_iso * n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
+  IsoWorkspace ws = iso_workspace_layout(workspace, n_elem, n_iso);
+  if (n_elem > 0 && (!workspace || workspace_bytes < ws.bytes)) return SEM_ERR_WORKSPACE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  hipError_t e = launch_isosurface(order, dt, *tab, n_elem, x, y, z, field, field_minmax, n_iso,
+                                   iso_host, tri_xyz, tri_capacity, tri_edge_key, tri_count,
+                                   active_cells, case_idx, ws, status_word,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal declarations shared by the host files and the kernel file.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/sem.h"
+
+namespace sem {
+
+constexpr int kMaxBasisOrder = 15;          // host basis queries
+constexpr int kMaxOrder = SEM_MAX_ORDER;    // kernels
+constexpr int kMcMaxTri = SEM_MC_MAX_TRI;
+
+// sem_basis.cpp
+bool gll_basis(int n, double* nodes, double* weights, double* dmat);
+// sem_mctable.cpp
+void build_mc_table(uint8_t* ntri, int8_t* tri);
+
+// Device-resident constant tables of one GPU.
+struct DeviceTables {
+  const double* d64[kMaxOrder + 1];   // row-major (N+1)^2 per order
+  const float* d32[kMaxOrder + 1];
+  const uint8_t* ntri;                // [256]
+  const int8_t* tri;                  // [256][kMcMaxTri][3]
+};
+
+template <typename T>
+struct IsoList {
+  T v[SEM_MAX_ISO];
+};
+
+// Isosurface workspace layout (offsets in bytes from the workspace start).
+struct IsoWorkspace {
+  int32_t* cnt;       // [n_iso * n_elem] triangles per (isovalue, element)
+  int64_t* offs;      // [n_iso * n_elem + 1] exclusive prefix of cnt
+  int64_t* partial;   // [scan blocks + 1]
+  size_t bytes;
+};
+IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso);
+int64_t scan_blocks(int64_t count);
+
+// sem_kernels.hip -- launchers return hipSuccess or the launch error.
+hipError_t launch_derivs(int order, sem_dtype dt, const DeviceTables& tab,
+                         int64_t n_elem, const void* x, const void* y,
+                         const void* z, const void* f, void* gx, void* gy,
+                         void* gz, int32_t* status, hipStream_t s);
+
+hipError_t launch_qcrit(int order, sem_dtype dt, const DeviceTables& tab,
+                        int64_t n_elem, const void* x, const void* y,
+                        const void* z, const void* u, const void* v,
+                        const void* w, void* q, void* om, void* qmm,
+                        int32_t* status, hipStream_t s);
+
+hipError_t launch_isosurface(int order, sem_dtype dt, const DeviceTables& tab,
+                             int64_t n_elem, const void* x, const void* y,
+                             const void* z, const void* field,
+                             const void* field_minmax, int n_iso,
+                             const double* iso_host, void* tri_xyz,
+                             int64_t tri_capacity, uint64_t* tri_edge_key,
+                             int64_t* tri_count, int64_t* active_cells,
+                             uint8_t* case_idx, const IsoWorkspace& ws,
+                             int32_t* status, hipStream_t s);
+
+}  // namespace sem

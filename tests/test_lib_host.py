@@ -1,0 +1,149 @@
+"""CPU tests of libsem: it loads, exports every declared symbol, its host-side
+basis and case table agree with the oracle's independent computations, and
+host-detectable argument errors are returned before any device work."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2312_09888_amd as sem
+from paper_2312_09888_amd import _lib
+from oracle import gll, mc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sem.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sem_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 9
+    lib = sem.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    for name, val in (("SEM_MAX_ORDER", _lib.SEM_MAX_ORDER), ("SEM_MAX_ISO", _lib.SEM_MAX_ISO),
+                      ("SEM_MC_MAX_TRI", _lib.SEM_MC_MAX_TRI),
+                      ("SEM_MIN_ORDER", _lib.SEM_MIN_ORDER)):
+        assert re.search(rf"#define {name} {val}\b", text), name
+
+
+@pytest.mark.parametrize("n", range(1, 16))
+def test_library_basis_matches_oracle(n):
+    xi, w, d = sem.gll(n)
+    np.testing.assert_allclose(xi, gll.gll_nodes(n), rtol=0, atol=2.3e-16)
+    np.testing.assert_allclose(w, gll.gll_weights(n), rtol=0, atol=4e-16)
+    np.testing.assert_allclose(d, gll.diff_matrix(n), rtol=0, atol=1e-14 * n * n)
+
+
+def test_library_case_table_equals_oracle_entry_by_entry():
+    ntri, tri = sem.mc_table()
+    o_ntri, o_tri = mc.case_table()
+    assert o_tri.shape == tri.shape
+    np.testing.assert_array_equal(ntri, o_ntri)
+    np.testing.assert_array_equal(tri, o_tri)
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert sem.status_str(code)
+    assert sem.status_str(123) == "unknown status"
+
+
+def test_gll_rejects_bad_order():
+    L = sem.lib()
+    assert L.sem_gll(0, None, None, None) == _lib.SEM_ERR_ORDER
+    assert L.sem_gll(16, None, None, None) == _lib.SEM_ERR_ORDER
+
+
+# Fake, never-dereferenced addresses: every call below must fail validation.
+FAKE = ctypes.c_void_p(0x1000)
+
+
+def _qcrit(**kw):
+    a = dict(n=4, order=7, dt=0, x=FAKE, y=FAKE, z=FAKE, u=FAKE, v=FAKE, w=FAKE,
+             q=FAKE, om=FAKE, mm=None)
+    a.update(kw)
+    return sem.lib().sem_qcrit(a["n"], a["order"], a["dt"], a["x"], a["y"], a["z"], a["u"],
+                               a["v"], a["w"], a["q"], a["om"], a["mm"], None, None)
+
+
+def test_qcrit_argument_errors():
+    assert _qcrit(order=0) == _lib.SEM_ERR_ORDER
+    assert _qcrit(order=10) == _lib.SEM_ERR_ORDER
+    assert _qcrit(dt=7) == _lib.SEM_ERR_DTYPE
+    assert _qcrit(n=-1) == _lib.SEM_ERR_ARG
+    assert _qcrit(x=None) == _lib.SEM_ERR_ARG
+    assert _qcrit(w=None) == _lib.SEM_ERR_ARG
+    assert _qcrit(q=None, om=None, mm=None) == _lib.SEM_ERR_ARG
+    assert _qcrit(n=0) == _lib.SEM_OK            # empty call is a no-op
+
+
+def test_derivs_argument_errors():
+    L = sem.lib()
+    f = FAKE
+    assert L.sem_derivs(4, 0, 0, f, f, f, f, f, f, f, None, None) == _lib.SEM_ERR_ORDER
+    assert L.sem_derivs(4, 7, 2, f, f, f, f, f, f, f, None, None) == _lib.SEM_ERR_DTYPE
+    assert L.sem_derivs(4, 7, 0, f, f, f, None, f, f, f, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_derivs(4, 7, 0, f, f, f, f, f, f, None, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_derivs(0, 7, 0, f, f, f, f, f, f, f, None, None) == _lib.SEM_OK
+
+
+def _iso(**kw):
+    iso = np.array([0.1, 0.2])
+    a = dict(n=4, order=7, dt=0, field=FAKE, n_iso=2, iso=iso.ctypes.data, tri=FAKE, cap=10,
+             count=FAKE, ws=FAKE, ws_bytes=1 << 30)
+    a.update(kw)
+    return sem.lib().sem_isosurface(a["n"], a["order"], a["dt"], FAKE, FAKE, FAKE, a["field"],
+                                    None, a["n_iso"], a["iso"], a["tri"], a["cap"], None,
+                                    a["count"], None, None, a["ws"], a["ws_bytes"], None, None)
+
+
+def test_isosurface_argument_errors():
+    assert _iso(order=0) == _lib.SEM_ERR_ORDER
+    assert _iso(dt=3) == _lib.SEM_ERR_DTYPE
+    assert _iso(n_iso=0) == _lib.SEM_ERR_ARG
+    assert _iso(n_iso=_lib.SEM_MAX_ISO + 1) == _lib.SEM_ERR_ARG
+    assert _iso(iso=None) == _lib.SEM_ERR_ARG
+    assert _iso(count=None) == _lib.SEM_ERR_ARG
+    assert _iso(field=None) == _lib.SEM_ERR_ARG
+    assert _iso(cap=-1) == _lib.SEM_ERR_ARG
+    assert _iso(tri=None) == _lib.SEM_ERR_ARG          # capacity > 0 needs a buffer
+    assert _iso(ws=None) == _lib.SEM_ERR_WORKSPACE
+    need = sem.workspace_bytes(4, 7, 2)
+    assert _iso(ws_bytes=need - 1) == _lib.SEM_ERR_WORKSPACE
+
+
+def test_workspace_size_grows_with_problem():
+    a = sem.workspace_bytes(1000, 7, 1)
+    b = sem.workspace_bytes(1000, 7, 3)
+    c = sem.workspace_bytes(100000, 7, 3)
+    assert 0 < a < b < c
+    assert c >= 100000 * 3 * (4 + 8)
+    assert sem.workspace_bytes(10, 7, 0) == 0
+
+
+def _no_gpu():
+    try:
+        import torch
+        return torch.cuda.device_count() == 0
+    except Exception:  # pragma: no cover
+        return True
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="only meaningful where no device exists")
+def test_compute_without_device_reports_not_initialised():
+    assert _qcrit() == _lib.SEM_ERR_NOT_INIT
+    assert sem.lib().sem_init(0) in (_lib.SEM_ERR_HIP, _lib.SEM_ERR_ARG)
