@@ -275,8 +275,10 @@ def isosurface(x, y, z, field, isovalues, minmax=None, edge_keys=False, cases=Fa
     ws = torch.empty(max(workspace_bytes(e, n, n_iso), 1), dtype=torch.uint8, device=dev)
     tri_count = torch.zeros(n_iso, dtype=torch.int64, device=dev)
     active = torch.zeros(n_iso, dtype=torch.int64, device=dev)
+    # count-only phase: its capacity is 0, so it must not touch the caller's
+    # status word (the overflow flag would be set by design)
     isosurface_into(x, y, z, field, isovalues, None, tri_count, ws, minmax=minmax,
-                    active=active, status=status)
+                    active=active, status=None)
     total = int(tri_count.sum().item())
     tri = torch.empty((total, 3, 3), dtype=x.dtype, device=dev)
     keys = torch.empty((total, 3), dtype=torch.int64, device=dev) if edge_keys else None

@@ -261,6 +261,21 @@ def test_isosurface_deterministic():
 # end to end: Q on the GPU, then its isosurface
 # --------------------------------------------------------------------------
 
+def _band_check(cases_gpu, cases_ref, q_ref, c_ref, band, n):
+    """Cells may differ only where a node lies within `band` of the isovalue."""
+    p = n + 1
+    e_cnt = q_ref.shape[0]
+    near = (np.abs(q_ref - c_ref) <= band).reshape(e_cnt, p, p, p)
+    cell_near = np.zeros((e_cnt, n, n, n), dtype=bool)
+    for a in (0, 1):
+        for b in (0, 1):
+            for cc in (0, 1):
+                cell_near |= near[:, cc:cc + n, b:b + n, a:a + n]
+    bad = cases_gpu.reshape(e_cnt, -1) != cases_ref.reshape(e_cnt, -1)
+    assert not np.any(bad & ~cell_near.reshape(e_cnt, -1))
+    return int(bad.sum())
+
+
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_taylor_green_end_to_end_counts_bit_exact(dt):
     n, c = 7, 0.1
@@ -271,8 +286,13 @@ def test_taylor_green_end_to_end_counts_bit_exact(dt):
     oq, _, _ = osem.qcrit(*(a.astype(np.float64) for a in arrs), gll.diff_matrix(n))
     o = mc.extract(*(a.astype(np.float64) for a in arrs[:3]), oq, [c])
     diff = np.abs(host(q).astype(np.float64) - oq).max()
-    margin = np.abs(oq - float(dt(c))).min()
-    assert margin > 1e3 * diff, (margin, diff)
+    c_dt = float(dt(c))
+    band = diff + abs(c_dt - c)
+    margin = np.abs(oq - c).min()
+    mism = _band_check(host(r["cases"])[0], o["cases"][0], oq, c, band, n)
+    # the closed-form margin of this snapshot (3.1e-4) exceeds the band
+    assert margin > band, (margin, band)
+    assert mism == 0
     np.testing.assert_array_equal(host(r["tri_count"]), o["tri_count"])
     np.testing.assert_array_equal(host(r["active"]), o["active"])
     np.testing.assert_array_equal(host(r["cases"]), o["cases"])
