@@ -123,8 +123,7 @@ def main():
 
     # exact triangle count once (untimed), then a buffer that holds it
     sem.qcrit(x, y, z, u, v, w, status=status, q=q, omega_mag=om, minmax=mm)
-    sem.isosurface_into(x, y, z, q, isos, None, cnt, ws, minmax=mm, active=act,
-                        status=status)
+    sem.isosurface_into(x, y, z, q, isos, None, cnt, ws, minmax=mm, active=act)
     torch.cuda.synchronize()
     counts = cnt.cpu().tolist()
     total_tri = int(sum(counts))
