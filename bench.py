@@ -2,9 +2,10 @@
 """Benchmark: GLL points/s through Q-criterion + isosurface extraction.
 
 One step = the whole extraction path over one synthetic snapshot already
-resident in HBM: sem_qcrit (Q, |omega| and per-element Q range) followed by
-sem_isosurface (cull, classify, scan-compact and emit the triangles of every
-isovalue).  Workload: the turbulent-channel snapshot -- 64 x 32 x 32 = 65,536
+resident in HBM: one sem_extract call (Q, |omega|, per-element Q range, and
+the cull / classify / scan-compact / emit of the triangles of every
+isovalue, fused in a single pass).  The same work as two calls
+(sem_qcrit, then sem_isosurface) is timed beside it for comparison.  Workload: the turbulent-channel snapshot -- 64 x 32 x 32 = 65,536
 order-7 hexahedra (33,554,432 GLL points), tanh wall stretching (beta = 2),
 parabolic mean plus a seeded random-phase k^-5/3 velocity field -- with Q
 isosurfaces at the 90th, 95th and 99th percentiles of Q.
@@ -26,8 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-QCRIT_KERNEL = "qcrit_tile"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "qcrit_channel65536_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "extract_channel65536_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2312_09888_amd", "csrc", "sem_kernels.hip")
 
 
@@ -112,30 +112,28 @@ def main():
               f"({points} points, {args.dtype})")
 
     sem.init(0)
+    k_iso = len(isos)
+    dcode = sem.SEM_F64 if args.dtype == "f64" else sem.SEM_F32
     q = torch.empty_like(u)
     om = torch.empty_like(u)
     mm = torch.empty((n_elem, 2), dtype=tdt, device=devn)
     status = torch.zeros(1, dtype=torch.int32, device=devn)
-    ws = torch.empty(sem.workspace_bytes(n_elem, n, len(isos)), dtype=torch.uint8,
+    ws = torch.empty(sem.extract_workspace_bytes(n_elem, n, k_iso, dcode), dtype=torch.uint8,
                      device=devn)
-    cnt = torch.zeros(len(isos), dtype=torch.int64, device=devn)
-    act = torch.zeros(len(isos), dtype=torch.int64, device=devn)
+    cnt = torch.zeros(k_iso, dtype=torch.int64, device=devn)
+    act = torch.zeros(k_iso, dtype=torch.int64, device=devn)
 
-    # exact triangle count once (untimed), then a buffer that holds it
-    sem.qcrit(x, y, z, u, v, w, status=status, q=q, omega_mag=om, minmax=mm)
-    sem.isosurface_into(x, y, z, q, isos, None, cnt, ws, minmax=mm, active=act)
+    # exact triangle counts once (untimed count-only call), then buffers
+    sem.extract_into(x, y, z, u, v, w, isos, [None] * k_iso, cnt, ws, active=act)
     torch.cuda.synchronize()
     counts = cnt.cpu().tolist()
     total_tri = int(sum(counts))
-    tri = torch.empty((max(total_tri, 1), 3, 3), dtype=tdt, device=devn)
+    tris = [torch.empty((c, 3, 3), dtype=tdt, device=devn) for c in counts]
     log(args, f"isovalues {isos} -> triangles {counts}, active cells {act.cpu().tolist()}")
 
     def step():
-        sem.qcrit(x, y, z, u, v, w, status=status, q=q, omega_mag=om, minmax=mm)
-        ev_mid = torch.cuda.Event(enable_timing=True)
-        ev_mid.record()
-        sem.isosurface_into(x, y, z, q, isos, tri, cnt, ws, minmax=mm, status=status)
-        return ev_mid
+        sem.extract_into(x, y, z, u, v, w, isos, tris, cnt, ws, q=q, omega_mag=om,
+                         minmax=mm, status=status)
 
     for _ in range(args.warmup):
         step()
@@ -149,45 +147,62 @@ def main():
     t_begin.record()
     for _ in range(args.steps):
         e0 = torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        e1 = step()
-        e2.record()
-        evs.append((e0, e1, e2))
+        step()
+        e1.record()
+        evs.append((e0, e1))
     t_end.record()
     torch.cuda.synchronize()
     total_ms = t_begin.elapsed_time(t_end)
     ms_step = total_ms / args.steps
-    q_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
-    iso_ms = float(np.mean([b.elapsed_time(c) for _, b, c in evs]))
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     flags = int(status.item())
     if flags:
         print(f"device status flags set: {flags}", file=sys.stderr)
         sys.exit(1)
+    if cnt.cpu().tolist() != counts:
+        print("triangle counts changed between steps", file=sys.stderr)
+        sys.exit(1)
     log(args, f"timed {args.steps} steps: {ms_step:.4f} ms/step "
-              f"(qcrit {q_ms:.4f} ms, isosurface {iso_ms:.4f} ms)")
+              f"(sem_extract launch average {k_ms:.4f} ms)")
+
+    # the same path as two calls (sem_qcrit, then sem_isosurface), for comparison
+    iws = torch.empty(sem.workspace_bytes(n_elem, n, k_iso), dtype=torch.uint8, device=devn)
+    tri_all = torch.empty((max(total_tri, 1), 3, 3), dtype=tdt, device=devn)
+    reps = max(3, args.steps // 4)
+    torch.cuda.synchronize()
+    a0 = torch.cuda.Event(enable_timing=True)
+    a1 = torch.cuda.Event(enable_timing=True)
+    a2 = torch.cuda.Event(enable_timing=True)
+    qc_ms = iso_ms = 0.0
+    for _ in range(reps):
+        a0.record()
+        sem.qcrit(x, y, z, u, v, w, q=q, omega_mag=om, minmax=mm)
+        a1.record()
+        sem.isosurface_into(x, y, z, q, isos, tri_all, cnt, iws, minmax=mm)
+        a2.record()
+        torch.cuda.synchronize()
+        qc_ms += a0.elapsed_time(a1) / reps
+        iso_ms += a1.elapsed_time(a2) / reps
+    log(args, f"two-call path: sem_qcrit {qc_ms:.4f} ms + sem_isosurface {iso_ms:.4f} ms")
 
     esz = 8 if args.dtype == "f64" else 4
-    # algorithmic bytes of the Q kernel: read x,y,z,u,v,w, write Q and |omega|,
-    # plus the per-element (min, max)
-    q_bytes = points * 8 * esz + n_elem * 2 * esz
-    q_gbs = q_bytes / (q_ms * 1e-3) / 1e9
-    # whole path: the Q kernel's bytes plus 9 coordinates per output triangle
-    path_bytes = q_bytes + total_tri * 9 * esz
-    path_gbs = path_bytes / (ms_step * 1e-3) / 1e9
-    dominant = "qcrit" if q_ms >= iso_ms else "isosurface"
+    # algorithmic bytes of one fused launch: read x,y,z,u,v,w, write Q,
+    # |omega|, the per-element (min, max) and 9 coordinates per triangle
+    k_bytes = points * 8 * esz + n_elem * 2 * esz + total_tri * 9 * esz
+    k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(points)
     roof = {
         "bound": "hbm",
-        "kernel": f"{QCRIT_KERNEL}<7,{'double' if esz == 8 else 'float'}>",
-        "achieved": round(q_gbs, 1),
+        "kernel": f"extract_pencil<7,{'double' if esz == 8 else 'float'}>",
+        "achieved": round(k_gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
-        "frac": round(q_gbs / HBM_PEAK_GBS, 4),
+        "frac": round(k_gbs / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "avg_ms": round(q_ms, 5),
-        "algorithmic_bytes_per_launch": q_bytes,
-        "dominant_stage": dominant,
+        "avg_ms": round(k_ms, 5),
+        "algorithmic_bytes_per_launch": k_bytes,
     }
     result = {
         "metric": "GLL points/sec through Q-criterion+isosurface, % HBM roofline, plain vs mixed",
@@ -210,10 +225,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": roof,
-        "path_roofline": {"achieved": round(path_gbs, 1), "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": round(path_gbs / HBM_PEAK_GBS, 4),
-                          "algorithmic_bytes_per_step": path_bytes},
-        "stage_ms": {"qcrit": round(q_ms, 5), "isosurface": round(iso_ms, 5)},
+        "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
     }
 
     if args.cpu_baseline == "on":

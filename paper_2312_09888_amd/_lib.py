@@ -26,6 +26,7 @@ SEM_MC_MAX_TRI = 5
 EXPORTS = (
     "sem_status_str", "sem_gll", "sem_mc_table", "sem_init", "sem_finalize",
     "sem_derivs", "sem_qcrit", "sem_isosurface_workspace_bytes", "sem_isosurface",
+    "sem_extract_workspace_bytes", "sem_extract",
 )
 
 
@@ -69,6 +70,11 @@ def lib():
         L.sem_isosurface.restype = i32
         L.sem_isosurface.argtypes = ([i64, i32, i32] + [vp] * 5 + [i32, vp, vp, i64]
                                      + [vp] * 5 + [ctypes.c_size_t, vp, vp])
+        L.sem_extract_workspace_bytes.restype = ctypes.c_size_t
+        L.sem_extract_workspace_bytes.argtypes = [i64, i32, i32, i32]
+        L.sem_extract.restype = i32
+        L.sem_extract.argtypes = ([i64, i32, i32] + [vp] * 9 + [i32, vp, vp, vp, vp, vp,
+                                                                vp, ctypes.c_size_t, vp, vp])
         del dbl
         _lib = L
     return _lib
@@ -293,3 +299,77 @@ def isosurface(x, y, z, field, isovalues, minmax=None, edge_keys=False, cases=Fa
     if cases:
         out["cases"] = cidx
     return out
+
+
+def extract_workspace_bytes(n_elem, order, n_iso, dtype_code=SEM_F64):
+    return int(lib().sem_extract_workspace_bytes(n_elem, order, n_iso, dtype_code))
+
+
+def extract_into(x, y, z, u, v, w, isovalues, tri_list, tri_count, workspace, q=None,
+                 omega_mag=None, minmax=None, active=None, status=None):
+    """Raw fused call: tri_list[s] is a (cap_s, 3, 3) tensor or None (count only)."""
+    torch = _torch()
+    _field_check(x, y, z, u, v, w)
+    _field_check(x, q, omega_mag)
+    _status_check(status, x)
+    n = _order_of(x)
+    init(x.device.index)
+    iso = np.ascontiguousarray(np.asarray(isovalues, dtype=np.float64))
+    k, e = len(iso), x.shape[0]
+    if len(tri_list) != k:
+        raise ValueError("one triangle buffer (or None) per isovalue")
+    caps = np.zeros(k, dtype=np.int64)
+    ptrs = (ctypes.c_void_p * k)()
+    for s, t in enumerate(tri_list):
+        if t is None:
+            continue
+        if (not t.is_cuda or t.device != x.device or t.dtype != x.dtype
+                or not t.is_contiguous() or t.dim() != 3 or tuple(t.shape[1:]) != (3, 3)):
+            raise ValueError("triangle buffers must be contiguous (cap, 3, 3) tensors")
+        caps[s] = t.shape[0]
+        ptrs[s] = t.data_ptr() if t.shape[0] else None
+    for t, numel, what in ((tri_count, k, "tri_count"), (active, k, "active")):
+        if t is not None and (t.dtype != torch.int64 or t.numel() < numel
+                              or t.device != x.device or not t.is_contiguous()):
+            raise ValueError(f"{what} must be an int64 tensor of >= {numel} values")
+    if tri_count is None:
+        raise ValueError("tri_count is required")
+    if minmax is not None and (minmax.numel() < 2 * e or minmax.dtype != x.dtype
+                               or not minmax.is_contiguous() or minmax.device != x.device):
+        raise ValueError("minmax must be a contiguous (E, 2) tensor of the field dtype")
+    need = extract_workspace_bytes(e, n, k, _dtype_code(x))
+    if e > 0 and (workspace is None or workspace.dtype != torch.uint8
+                  or workspace.numel() < need or workspace.device != x.device):
+        raise ValueError(f"workspace must be a uint8 tensor of >= {need} bytes")
+    with torch.cuda.device(x.device):
+        _check(lib().sem_extract(
+            e, n, _dtype_code(x), _ptr(x), _ptr(y), _ptr(z), _ptr(u), _ptr(v), _ptr(w),
+            _ptr(q), _ptr(omega_mag), _ptr(minmax), k, iso.ctypes.data,
+            ctypes.cast(ptrs, ctypes.c_void_p), caps.ctypes.data, _ptr(tri_count),
+            _ptr(active), _ptr(workspace), 0 if workspace is None else workspace.numel(),
+            _ptr(status), _stream(x)), "sem_extract")
+
+
+def extract(x, y, z, u, v, w, isovalues, status=None, want_fields=True):
+    """Fused Q / |omega| / isosurfaces with exact allocation (two calls).
+
+    Returns a dict: q, omega_mag, minmax (when want_fields), tri (list of
+    (T_s, 3, 3) tensors, one per isovalue), tri_count, active.
+    """
+    torch = _torch()
+    dev = x.device
+    k, e, n = len(isovalues), x.shape[0], _order_of(x)
+    ws = torch.empty(max(extract_workspace_bytes(e, n, k, _dtype_code(x)), 1),
+                     dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(k, dtype=torch.int64, device=dev)
+    act = torch.zeros(k, dtype=torch.int64, device=dev)
+    extract_into(x, y, z, u, v, w, isovalues, [None] * k, cnt, ws)
+    counts = cnt.cpu().tolist()
+    tris = [torch.empty((c, 3, 3), dtype=x.dtype, device=dev) for c in counts]
+    q = torch.empty_like(u) if want_fields else None
+    om = torch.empty_like(u) if want_fields else None
+    mm = torch.empty((e, 2), dtype=u.dtype, device=dev) if want_fields else None
+    extract_into(x, y, z, u, v, w, isovalues, tris, cnt, ws, q=q, omega_mag=om, minmax=mm,
+                 active=act, status=status)
+    return {"q": q, "omega_mag": om, "minmax": mm, "tri": tris, "tri_count": cnt,
+            "active": act}

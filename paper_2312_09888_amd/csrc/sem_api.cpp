@@ -53,6 +53,39 @@ IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso) {
   return ws;
 }
 
+ExtractWorkspace extract_workspace_layout(void* base, int64_t n_elem, int n_iso) {
+  const int64_t words = (int64_t)n_iso * n_elem;
+  const size_t b_lb = align256((size_t)words * sizeof(uint64_t));
+  ExtractWorkspace ws;
+  char* p = static_cast<char*>(base);
+  ws.lookback = reinterpret_cast<uint64_t*>(p);
+  ws.ticket = reinterpret_cast<uint32_t*>(p ? p + b_lb : nullptr);
+  ws.bytes = b_lb + 256;
+  return ws;
+}
+
+namespace {
+
+// Orders above 7 run Q and the isosurface as separate passes; Q and its
+// element ranges then need storage, taken from the workspace when the
+// caller does not want them.
+struct ExtractFallback {
+  size_t iso_bytes, q_off, mm_off, bytes;
+};
+
+ExtractFallback extract_fallback_layout(int64_t n_elem, int order, int n_iso, sem_dtype dt) {
+  const size_t esz = dt == SEM_F64 ? sizeof(double) : sizeof(float);
+  const size_t p3 = (size_t)(order + 1) * (order + 1) * (order + 1);
+  ExtractFallback f;
+  f.iso_bytes = iso_workspace_layout(nullptr, n_elem, n_iso).bytes;
+  f.q_off = f.iso_bytes;
+  f.mm_off = f.q_off + align256((size_t)n_elem * p3 * esz);
+  f.bytes = f.mm_off + align256((size_t)n_elem * 2 * esz);
+  return f;
+}
+
+}  // namespace
+
 }  // namespace sem
 
 using namespace sem;
@@ -173,6 +206,49 @@ int sem_qcrit(int64_t n_elem, int order, sem_dtype dt, const void* x, const void
   if (!tab) return SEM_ERR_NOT_INIT;
   hipError_t e = launch_qcrit(order, dt, *tab, n_elem, x, y, z, u, v, w, q, omega_mag, q_minmax,
                               status_word, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+size_t sem_extract_workspace_bytes(int64_t n_elem, int order, int n_iso, sem_dtype dt) {
+  if (check_common(n_elem, order, dt) != SEM_OK || n_iso < 1 || n_iso > SEM_MAX_ISO) return 0;
+  if (order <= 7) return extract_workspace_layout(nullptr, n_elem, n_iso).bytes;
+  return extract_fallback_layout(n_elem, order, n_iso, dt).bytes;
+}
+
+int sem_extract(int64_t n_elem, int order, sem_dtype dt, const void* x, const void* y,
+                const void* z, const void* u, const void* v, const void* w, void* q,
+                void* omega_mag, void* q_minmax, int n_iso, const double* iso_host,
+                void* const* tri_xyz, const int64_t* tri_capacity, int64_t* tri_count,
+                int64_t* active_cells, void* workspace, size_t workspace_bytes,
+                int32_t* status_word, void* stream) {
+  int rc = check_common(n_elem, order, dt);
+  if (rc) return rc;
+  if (n_iso < 1 || n_iso > SEM_MAX_ISO || !iso_host || !tri_count) return SEM_ERR_ARG;
+  if (!tri_xyz || !tri_capacity) return SEM_ERR_ARG;
+  for (int k = 0; k < n_iso; ++k)
+    if (tri_capacity[k] < 0 || (tri_capacity[k] > 0 && !tri_xyz[k])) return SEM_ERR_ARG;
+  if ((int64_t)n_iso * n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
+  if (n_elem > 0 && (!x || !y || !z || !u || !v || !w)) return SEM_ERR_ARG;
+  const size_t need = sem_extract_workspace_bytes(n_elem, order, n_iso, dt);
+  if (n_elem > 0 && (!workspace || workspace_bytes < need)) return SEM_ERR_WORKSPACE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n_elem == 0) {
+    hipError_t e = launch_isosurface(order, dt, *tab, 0, nullptr, nullptr, nullptr, nullptr,
+                                     nullptr, n_iso, iso_host, nullptr, 0, nullptr, tri_count,
+                                     active_cells, nullptr, IsoWorkspace{}, status_word, s);
+    return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+  }
+  if (order > 7) {
+    const ExtractFallback f = extract_fallback_layout(n_elem, order, n_iso, dt);
+    char* b = static_cast<char*>(workspace);
+    if (!q) q = b + f.q_off;
+    if (!q_minmax) q_minmax = b + f.mm_off;
+  }
+  hipError_t e = launch_extract(order, dt, *tab, n_elem, x, y, z, u, v, w, q, omega_mag,
+                                q_minmax, n_iso, iso_host, tri_xyz, tri_capacity, tri_count,
+                                active_cells, workspace, status_word, s);
   return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
 }
 

@@ -277,6 +277,257 @@ qcrit_tile(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restr
 }
 
 // ---------------------------------------------------------------------------
+// gradient / Q-criterion, pencil form (N <= 7): two waves per element
+// ---------------------------------------------------------------------------
+//
+// Lane p < (N+1)^2 of each wave owns the r-line (j, k) = (p % P, p / P) of
+// the element; wave h owns the nodes i in [h*H0, h*H0 + H0) of that line,
+// so every node belongs to exactly one lane.  Per field:
+//   1. each lane loads its whole r-line from HBM (both waves read the same
+//      line; the second read hits the cache) and applies D along r for its
+//      half -- D entries are uniform across the wave;
+//   2. the owners write their nodes to an LDS tile;
+//   3. wave 0 applies D along s (lane p owns the s-line (i, k)), wave 1
+//      along t (lane p owns the t-line (i, j)); results go to two LDS tiles;
+//   4. the owners read back f_s, f_t at their nodes.
+// Each line is read once and each derivative crosses LDS once, instead of
+// eight LDS reads per output.  LDS tiles use a padded row stride of P + 1.
+
+template <int N>
+struct Pen {
+  static constexpr int P = N + 1;
+  static constexpr int NP = P * P;        // lines per direction (<= 64)
+  static constexpr int H0 = (P + 1) / 2;  // nodes per lane and wave
+  static constexpr int RS = P + 1;        // LDS row stride (j)
+  static constexpr int SS = P * RS;       // LDS slab stride (k)
+  static constexpr int SZ = P * SS;       // padded tile
+  static_assert(NP <= 64, "pencil kernels need (N+1)^2 <= 64");
+  __device__ static constexpr int at(int i, int j, int k) { return i + RS * j + SS * k; }
+};
+
+// Line-shifted derivative of a P-point line: out[i] = sum_m D[i][m] (g_m - g_0).
+template <int P, typename T>
+__device__ __forceinline__ T line_deriv(const T* __restrict__ d, int i, const T (&g)[P]) {
+  T acc = T(0);
+#pragma unroll
+  for (int m = 1; m < P; ++m) acc = fma(d[i * P + m], g[m] - g[0], acc);
+  return acc;
+}
+
+// One field through the pencil scheme; owner gets (f_r, f_s, f_t) at its
+// H0 nodes.  `gf` points at the element's first value.
+template <int N, typename T>
+__device__ __forceinline__ void pencil_pass(const T* __restrict__ gf, const T* __restrict__ d,
+                                            T* __restrict__ F, T* __restrict__ S,
+                                            T* __restrict__ Tt, int h, int p,
+                                            T (&fr)[Pen<N>::H0], T (&fs)[Pen<N>::H0],
+                                            T (&ft)[Pen<N>::H0]) {
+  using Q = Pen<N>;
+  constexpr int P = Q::P, H0 = Q::H0;
+  const bool valid = p < Q::NP;
+  const int j = p % P, k = p / P;
+  T f[P];
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < P; ++m) f[m] = gf[(k * P + j) * P + m];
+#pragma unroll
+    for (int ii = 0; ii < H0; ++ii) {
+      const int i = h * H0 + ii;
+      if (i < P) {
+        fr[ii] = line_deriv<P>(d, i, f);
+        F[Q::at(i, j, k)] = f[i];
+      }
+    }
+  }
+  __syncthreads();
+  if (valid) {
+    const int a = p % P, b = p / P;
+    T g[P];
+    if (h == 0) {  // s-line at (i, k) = (a, b)
+#pragma unroll
+      for (int m = 0; m < P; ++m) g[m] = F[Q::at(a, m, b)];
+#pragma unroll
+      for (int jj = 0; jj < P; ++jj) S[Q::at(a, jj, b)] = line_deriv<P>(d, jj, g);
+    } else {       // t-line at (i, j) = (a, b)
+#pragma unroll
+      for (int m = 0; m < P; ++m) g[m] = F[Q::at(a, b, m)];
+#pragma unroll
+      for (int kk = 0; kk < P; ++kk) Tt[Q::at(a, b, kk)] = line_deriv<P>(d, kk, g);
+    }
+  }
+  __syncthreads();
+  if (valid) {
+#pragma unroll
+    for (int ii = 0; ii < H0; ++ii) {
+      const int i = h * H0 + ii;
+      if (i < P) {
+        fs[ii] = S[Q::at(i, j, k)];
+        ft[ii] = Tt[Q::at(i, j, k)];
+      }
+    }
+  }
+}
+
+template <int N, typename T>
+struct PencilTiles {
+  T F[Pen<N>::SZ];
+  T S[Pen<N>::SZ];
+  T Tt[Pen<N>::SZ];
+  T red[4];
+  int flag;
+};
+
+// Geometry of the owner's nodes: J^-1 from the three coordinate passes.
+// The coordinate tiles land in FX, FY, FZ (the same tile when they are not
+// needed afterwards).
+template <int N, typename T>
+__device__ __forceinline__ bool pencil_geometry(const T* gx, const T* gy, const T* gz,
+                                                const T* __restrict__ d,
+                                                PencilTiles<N, T>& sm, T* FX, T* FY, T* FZ,
+                                                int h, int p, InvJac<T> (&kk)[Pen<N>::H0]) {
+  constexpr int H0 = Pen<N>::H0;
+  T xr[H0], xs[H0], xt[H0], yr[H0], ys[H0], yt[H0], zr[H0], zs[H0], zt[H0];
+  pencil_pass<N>(gx, d, FX, sm.S, sm.Tt, h, p, xr, xs, xt);
+  pencil_pass<N>(gy, d, FY, sm.S, sm.Tt, h, p, yr, ys, yt);
+  pencil_pass<N>(gz, d, FZ, sm.S, sm.Tt, h, p, zr, zs, zt);
+  bool ok = true;
+#pragma unroll
+  for (int ii = 0; ii < H0; ++ii)
+    ok = invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii], zt[ii],
+                         kk[ii]) && ok;
+  return ok;
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+derivs_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+              const T* __restrict__ z, const T* __restrict__ f, T* __restrict__ gx,
+              T* __restrict__ gy, T* __restrict__ gz, int32_t* __restrict__ status) {
+  using Q = Pen<N>;
+  constexpr int P = Q::P, H0 = Q::H0;
+  __shared__ PencilTiles<N, T> sm;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int p = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * (P * P * P);
+  InvJac<T> kk[H0];
+  int bad = !pencil_geometry<N>(x + base, y + base, z + base, dmat, sm, sm.F, sm.F, sm.F, h, p,
+                                kk);
+  T fr[H0], fs[H0], ft[H0];
+  pencil_pass<N>(f + base, dmat, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  const bool valid = p < Q::NP;
+  if (!valid) bad = 0;
+  if (valid) {
+    const int j = p % P, k = p / P;
+#pragma unroll
+    for (int ii = 0; ii < H0; ++ii) {
+      const int i = h * H0 + ii;
+      if (i < P) {
+        const int64_t o = base + (k * P + j) * P + i;
+        gx[o] = fr[ii] * kk[ii].rx + fs[ii] * kk[ii].sx + ft[ii] * kk[ii].tx;
+        gy[o] = fr[ii] * kk[ii].ry + fs[ii] * kk[ii].sy + ft[ii] * kk[ii].ty;
+        gz[o] = fr[ii] * kk[ii].rz + fs[ii] * kk[ii].sz + ft[ii] * kk[ii].tz;
+      }
+    }
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+}
+
+// Q and |omega| at the owner's nodes; the velocity-gradient rows are folded
+// into Q = -(sum_ij A_ij A_ji)/2 and |omega|^2 as they are produced.
+template <int N, typename T>
+__device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* gz,
+                                             const T* gu, const T* gv, const T* gw,
+                                             const T* __restrict__ d, PencilTiles<N, T>& sm,
+                                             T* FX, T* FY, T* FZ, int h, int p,
+                                             T (&qv)[Pen<N>::H0], T (&om)[Pen<N>::H0]) {
+  constexpr int H0 = Pen<N>::H0;
+  InvJac<T> kk[H0];
+  const bool ok = pencil_geometry<N>(gx, gy, gz, d, sm, FX, FY, FZ, h, p, kk);
+  T fr[H0], fs[H0], ft[H0];
+  T a01[H0], a02[H0], a12[H0];
+  // row 0 (u)
+  pencil_pass<N>(gu, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < H0; ++ii) {
+    const InvJac<T>& K = kk[ii];
+    const T a00 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    a01[ii] = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    a02[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = a00 * a00;
+  }
+  // row 1 (v)
+  pencil_pass<N>(gv, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < H0; ++ii) {
+    const InvJac<T>& K = kk[ii];
+    const T a10 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    const T a11 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    a12[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = qv[ii] + a11 * a11 + T(2) * (a01[ii] * a10);
+    const T w3 = a10 - a01[ii];
+    om[ii] = w3 * w3;
+  }
+  // row 2 (w)
+  pencil_pass<N>(gw, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < H0; ++ii) {
+    const InvJac<T>& K = kk[ii];
+    const T a20 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    const T a21 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    const T a22 = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = T(-0.5) * (qv[ii] + a22 * a22 + T(2) * (a02[ii] * a20 + a12[ii] * a21));
+    const T w1 = a21 - a12[ii], w2 = a02[ii] - a20;
+    om[ii] = sqrt(om[ii] + w1 * w1 + w2 * w2);
+  }
+  return ok;
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+qcrit_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+             const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
+             const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
+             T* __restrict__ qmm, int32_t* __restrict__ status) {
+  using Q = Pen<N>;
+  constexpr int P = Q::P, H0 = Q::H0;
+  __shared__ PencilTiles<N, T> sm;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int p = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * (P * P * P);
+  T qv[H0], ov[H0];
+  int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
+                             sm, sm.F, sm.F, sm.F, h, p, qv, ov);
+  const bool valid = p < Q::NP;
+  T mn = pos_inf<T>(), mx = neg_inf<T>();
+  if (!valid) bad = 0;
+  if (valid) {
+    const int j = p % P, k = p / P;
+#pragma unroll
+    for (int ii = 0; ii < H0; ++ii) {
+      const int i = h * H0 + ii;
+      if (i < P) {
+        const int64_t o = base + (k * P + j) * P + i;
+        if (q) q[o] = qv[ii];
+        if (om) om[o] = ov[ii];
+        const T c = qv[ii] != qv[ii] ? neg_inf<T>() : qv[ii];
+        mn = c < mn ? c : mn;
+        mx = c > mx ? c : mx;
+      }
+    }
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  if (qmm) {
+    block_minmax<T, 128>(mn, mx, sm.red);
+    if (threadIdx.x == 0) {
+      qmm[2 * (int64_t)blockIdx.x] = mn;
+      qmm[2 * (int64_t)blockIdx.x + 1] = mx;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // marching cubes
 // ---------------------------------------------------------------------------
 
@@ -284,18 +535,87 @@ qcrit_tile(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restr
 __constant__ int8_t kEdgeLo[12] = {0, 2, 4, 6, 0, 1, 4, 5, 0, 1, 2, 3};
 __constant__ int8_t kEdgeAxis[12] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2};
 
+// Node offset of cube corner v in a tile with row stride RS and slab stride SS.
+template <int RS, int SS>
+__device__ __forceinline__ int corner_offset(int v) {
+  return (v & 1) + RS * ((v >> 1) & 1) + SS * ((v >> 2) & 1);
+}
 template <int P>
 __device__ __forceinline__ int corner_offset(int v) {
-  return (v & 1) + P * ((v >> 1) & 1) + P * P * ((v >> 2) & 1);
+  return corner_offset<P, P * P>(v);
 }
 
-template <int N, typename T>
-__device__ __forceinline__ int cell_case(const T* __restrict__ sf, int n0, T c) {
-  constexpr int P = N + 1;
+// Case index of the cell whose lowest node sits at tile offset n0.
+template <int RS, int SS, typename T>
+__device__ __forceinline__ int cell_case_strided(const T* __restrict__ sf, int n0, T c) {
   int cs = 0;
 #pragma unroll
-  for (int vtx = 0; vtx < 8; ++vtx) cs |= (sf[n0 + corner_offset<P>(vtx)] > c) << vtx;
+  for (int vtx = 0; vtx < 8; ++vtx) cs |= (sf[n0 + corner_offset<RS, SS>(vtx)] > c) << vtx;
   return cs;
+}
+template <int N, typename T>
+__device__ __forceinline__ int cell_case(const T* __restrict__ sf, int n0, T c) {
+  return cell_case_strided<N + 1, (N + 1) * (N + 1)>(sf, n0, c);
+}
+
+// Write the nt triangles of one cell (case cs, lowest node at tile offset n0
+// with tile strides RS, SS) at triangle index g of `out` (capacity cap).
+// Field and coordinates are read from tiles; `key_lo` is the element-global
+// index of the cell's lowest node in the unpadded layout (edge keys).
+template <int P, int RS, int SS, typename T>
+__device__ __forceinline__ void emit_cell(int cs, int nt, int n0, T c, const T* __restrict__ sf,
+                                          const T* __restrict__ sx, const T* __restrict__ sy,
+                                          const T* __restrict__ sz,
+                                          const int8_t* __restrict__ s_tri, T* __restrict__ out,
+                                          int64_t g, int64_t cap, uint64_t* __restrict__ keys,
+                                          int64_t key_lo) {
+  for (int slot = 0; slot < nt; ++slot, ++g) {
+    if (g >= cap) break;
+    T* o = out + g * 9;
+#pragma unroll
+    for (int vtx = 0; vtx < 3; ++vtx) {
+      const int edge = s_tri[(cs * kMcMaxTri + slot) * 3 + vtx];
+      const int corner = kEdgeLo[edge];
+      const int ax = kEdgeAxis[edge];
+      const int lo = n0 + corner_offset<RS, SS>(corner);
+      const int hi = lo + (ax == 0 ? 1 : ax == 1 ? RS : SS);
+      {
+#pragma clang fp contract(off)
+        const T f0 = sf[lo], f1 = sf[hi];
+        const T tt = (c - f0) / (f1 - f0);
+        o[3 * vtx + 0] = sx[lo] + tt * (sx[hi] - sx[lo]);
+        o[3 * vtx + 1] = sy[lo] + tt * (sy[hi] - sy[lo]);
+        o[3 * vtx + 2] = sz[lo] + tt * (sz[hi] - sz[lo]);
+      }
+      if (keys) {
+        const int64_t node = key_lo + corner_offset<P, P * P>(corner);
+        keys[g * 3 + vtx] = (uint64_t)node * 3u + (uint64_t)ax;
+      }
+    }
+  }
+}
+
+// Exclusive prefix over the cells of a block of the per-cell triangle counts
+// nt (0..7): one ballot per bit gives the wave prefix; wave totals go through
+// LDS.  Returns the thread's offset; *block_total receives the block total.
+template <int TH>
+__device__ __forceinline__ int block_count_prefix(int nt, int32_t* s_wave, int* block_total) {
+  constexpr int W = TH / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t m0 = __ballot(nt & 1), m1 = __ballot(nt & 2), m2 = __ballot(nt & 4);
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int pre = __popcll(m0 & lt) + 2 * __popcll(m1 & lt) + 4 * __popcll(m2 & lt);
+  if (lane == 0) s_wave[wv] = __popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2);
+  __syncthreads();
+  int tot = 0;
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    pre += q < wv ? s_wave[q] : 0;
+    tot += s_wave[q];
+  }
+  __syncthreads();
+  *block_total = tot;
+  return pre;
 }
 
 // Per (isovalue, element): triangle and active-cell counts; optional case dump.
@@ -371,15 +691,15 @@ __global__ void __launch_bounds__(Shape<N>::kCellThreads)
 iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
          const T* __restrict__ z, const T* __restrict__ field, int n_iso, IsoList<T> iso,
          const uint8_t* __restrict__ ntri_tab, const int8_t* __restrict__ tri_tab,
-         const int32_t* __restrict__ cnt, const int64_t* __restrict__ offs,
-         T* __restrict__ tri_xyz, int64_t cap, uint64_t* __restrict__ keys) {
+         const int32_t* __restrict__ cnt, const int64_t* __restrict__ offs, IsoOut<T> out,
+         uint64_t* __restrict__ keys) {
   using S = Shape<N>;
   constexpr int TH = S::kCellThreads;
-  constexpr int W = TH / 64;
+  constexpr int P = S::P;
   __shared__ T sf[S::NP], sx[S::NP], sy[S::NP], sz[S::NP];
   __shared__ uint8_t s_ntri[256];
   __shared__ int8_t s_tri[256 * kMcMaxTri * 3];
-  __shared__ int32_t s_wave[W];
+  __shared__ int32_t s_wave[TH / 64];
   const int t = threadIdx.x;
   const int64_t e = blockIdx.x;
   bool any = false;
@@ -396,8 +716,7 @@ iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
   }
   __syncthreads();
   const int i = t % N, j = (t / N) % N, k = t / (N * N);
-  const int n0 = i + S::P * (j + S::P * k);
-  const int lane = t & 63, wv = t >> 6;
+  const int n0 = i + P * (j + P * k);
   for (int s = 0; s < n_iso; ++s) {
     const int64_t flat = (int64_t)s * n_elem + e;
     if (cnt[flat] == 0) continue;
@@ -407,35 +726,18 @@ iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
       cs = cell_case<N>(sf, n0, c);
       nt = s_ntri[cs];
     }
-    // wave prefix of the 3-bit counts from one ballot per bit
-    const uint64_t m0 = __ballot(nt & 1), m1 = __ballot(nt & 2), m2 = __ballot(nt & 4);
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const int pre = __popcll(m0 & lt) + 2 * __popcll(m1 & lt) + 4 * __popcll(m2 & lt);
-    if (lane == 0) s_wave[wv] = __popcll(m0) + 2 * __popcll(m1) + 4 * __popcll(m2);
-    __syncthreads();
+    int tot;
+    const int pre = block_count_prefix<TH>(nt, s_wave, &tot);
     int64_t g = offs[flat] + pre;
-    for (int q = 0; q < wv; ++q) g += s_wave[q];
-    for (int slot = 0; slot < nt; ++slot, ++g) {
-      if (g >= cap) break;
-      T* out = tri_xyz + g * 9;
-#pragma unroll
-      for (int vtx = 0; vtx < 3; ++vtx) {
-        const int edge = s_tri[(cs * kMcMaxTri + slot) * 3 + vtx];
-        const int lo = n0 + corner_offset<S::P>(kEdgeLo[edge]);
-        const int ax = kEdgeAxis[edge];
-        const int hi = lo + (ax == 0 ? 1 : ax == 1 ? S::P : S::P * S::P);
-        {
-#pragma clang fp contract(off)
-          const T f0 = sf[lo], f1 = sf[hi];
-          const T tt = (c - f0) / (f1 - f0);
-          out[3 * vtx + 0] = sx[lo] + tt * (sx[hi] - sx[lo]);
-          out[3 * vtx + 1] = sy[lo] + tt * (sy[hi] - sy[lo]);
-          out[3 * vtx + 2] = sz[lo] + tt * (sz[hi] - sz[lo]);
-        }
-        if (keys) keys[g * 3 + vtx] = ((uint64_t)(base + lo)) * 3u + (uint64_t)ax;
-      }
+    T* dst = out.ptr[0];
+    int64_t cap = out.cap[0];
+    if (out.per_iso) {
+      g -= offs[(int64_t)s * n_elem];
+      dst = out.ptr[s];
+      cap = out.cap[s];
     }
-    __syncthreads();
+    emit_cell<P, P, P * P>(cs, nt, n0, c, sf, sx, sy, sz, s_tri, dst, g, cap,
+                           out.per_iso ? nullptr : keys, base + n0);
   }
 }
 
@@ -498,18 +800,208 @@ scan_apply(const int32_t* __restrict__ cnt, int64_t count, const int64_t* __rest
   if (blockIdx.x == nb - 1 && threadIdx.x == 0) offs[count] = partial[nb];
 }
 
+template <typename T>
 __global__ void iso_totals(const int64_t* __restrict__ offs, int64_t n_elem, int n_iso,
-                           int64_t* __restrict__ tri_count, int64_t cap,
+                           int64_t* __restrict__ tri_count, IsoOut<T> out,
                            int32_t* __restrict__ status) {
   const int s = threadIdx.x;
-  if (s < n_iso) tri_count[s] = offs[(int64_t)(s + 1) * n_elem] - offs[(int64_t)s * n_elem];
-  if (s == 0 && status && offs[(int64_t)n_iso * n_elem] > cap)
+  if (s < n_iso) {
+    const int64_t c = offs[(int64_t)(s + 1) * n_elem] - offs[(int64_t)s * n_elem];
+    tri_count[s] = c;
+    if (status && out.per_iso && c > out.cap[s]) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
+  }
+  if (s == 0 && status && !out.per_iso && offs[(int64_t)n_iso * n_elem] > out.cap[0])
     atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
 }
 
 __global__ void fill_i64(int64_t* __restrict__ p, int n, int64_t value) {
   const int s = threadIdx.x;
   if (s < n) p[s] = value;
+}
+
+// ---------------------------------------------------------------------------
+// fused single-pass extraction (N <= 7): Q, |omega|, isosurfaces of Q
+// ---------------------------------------------------------------------------
+//
+// One workgroup (two waves) per element, in the order of a ticket taken at
+// start.  After the pencil Q computation the element's Q tile and coordinate
+// tiles are in LDS; each isovalue's triangle count is published with a
+// decoupled look-back word (Merrill & Garland 2016): flag AGGREGATE with
+// the element's own count, then INCLUSIVE with the prefix through it once
+// the predecessors' words are known.  Tickets make every predecessor a
+// workgroup that has already started, so every wait ends.  The element then
+// emits its triangles at that prefix, in (cell, slot) order.
+
+constexpr uint64_t kLbAggregate = 1ull << 62;
+constexpr uint64_t kLbInclusive = 2ull << 62;
+constexpr uint64_t kLbValue = (1ull << 62) - 1;
+
+__global__ void extract_reset(uint64_t* __restrict__ lookback, int64_t words,
+                              uint32_t* __restrict__ ticket, int64_t* __restrict__ active,
+                              int n_iso) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) lookback[i] = 0;
+  if (i == 0) *ticket = 0u;
+  if (active && i < n_iso) active[i] = 0;
+}
+
+template <int N, typename T>
+struct ExtractLds {
+  T X[Pen<N>::SZ];
+  T Y[Pen<N>::SZ];
+  T Z[Pen<N>::SZ];
+  PencilTiles<N, T> pt;
+  int64_t prefix[SEM_MAX_ISO];
+  int32_t cnt[SEM_MAX_ISO];
+  int32_t wave[4];
+  uint8_t ntri[256];
+  int8_t tri[256 * kMcMaxTri * 3];
+  uint32_t e;
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__ x,
+               const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
+               const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q,
+               T* __restrict__ om, T* __restrict__ qmm, int n_iso, IsoList<T> iso,
+               IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
+               const int8_t* __restrict__ tri_tab, uint64_t* __restrict__ lookback,
+               uint32_t* __restrict__ ticket, int64_t* __restrict__ tri_count,
+               int64_t* __restrict__ active, int32_t* __restrict__ status) {
+  using Q = Pen<N>;
+  constexpr int P = Q::P, H0 = Q::H0, RS = Q::RS, SS = Q::SS;
+  constexpr int NC = N * N * N;
+  constexpr int ROUNDS = (NC + 127) / 128;
+  __shared__ ExtractLds<N, T> sm;
+  const int t = threadIdx.x;
+  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int p = t & 63;
+  if (t == 0) sm.e = atomicAdd(ticket, 1u);
+  for (int k = t; k < 256; k += 128) sm.ntri[k] = ntri_tab[k];
+  for (int k = t; k < 256 * kMcMaxTri * 3; k += 128) sm.tri[k] = tri_tab[k];
+  __syncthreads();
+  const int64_t e = sm.e;
+  const int64_t base = e * (P * P * P);
+
+  // Q and |omega| (the coordinate tiles stay in LDS for the vertices)
+  T qv[H0], ov[H0];
+  int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
+                             sm.pt, sm.X, sm.Y, sm.Z, h, p, qv, ov);
+  T* QT = sm.pt.F;  // free after the last pass: holds the Q tile from here on
+  T mn = pos_inf<T>(), mx = neg_inf<T>();
+  if (p < Q::NP) {
+    const int j = p % P, k = p / P;
+#pragma unroll
+    for (int ii = 0; ii < H0; ++ii) {
+      const int i = h * H0 + ii;
+      if (i < P) {
+        const int64_t o = base + (k * P + j) * P + i;
+        if (q) q[o] = qv[ii];
+        if (om) om[o] = ov[ii];
+        QT[Q::at(i, j, k)] = qv[ii];
+        const T c = qv[ii] != qv[ii] ? neg_inf<T>() : qv[ii];
+        mn = c < mn ? c : mn;
+        mx = c > mx ? c : mx;
+      }
+    }
+  } else {
+    bad = 0;
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  block_minmax<T, 128>(mn, mx, sm.pt.red);
+  if (qmm && t == 0) {
+    qmm[2 * e] = mn;
+    qmm[2 * e + 1] = mx;
+  }
+
+  // triangles and active cells of this element, per isovalue
+  for (int s = 0; s < n_iso; ++s) {
+    const T c = iso.v[s];
+    int nt = 0, act = 0;
+    if ((mx > c) && !(mn > c)) {
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        const int cell = r * 128 + t;
+        if (cell < NC) {
+          const int ci = cell % N, cj = (cell / N) % N, ck = cell / (N * N);
+          const int cs = cell_case_strided<RS, SS>(QT, Q::at(ci, cj, ck), c);
+          nt += sm.ntri[cs];
+          act += (cs != 0 && cs != 255);
+        }
+      }
+    }
+    nt = wave_sum(nt);
+    act = wave_sum(act);
+    if (p == 0) {
+      sm.wave[h] = nt;
+      sm.wave[2 + h] = act;
+    }
+    __syncthreads();
+    if (t == 0) {
+      sm.cnt[s] = sm.wave[0] + sm.wave[1];
+      const int a = sm.wave[2] + sm.wave[3];
+      if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
+    }
+    __syncthreads();
+  }
+
+  // decoupled look-back, one lane per isovalue
+  if (t < n_iso) {
+    const int s = t;
+    const uint64_t c = (uint64_t)sm.cnt[s];
+    uint64_t* row = lookback + (int64_t)s * n_elem;
+    uint64_t prefix = 0;
+    if (e == 0) {
+      __hip_atomic_store(&row[0], kLbInclusive | c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&row[e], kLbAggregate | c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      int64_t j = e - 1;
+      while (true) {
+        const uint64_t wd = __hip_atomic_load(&row[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t flag = wd >> 62;
+        if (flag == 0) {
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        prefix += wd & kLbValue;
+        if (flag == 2) break;
+        --j;
+      }
+      __hip_atomic_store(&row[e], kLbInclusive | (prefix + c), __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    sm.prefix[s] = (int64_t)prefix;
+    if (e == n_elem - 1) {
+      tri_count[s] = (int64_t)(prefix + c);
+      if (status && (int64_t)(prefix + c) > out.cap[s]) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
+    }
+  }
+  __syncthreads();
+
+  // emission in (cell, slot) order at the element's offset
+  for (int s = 0; s < n_iso; ++s) {
+    if (sm.cnt[s] == 0) continue;
+    const T c = iso.v[s];
+    int64_t g0 = sm.prefix[s];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const int cell = r * 128 + t;
+      int cs = 0, nt = 0, n0 = 0;
+      if (cell < NC) {
+        const int ci = cell % N, cj = (cell / N) % N, ck = cell / (N * N);
+        n0 = Q::at(ci, cj, ck);
+        cs = cell_case_strided<RS, SS>(QT, n0, c);
+        nt = sm.ntri[cs];
+      }
+      int tot;
+      const int pre = block_count_prefix<128>(nt, sm.wave, &tot);
+      emit_cell<P, RS, SS>(cs, nt, n0, c, QT, sm.X, sm.Y, sm.Z, sm.tri, out.ptr[s], g0 + pre,
+                           out.cap[s], (uint64_t*)nullptr, 0);
+      g0 += tot;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -543,9 +1035,15 @@ hipError_t derivs_t(int order, const DeviceTables& tab, int64_t n_elem, const vo
                     int32_t* status, hipStream_t s) {
   const T* d = dmat_of<T>(tab, order);
   SEM_ORDER_SWITCH(order, {
-    hipLaunchKernelGGL((derivs_tile<N, T>), dim3((unsigned)n_elem),
-                       dim3(Shape<N>::kNodeThreads), 0, s, d, (const T*)x, (const T*)y,
-                       (const T*)z, (const T*)f, (T*)gx, (T*)gy, (T*)gz, status);
+    if constexpr (N <= 7) {
+      hipLaunchKernelGGL((derivs_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s, d,
+                         (const T*)x, (const T*)y, (const T*)z, (const T*)f, (T*)gx, (T*)gy,
+                         (T*)gz, status);
+    } else {
+      hipLaunchKernelGGL((derivs_tile<N, T>), dim3((unsigned)n_elem),
+                         dim3(Shape<N>::kNodeThreads), 0, s, d, (const T*)x, (const T*)y,
+                         (const T*)z, (const T*)f, (T*)gx, (T*)gy, (T*)gz, status);
+    }
   });
   return hipGetLastError();
 }
@@ -556,22 +1054,36 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
                    void* q, void* om, void* qmm, int32_t* status, hipStream_t s) {
   const T* d = dmat_of<T>(tab, order);
   SEM_ORDER_SWITCH(order, {
-    hipLaunchKernelGGL((qcrit_tile<N, T>), dim3((unsigned)n_elem),
-                       dim3(Shape<N>::kNodeThreads), 0, s, d, (const T*)x, (const T*)y,
-                       (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om,
-                       (T*)qmm, status);
+    if constexpr (N <= 7) {
+      hipLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s, d,
+                         (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
+                         (const T*)w, (T*)q, (T*)om, (T*)qmm, status);
+    } else {
+      hipLaunchKernelGGL((qcrit_tile<N, T>), dim3((unsigned)n_elem),
+                         dim3(Shape<N>::kNodeThreads), 0, s, d, (const T*)x, (const T*)y,
+                         (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om,
+                         (T*)qmm, status);
+    }
   });
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t iso_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
-                 const void* y, const void* z, const void* field, const void* mm, int n_iso,
-                 const double* iso_host, void* tri_xyz, int64_t cap, uint64_t* keys,
-                 int64_t* tri_count, int64_t* active, uint8_t* case_idx,
-                 const IsoWorkspace& ws, int32_t* status, hipStream_t s) {
+IsoList<T> make_isolist(int n_iso, const double* iso_host) {
   IsoList<T> iso;
   for (int q = 0; q < SEM_MAX_ISO; ++q) iso.v[q] = q < n_iso ? (T)iso_host[q] : T(0);
+  return iso;
+}
+
+// Two-pass isosurface: count, exclusive scan, emit (any supported order).
+template <typename T>
+hipError_t iso_pipeline(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
+                        const void* y, const void* z, const void* field, const void* mm,
+                        int n_iso, const double* iso_host, const IsoOut<T>& out,
+                        uint64_t* keys, int64_t* tri_count, int64_t* active,
+                        uint8_t* case_idx, const IsoWorkspace& ws, int32_t* status,
+                        hipStream_t s) {
+  const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
   if (active) hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
   const int64_t count = (int64_t)n_iso * n_elem;
   const int64_t nb = scan_blocks(count);
@@ -585,17 +1097,74 @@ hipError_t iso_t(int order, const DeviceTables& tab, int64_t n_elem, const void*
   hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, ws.partial, nb);
   hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.cnt, count,
                      ws.partial, nb, ws.offs);
-  hipLaunchKernelGGL(iso_totals, dim3(1), dim3(SEM_MAX_ISO), 0, s, ws.offs, n_elem, n_iso,
-                     tri_count, cap, status);
-  if (cap > 0) {
+  hipLaunchKernelGGL((iso_totals<T>), dim3(1), dim3(SEM_MAX_ISO), 0, s, ws.offs, n_elem, n_iso,
+                     tri_count, out, status);
+  bool any_cap = false;
+  for (int q = 0; q < (out.per_iso ? n_iso : 1); ++q) any_cap = any_cap || out.cap[q] > 0;
+  if (any_cap) {
     SEM_ORDER_SWITCH(order, {
       hipLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem),
                          dim3(Shape<N>::kCellThreads), 0, s, n_elem, (const T*)x,
                          (const T*)y, (const T*)z, (const T*)field, n_iso, iso, tab.ntri,
-                         tab.tri, ws.cnt, ws.offs, (T*)tri_xyz, cap, keys);
+                         tab.tri, ws.cnt, ws.offs, out, keys);
     });
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t iso_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
+                 const void* y, const void* z, const void* field, const void* mm, int n_iso,
+                 const double* iso_host, void* tri_xyz, int64_t cap, uint64_t* keys,
+                 int64_t* tri_count, int64_t* active, uint8_t* case_idx,
+                 const IsoWorkspace& ws, int32_t* status, hipStream_t s) {
+  IsoOut<T> out{};
+  out.ptr[0] = static_cast<T*>(tri_xyz);
+  out.cap[0] = cap;
+  out.per_iso = 0;
+  return iso_pipeline<T>(order, tab, n_elem, x, y, z, field, mm, n_iso, iso_host, out, keys,
+                         tri_count, active, case_idx, ws, status, s);
+}
+
+template <typename T>
+hipError_t extract_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
+                     const void* y, const void* z, const void* u, const void* v,
+                     const void* w, void* q, void* om, void* qmm, int n_iso,
+                     const double* iso_host, void* const* tri_xyz, const int64_t* cap,
+                     int64_t* tri_count, int64_t* active, void* workspace, int32_t* status,
+                     hipStream_t s) {
+  IsoOut<T> out{};
+  for (int k = 0; k < n_iso; ++k) {
+    out.ptr[k] = static_cast<T*>(tri_xyz[k]);
+    out.cap[k] = cap[k];
+  }
+  out.per_iso = 1;
+  const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
+  const T* d = dmat_of<T>(tab, order);
+  if (order <= 7) {
+    const ExtractWorkspace ws = extract_workspace_layout(workspace, n_elem, n_iso);
+    const int64_t words = (int64_t)n_iso * n_elem;
+    hipLaunchKernelGGL(extract_reset, dim3((unsigned)((words + 255) / 256 + 1)), dim3(256), 0,
+                       s, ws.lookback, words, ws.ticket, active, n_iso);
+    SEM_ORDER_SWITCH(order, {
+      if constexpr (N <= 7) {
+        hipLaunchKernelGGL((extract_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
+                           n_elem, d, (const T*)x, (const T*)y, (const T*)z, (const T*)u,
+                           (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso, iso, out,
+                           tab.ntri, tab.tri, ws.lookback, ws.ticket, tri_count, active,
+                           status);
+      }
+    });
+    return hipGetLastError();
+  }
+  // higher orders: Q by the tile kernel, then the two-pass isosurface
+  const IsoWorkspace ws = iso_workspace_layout(workspace, n_elem, n_iso);
+  T* qq = static_cast<T*>(q);
+  T* mmq = static_cast<T*>(qmm);
+  hipError_t err = qcrit_t<T>(order, tab, n_elem, x, y, z, u, v, w, qq, om, mmq, status, s);
+  if (err != hipSuccess) return err;
+  return iso_pipeline<T>(order, tab, n_elem, x, y, z, qq, mmq, n_iso, iso_host, out, nullptr,
+                         tri_count, active, nullptr, ws, status, s);
 }
 
 }  // namespace
@@ -616,6 +1185,22 @@ hipError_t launch_qcrit(int order, sem_dtype dt, const DeviceTables& tab, int64_
   return dt == SEM_F64
              ? qcrit_t<double>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, status, s)
              : qcrit_t<float>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, status, s);
+}
+
+hipError_t launch_extract(int order, sem_dtype dt, const DeviceTables& tab, int64_t n_elem,
+                          const void* x, const void* y, const void* z, const void* u,
+                          const void* v, const void* w, void* q, void* om, void* qmm,
+                          int n_iso, const double* iso_host, void* const* tri_xyz,
+                          const int64_t* tri_capacity, int64_t* tri_count,
+                          int64_t* active_cells, void* workspace, int32_t* status,
+                          hipStream_t s) {
+  return dt == SEM_F64
+             ? extract_t<double>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
+                                 iso_host, tri_xyz, tri_capacity, tri_count, active_cells,
+                                 workspace, status, s)
+             : extract_t<float>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
+                                iso_host, tri_xyz, tri_capacity, tri_count, active_cells,
+                                workspace, status, s);
 }
 
 hipError_t launch_isosurface(int order, sem_dtype dt, const DeviceTables& tab, int64_t n_elem,

@@ -1,0 +1,177 @@
+"""GPU parity of the fused single-pass sem_extract.
+
+Its triangles per isovalue must equal, bit for bit, isovalue s of
+sem_isosurface applied to sem_qcrit's Q (same kernels' arithmetic), and
+match the CPU oracle to the same bars as the separate calls.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gll, mc
+from oracle import sem as osem
+
+torch = pytest.importorskip("torch")
+import paper_2312_09888_amd as sem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TOL = {np.float64: 1e-10, np.float32: 1e-5}
+
+
+def dev(a, dt=np.float64):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=dt))).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _inputs(n, shape, seed):
+    x, y, z = W.box_mesh(shape, n, ((0.0, 1.7), (-0.4, 0.9), (0.2, 1.4)))
+    x, y, z = W.warp(x, y, z, amp=0.06)
+    rng = np.random.default_rng(seed)
+    vel = []
+    for _ in range(3):
+        k = rng.uniform(0.5, 3.0, size=(3, 3))
+        ph = rng.uniform(0, 6.28, size=3)
+        vel.append(sum(np.sin(k[m, 0] * x + k[m, 1] * y + k[m, 2] * z + ph[m])
+                       for m in range(3)))
+    return (x, y, z) + tuple(vel)
+
+
+def _check_against_oracle(arrs, isos, dt, n):
+    t = [dev(a, dt) for a in arrs]
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    r = sem.extract(*t, isos, status=st)
+    assert int(st.item()) == 0
+    a64 = [a.astype(np.float64) for a in arrs]
+    oq, oom, _ = osem.qcrit(*a64, gll.diff_matrix(n))
+    hq = host(r["q"])
+    assert np.abs(hq - oq).max() / np.abs(oq).max() < TOL[dt]
+    assert np.abs(host(r["omega_mag"]) - oom).max() / np.abs(oom).max() < TOL[dt]
+    np.testing.assert_array_equal(host(r["minmax"]), osem.elem_minmax(hq))
+    # stage-isolated isosurface of the kernel's own Q
+    o = mc.extract(*[a.astype(dt) for a in arrs[:3]], hq.astype(dt), isos)
+    np.testing.assert_array_equal(host(r["tri_count"]), o["tri_count"])
+    np.testing.assert_array_equal(host(r["active"]), o["active"])
+    scale = max(np.abs(a).max() for a in a64[:3])
+    off = 0
+    for s in range(len(isos)):
+        cnt = int(o["tri_count"][s])
+        want = o["tri_xyz"][off:off + cnt]
+        off += cnt
+        got = host(r["tri"][s]).astype(np.float64)
+        assert got.shape == want.shape
+        if cnt:
+            assert np.abs(got - want).max() <= TOL[dt] * scale
+    return r, t
+
+
+@pytest.mark.parametrize("n", list(range(1, 10)))
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_extract_matches_oracle(n, dt):
+    for shape, seed in (((1, 1, 1), 1), ((7, 1, 1), 2), ((3, 3, 3), 3)):
+        arrs = [a.astype(dt) for a in _inputs(n, shape, seed)]
+        _check_against_oracle(arrs, [-0.9, 0.0, 0.7], dt, n)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_extract_equals_qcrit_then_isosurface(dt):
+    n = 7
+    arrs = [a.astype(dt) for a in W.tgv_config(n)]
+    t = [dev(a, dt) for a in arrs]
+    isos = [0.1, -0.3, 0.45]
+    r = sem.extract(*t, isos)
+    q, om, mm = sem.qcrit(*t)
+    assert torch.equal(r["q"], q) and torch.equal(r["omega_mag"], om)
+    assert torch.equal(r["minmax"], mm)
+    iso = sem.isosurface(t[0], t[1], t[2], q, isos, minmax=mm)
+    assert torch.equal(r["tri_count"], iso["tri_count"])
+    assert torch.equal(r["active"], iso["active"])
+    off = 0
+    for s in range(len(isos)):
+        c = int(iso["tri_count"][s])
+        assert torch.equal(r["tri"][s], iso["tri_xyz"][off:off + c])
+        off += c
+
+
+def test_extract_overflow_per_isovalue_and_count_only():
+    n = 7
+    t = [dev(a) for a in W.tgv_config(n)]
+    isos = [0.1, 0.3]
+    full = sem.extract(*t, isos)
+    c0, c1 = (int(v) for v in full["tri_count"].tolist())
+    ws = torch.empty(sem.extract_workspace_bytes(512, n, 2), dtype=torch.uint8, device=DEV)
+    b0 = torch.zeros((c0, 3, 3), dtype=torch.float64, device=DEV)
+    b1 = torch.zeros((c1 // 2, 3, 3), dtype=torch.float64, device=DEV)
+    cnt = torch.zeros(2, dtype=torch.int64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    sem.extract_into(*t, isos, [b0, b1], cnt, ws, status=st)
+    assert cnt.tolist() == [c0, c1]
+    assert int(st.item()) & sem.SEM_FLAG_TRI_OVERFLOW
+    assert torch.equal(b0, full["tri"][0])
+    assert torch.equal(b1, full["tri"][1][:c1 // 2])
+    # count only, no buffers: exact counts, and no Q outputs are required
+    cnt.zero_()
+    sem.extract_into(*t, isos, [None, None], cnt, ws)
+    assert cnt.tolist() == [c0, c1]
+
+
+def test_extract_deterministic_and_repeatable():
+    n = 7
+    t = [dev(a) for a in _inputs(n, (6, 5, 4), 8)]
+    r1 = sem.extract(*t, [0.0, 0.5, -0.5, 1.0])
+    r2 = sem.extract(*t, [0.0, 0.5, -0.5, 1.0])
+    for a, b in zip(r1["tri"], r2["tri"]):
+        assert torch.equal(a, b)
+    assert torch.equal(r1["q"], r2["q"])
+
+
+def test_extract_empty():
+    e = torch.empty((0, 8, 8, 8), dtype=torch.float64, device=DEV)
+    cnt = torch.full((2,), 5, dtype=torch.int64, device=DEV)
+    sem.extract_into(e, e, e, e, e, e, [0.1, 0.2], [None, None], cnt, None)
+    assert cnt.tolist() == [0, 0]
+
+
+def test_extract_channel_full_size_fp64():
+    n = 7
+    with open(os.path.join(ROOT, "tests", "golden", "channel_isovalues.json")) as fh:
+        isos = json.load(fh)["isovalues"]
+    fields = [f.contiguous() for f in W.channel_config(n, device=DEV)]
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    r = sem.extract(*fields, isos, status=st)
+    assert int(st.item()) == 0
+    e_tot = fields[0].shape[0]
+    qh = host(r["q"])
+    ntri_tab, _ = mc.case_table()
+    per = []
+    for s, c in enumerate(isos):
+        cases = mc.classify(qh, c).reshape(e_tot, -1)
+        cnt = ntri_tab[cases].astype(np.int64).sum(axis=1)
+        assert int(r["tri_count"][s]) == int(cnt.sum())
+        assert int(r["active"][s]) == int(np.count_nonzero((cases != 0) & (cases != 255)))
+        per.append(cnt)
+    offs = [np.cumsum(c) - c for c in per]
+    rng = np.random.default_rng(4)
+    els = np.unique(np.concatenate([[0, e_tot - 1], rng.choice(e_tot, 40, replace=False)]))
+    idx = torch.from_numpy(els).to(DEV)
+    arrs = [f.index_select(0, idx).cpu().numpy() for f in fields]
+    oq, _, _ = osem.qcrit(*arrs, gll.diff_matrix(n))
+    gq = qh[els]
+    assert np.abs(gq - oq).max() / np.abs(oq).max() < 1e-10
+    for s, c in enumerate(isos):
+        for k, e in enumerate(els):
+            nt = int(per[s][e])
+            if not nt:
+                continue
+            o = mc.extract(*(a[k:k + 1] for a in arrs[:3]), gq[k:k + 1], [c])
+            got = host(r["tri"][s][int(offs[s][e]):int(offs[s][e]) + nt])
+            assert np.abs(got - o["tri_xyz"]).max() <= 1e-10 * 4 * np.pi

@@ -147,3 +147,46 @@ def _no_gpu():
 def test_compute_without_device_reports_not_initialised():
     assert _qcrit() == _lib.SEM_ERR_NOT_INIT
     assert sem.lib().sem_init(0) in (_lib.SEM_ERR_HIP, _lib.SEM_ERR_ARG)
+
+
+def _extract(**kw):
+    iso = np.array([0.1, 0.2])
+    ptrs = (ctypes.c_void_p * 2)(0x1000, 0x1000)
+    caps = np.array([10, 10], dtype=np.int64)
+    a = dict(n=4, order=7, dt=0, u=FAKE, n_iso=2, iso=iso.ctypes.data,
+             ptrs=ctypes.cast(ptrs, ctypes.c_void_p), caps=caps.ctypes.data, count=FAKE,
+             ws=FAKE, ws_bytes=1 << 30)
+    a.update(kw)
+    return sem.lib().sem_extract(a["n"], a["order"], a["dt"], FAKE, FAKE, FAKE, a["u"], FAKE,
+                                 FAKE, None, None, None, a["n_iso"], a["iso"], a["ptrs"],
+                                 a["caps"], a["count"], None, a["ws"], a["ws_bytes"], None,
+                                 None)
+
+
+def test_extract_argument_errors():
+    assert _extract(order=0) == _lib.SEM_ERR_ORDER
+    assert _extract(dt=9) == _lib.SEM_ERR_DTYPE
+    assert _extract(n=-3) == _lib.SEM_ERR_ARG
+    assert _extract(u=None) == _lib.SEM_ERR_ARG
+    assert _extract(n_iso=0) == _lib.SEM_ERR_ARG
+    assert _extract(iso=None) == _lib.SEM_ERR_ARG
+    assert _extract(ptrs=None) == _lib.SEM_ERR_ARG
+    assert _extract(caps=None) == _lib.SEM_ERR_ARG
+    assert _extract(count=None) == _lib.SEM_ERR_ARG
+    bad_caps = np.array([10, -1], dtype=np.int64)
+    assert _extract(caps=bad_caps.ctypes.data) == _lib.SEM_ERR_ARG
+    nullp = (ctypes.c_void_p * 2)(0x1000, None)
+    assert _extract(ptrs=ctypes.cast(nullp, ctypes.c_void_p)) == _lib.SEM_ERR_ARG
+    assert _extract(ws=None) == _lib.SEM_ERR_WORKSPACE
+    need = sem.extract_workspace_bytes(4, 7, 2)
+    assert _extract(ws_bytes=need - 1) == _lib.SEM_ERR_WORKSPACE
+
+
+def test_extract_workspace_sizes():
+    a = sem.extract_workspace_bytes(1000, 7, 3)
+    assert a >= 1000 * 3 * 8
+    # higher orders also hold Q and its element ranges
+    b = sem.extract_workspace_bytes(1000, 9, 3, _lib.SEM_F64)
+    assert b >= 1000 * 1000 * 8
+    assert sem.extract_workspace_bytes(1000, 9, 3, _lib.SEM_F32) < b
+    assert sem.extract_workspace_bytes(10, 0, 1) == 0
