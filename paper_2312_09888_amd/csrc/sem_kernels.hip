@@ -316,8 +316,21 @@ __device__ __forceinline__ T line_deriv(const T* __restrict__ d, int i, const T 
 
 // One field through the pencil scheme; owner gets (f_r, f_s, f_t) at its
 // H0 nodes.  `gf` points at the element's first value.
+// Load the owner's r-line of one field (issued early so that several
+// fields' loads are in flight at once).
 template <int N, typename T>
-__device__ __forceinline__ void pencil_pass(const T* __restrict__ gf, const T* __restrict__ d,
+__device__ __forceinline__ void pencil_load(const T* __restrict__ gf, int p, T (&f)[N + 1]) {
+  using Q = Pen<N>;
+  constexpr int P = Q::P;
+  if (p < Q::NP) {
+    const int j = p % P, k = p / P;
+#pragma unroll
+    for (int m = 0; m < P; ++m) f[m] = gf[(k * P + j) * P + m];
+  }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void pencil_pass(const T (&f)[N + 1], const T* __restrict__ d,
                                             T* __restrict__ F, T* __restrict__ S,
                                             T* __restrict__ Tt, int h, int p,
                                             T (&fr)[Pen<N>::H0], T (&fs)[Pen<N>::H0],
@@ -326,10 +339,7 @@ __device__ __forceinline__ void pencil_pass(const T* __restrict__ gf, const T* _
   constexpr int P = Q::P, H0 = Q::H0;
   const bool valid = p < Q::NP;
   const int j = p % P, k = p / P;
-  T f[P];
   if (valid) {
-#pragma unroll
-    for (int m = 0; m < P; ++m) f[m] = gf[(k * P + j) * P + m];
 #pragma unroll
     for (int ii = 0; ii < H0; ++ii) {
       const int i = h * H0 + ii;
@@ -381,20 +391,22 @@ struct PencilTiles {
 // The coordinate tiles land in FX, FY, FZ (the same tile when they are not
 // needed afterwards).
 template <int N, typename T>
-__device__ __forceinline__ bool pencil_geometry(const T* gx, const T* gy, const T* gz,
-                                                const T* __restrict__ d,
+__device__ __forceinline__ bool pencil_geometry(const T (&lx)[N + 1], const T (&ly)[N + 1],
+                                                const T (&lz)[N + 1], const T* __restrict__ d,
                                                 PencilTiles<N, T>& sm, T* FX, T* FY, T* FZ,
                                                 int h, int p, InvJac<T> (&kk)[Pen<N>::H0]) {
-  constexpr int H0 = Pen<N>::H0;
+  constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
   T xr[H0], xs[H0], xt[H0], yr[H0], ys[H0], yt[H0], zr[H0], zs[H0], zt[H0];
-  pencil_pass<N>(gx, d, FX, sm.S, sm.Tt, h, p, xr, xs, xt);
-  pencil_pass<N>(gy, d, FY, sm.S, sm.Tt, h, p, yr, ys, yt);
-  pencil_pass<N>(gz, d, FZ, sm.S, sm.Tt, h, p, zr, zs, zt);
+  pencil_pass<N>(lx, d, FX, sm.S, sm.Tt, h, p, xr, xs, xt);
+  pencil_pass<N>(ly, d, FY, sm.S, sm.Tt, h, p, yr, ys, yt);
+  pencil_pass<N>(lz, d, FZ, sm.S, sm.Tt, h, p, zr, zs, zt);
   bool ok = true;
 #pragma unroll
-  for (int ii = 0; ii < H0; ++ii)
-    ok = invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii], zt[ii],
-                         kk[ii]) && ok;
+  for (int ii = 0; ii < H0; ++ii) {
+    const bool good = invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii],
+                                      zs[ii], zt[ii], kk[ii]);
+    if (h * H0 + ii < P) ok = ok && good;   // odd P: wave 1 owns one node fewer
+  }
   return ok;
 }
 
@@ -409,11 +421,15 @@ derivs_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __re
   const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int p = threadIdx.x & 63;
   const int64_t base = (int64_t)blockIdx.x * (P * P * P);
+  T lx[P], ly[P], lz[P], lf[P];
+  pencil_load<N>(x + base, p, lx);
+  pencil_load<N>(y + base, p, ly);
+  pencil_load<N>(z + base, p, lz);
+  pencil_load<N>(f + base, p, lf);
   InvJac<T> kk[H0];
-  int bad = !pencil_geometry<N>(x + base, y + base, z + base, dmat, sm, sm.F, sm.F, sm.F, h, p,
-                                kk);
+  int bad = !pencil_geometry<N>(lx, ly, lz, dmat, sm, sm.F, sm.F, sm.F, h, p, kk);
   T fr[H0], fs[H0], ft[H0];
-  pencil_pass<N>(f + base, dmat, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  pencil_pass<N>(lf, dmat, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
   const bool valid = p < Q::NP;
   if (!valid) bad = 0;
   if (valid) {
@@ -441,13 +457,21 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
                                              const T* __restrict__ d, PencilTiles<N, T>& sm,
                                              T* FX, T* FY, T* FZ, int h, int p,
                                              T (&qv)[Pen<N>::H0], T (&om)[Pen<N>::H0]) {
-  constexpr int H0 = Pen<N>::H0;
+  constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
+  // all six lines are requested before any arithmetic
+  T lx[P], ly[P], lz[P], lu[P], lv[P], lw[P];
+  pencil_load<N>(gx, p, lx);
+  pencil_load<N>(gy, p, ly);
+  pencil_load<N>(gz, p, lz);
+  pencil_load<N>(gu, p, lu);
+  pencil_load<N>(gv, p, lv);
+  pencil_load<N>(gw, p, lw);
   InvJac<T> kk[H0];
-  const bool ok = pencil_geometry<N>(gx, gy, gz, d, sm, FX, FY, FZ, h, p, kk);
+  const bool ok = pencil_geometry<N>(lx, ly, lz, d, sm, FX, FY, FZ, h, p, kk);
   T fr[H0], fs[H0], ft[H0];
   T a01[H0], a02[H0], a12[H0];
   // row 0 (u)
-  pencil_pass<N>(gu, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  pencil_pass<N>(lu, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
     const InvJac<T>& K = kk[ii];
@@ -457,7 +481,7 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
     qv[ii] = a00 * a00;
   }
   // row 1 (v)
-  pencil_pass<N>(gv, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  pencil_pass<N>(lv, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
     const InvJac<T>& K = kk[ii];
@@ -469,7 +493,7 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
     om[ii] = w3 * w3;
   }
   // row 2 (w)
-  pencil_pass<N>(gw, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  pencil_pass<N>(lw, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
     const InvJac<T>& K = kk[ii];
@@ -947,35 +971,52 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
     __syncthreads();
   }
 
-  // decoupled look-back, one lane per isovalue
-  if (t < n_iso) {
-    const int s = t;
-    const uint64_t c = (uint64_t)sm.cnt[s];
-    uint64_t* row = lookback + (int64_t)s * n_elem;
-    uint64_t prefix = 0;
-    if (e == 0) {
-      __hip_atomic_store(&row[0], kLbInclusive | c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&row[e], kLbAggregate | c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      int64_t j = e - 1;
-      while (true) {
-        const uint64_t wd = __hip_atomic_load(&row[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t flag = wd >> 62;
-        if (flag == 0) {
-          __builtin_amdgcn_s_sleep(1);
-          continue;
+  // decoupled look-back: wave 0 inspects 64 predecessors per step
+  if (h == 0) {
+    for (int s = 0; s < n_iso; ++s) {
+      const uint64_t c = (uint64_t)sm.cnt[s];
+      uint64_t* row = lookback + (int64_t)s * n_elem;
+      uint64_t prefix = 0;
+      if (e == 0) {
+        if (p == 0)
+          __hip_atomic_store(&row[0], kLbInclusive | c, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        if (p == 0)
+          __hip_atomic_store(&row[e], kLbAggregate | c, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        int64_t top = e - 1;
+        while (true) {
+          const int64_t idx = top - p;
+          const uint64_t wd = idx >= 0 ? __hip_atomic_load(&row[idx], __ATOMIC_ACQUIRE,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : kLbInclusive;
+          const uint64_t flag = wd >> 62;
+          const uint64_t inc = __ballot(flag == 2);
+          const uint64_t inv = __ballot(flag == 0);
+          // lanes up to (and including) the nearest inclusive word must be ready
+          const int first = inc ? __ffsll((unsigned long long)inc) - 1 : 63;
+          const uint64_t upto = first == 63 ? ~0ull : ((2ull << first) - 1ull);
+          if (inv & upto) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          prefix += wave_sum<uint64_t>((uint64_t)p <= (uint64_t)first ? (wd & kLbValue) : 0ull);
+          if (inc) break;
+          top -= 64;
         }
-        prefix += wd & kLbValue;
-        if (flag == 2) break;
-        --j;
+        if (p == 0)
+          __hip_atomic_store(&row[e], kLbInclusive | (prefix + c), __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
       }
-      __hip_atomic_store(&row[e], kLbInclusive | (prefix + c), __ATOMIC_RELEASE,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    sm.prefix[s] = (int64_t)prefix;
-    if (e == n_elem - 1) {
-      tri_count[s] = (int64_t)(prefix + c);
-      if (status && (int64_t)(prefix + c) > out.cap[s]) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
+      if (p == 0) {
+        sm.prefix[s] = (int64_t)prefix;
+        if (e == n_elem - 1) {
+          tri_count[s] = (int64_t)(prefix + c);
+          if (status && (int64_t)(prefix + c) > out.cap[s])
+            atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
+        }
+      }
     }
   }
   __syncthreads();
