@@ -852,7 +852,9 @@ __global__ void fill_i64(int64_t* __restrict__ p, int n, int64_t value) {
 // tiles are in LDS; each isovalue's triangle count is published with a
 // decoupled look-back word (Merrill & Garland 2016): flag AGGREGATE with
 // the element's own count, then INCLUSIVE with the prefix through it once
-// the predecessors' words are known.  Tickets make every predecessor a
+// the predecessors' words are known.  Flag and value share one 64-bit word
+// and nothing else is published through it, so relaxed device-scope atomics
+// suffice (an acquire load would invalidate the CU's L1 on every poll).  Tickets make every predecessor a
 // workgroup that has already started, so every wait ends.  The element then
 // emits its triangles at that prefix, in (cell, slot) order.
 
@@ -979,16 +981,16 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
       uint64_t prefix = 0;
       if (e == 0) {
         if (p == 0)
-          __hip_atomic_store(&row[0], kLbInclusive | c, __ATOMIC_RELEASE,
+          __hip_atomic_store(&row[0], kLbInclusive | c, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
       } else {
         if (p == 0)
-          __hip_atomic_store(&row[e], kLbAggregate | c, __ATOMIC_RELEASE,
+          __hip_atomic_store(&row[e], kLbAggregate | c, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
         int64_t top = e - 1;
         while (true) {
           const int64_t idx = top - p;
-          const uint64_t wd = idx >= 0 ? __hip_atomic_load(&row[idx], __ATOMIC_ACQUIRE,
+          const uint64_t wd = idx >= 0 ? __hip_atomic_load(&row[idx], __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT)
                                        : kLbInclusive;
           const uint64_t flag = wd >> 62;
@@ -998,7 +1000,7 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
           const int first = inc ? __ffsll((unsigned long long)inc) - 1 : 63;
           const uint64_t upto = first == 63 ? ~0ull : ((2ull << first) - 1ull);
           if (inv & upto) {
-            __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_s_sleep(8);
             continue;
           }
           prefix += wave_sum<uint64_t>((uint64_t)p <= (uint64_t)first ? (wd & kLbValue) : 0ull);
@@ -1006,7 +1008,7 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
           top -= 64;
         }
         if (p == 0)
-          __hip_atomic_store(&row[e], kLbInclusive | (prefix + c), __ATOMIC_RELEASE,
+          __hip_atomic_store(&row[e], kLbInclusive | (prefix + c), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
       }
       if (p == 0) {
