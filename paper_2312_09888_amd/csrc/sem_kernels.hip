@@ -871,6 +871,90 @@ __global__ void extract_reset(uint64_t* __restrict__ lookback, int64_t words,
   if (active && i < n_iso) active[i] = 0;
 }
 
+constexpr int kLbGroup = 4;    // isovalues per look-back group
+constexpr int kLbDepth = 2;    // 64-predecessor windows per step
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t* row, int64_t idx) {
+  return idx >= 0 ? __hip_atomic_load(&row[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : kLbInclusive;   // before element 0: inclusive prefix 0
+}
+
+// Decoupled look-back of element e for isovalues [s0, s0 + ns), run by one
+// full wave (lane p).  Publishes AGGREGATE, finds the running prefix from
+// the nearest INCLUSIVE word (all words in between must be published),
+// publishes INCLUSIVE and stores the exclusive prefix in prefix[s].
+__device__ __forceinline__ void lookback_group(uint64_t* __restrict__ lookback, int64_t n_elem,
+                                               int64_t e, int s0, int ns,
+                                               const int32_t* cnt, int64_t* prefix, int p) {
+  uint64_t* row[kLbGroup];
+  uint64_t pre[kLbGroup], own[kLbGroup];
+  int64_t top[kLbGroup];
+  bool done[kLbGroup];
+#pragma unroll
+  for (int g = 0; g < kLbGroup; ++g) {
+    const int s = s0 + (g < ns ? g : 0);
+    row[g] = lookback + (int64_t)s * n_elem;
+    own[g] = (uint64_t)cnt[s];
+    pre[g] = 0;
+    top[g] = e - 1;
+    done[g] = g >= ns || e == 0;
+    if (g < ns && p == 0)
+      __hip_atomic_store(&row[g][e], (e == 0 ? kLbInclusive : kLbAggregate) | own[g],
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int g = 0; g < kLbGroup; ++g) all = all && done[g];
+    if (all) break;
+    uint64_t wd[kLbGroup][kLbDepth];
+#pragma unroll
+    for (int g = 0; g < kLbGroup; ++g)
+#pragma unroll
+      for (int k = 0; k < kLbDepth; ++k)
+        wd[g][k] = done[g] ? kLbInclusive : lb_load(row[g], top[g] - p - 64 * k);
+    bool waiting = false;
+#pragma unroll
+    for (int g = 0; g < kLbGroup; ++g) {
+      if (done[g]) continue;
+      // nearest inclusive word, window by window
+      uint64_t add = 0;
+      bool ready = true, found = false;
+#pragma unroll
+      for (int k = 0; k < kLbDepth; ++k) {
+        if (found || !ready) continue;
+        const uint64_t flag = wd[g][k] >> 62;
+        const uint64_t inc = __ballot(flag == 2);
+        const uint64_t inv = __ballot(flag == 0);
+        const int first = inc ? __ffsll((unsigned long long)inc) - 1 : 63;
+        const uint64_t upto = first == 63 ? ~0ull : ((2ull << first) - 1ull);
+        if (inv & upto) {
+          ready = false;
+          continue;
+        }
+        add += (uint64_t)p <= (uint64_t)first ? (wd[g][k] & kLbValue) : 0ull;
+        found = inc != 0;
+      }
+      if (!ready) {
+        waiting = true;
+        continue;
+      }
+      pre[g] += wave_sum<uint64_t>(add);
+      if (found) {
+        done[g] = true;
+        if (p == 0)
+          __hip_atomic_store(&row[g][e], kLbInclusive | (pre[g] + own[g]), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        top[g] -= 64 * kLbDepth;
+      }
+    }
+    if (waiting) __builtin_amdgcn_s_sleep(4);
+  }
+  if (p == 0)
+    for (int g = 0; g < ns; ++g) prefix[s0 + g] = (int64_t)pre[g];
+}
+
 template <int N, typename T>
 struct ExtractLds {
   T X[Pen<N>::SZ];
@@ -973,51 +1057,19 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
     __syncthreads();
   }
 
-  // decoupled look-back: wave 0 inspects 64 predecessors per step
+  // decoupled look-back (wave 0): every step reads the words of 128
+  // predecessors for up to kLbGroup isovalues at once, so one device-scope
+  // round trip advances all of them
   if (h == 0) {
-    for (int s = 0; s < n_iso; ++s) {
-      const uint64_t c = (uint64_t)sm.cnt[s];
-      uint64_t* row = lookback + (int64_t)s * n_elem;
-      uint64_t prefix = 0;
-      if (e == 0) {
-        if (p == 0)
-          __hip_atomic_store(&row[0], kLbInclusive | c, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        if (p == 0)
-          __hip_atomic_store(&row[e], kLbAggregate | c, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        int64_t top = e - 1;
-        while (true) {
-          const int64_t idx = top - p;
-          const uint64_t wd = idx >= 0 ? __hip_atomic_load(&row[idx], __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : kLbInclusive;
-          const uint64_t flag = wd >> 62;
-          const uint64_t inc = __ballot(flag == 2);
-          const uint64_t inv = __ballot(flag == 0);
-          // lanes up to (and including) the nearest inclusive word must be ready
-          const int first = inc ? __ffsll((unsigned long long)inc) - 1 : 63;
-          const uint64_t upto = first == 63 ? ~0ull : ((2ull << first) - 1ull);
-          if (inv & upto) {
-            __builtin_amdgcn_s_sleep(8);
-            continue;
-          }
-          prefix += wave_sum<uint64_t>((uint64_t)p <= (uint64_t)first ? (wd & kLbValue) : 0ull);
-          if (inc) break;
-          top -= 64;
-        }
-        if (p == 0)
-          __hip_atomic_store(&row[e], kLbInclusive | (prefix + c), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (p == 0) {
-        sm.prefix[s] = (int64_t)prefix;
-        if (e == n_elem - 1) {
-          tri_count[s] = (int64_t)(prefix + c);
-          if (status && (int64_t)(prefix + c) > out.cap[s])
-            atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
-        }
+    for (int s0 = 0; s0 < n_iso; s0 += kLbGroup) {
+      const int ns = n_iso - s0 < kLbGroup ? n_iso - s0 : kLbGroup;
+      lookback_group(lookback, n_elem, e, s0, ns, sm.cnt, sm.prefix, p);
+    }
+    if (p == 0 && e == n_elem - 1) {
+      for (int s = 0; s < n_iso; ++s) {
+        const int64_t tot = sm.prefix[s] + sm.cnt[s];
+        tri_count[s] = tot;
+        if (status && tot > out.cap[s]) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
       }
     }
   }
