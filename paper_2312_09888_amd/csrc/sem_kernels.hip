@@ -872,7 +872,7 @@ __global__ void extract_reset(uint64_t* __restrict__ lookback, int64_t words,
 }
 
 constexpr int kLbGroup = 4;    // isovalues per look-back group
-constexpr int kLbDepth = 2;    // 64-predecessor windows per step
+constexpr int kLbDepth = 8;    // 64-predecessor windows per step
 
 __device__ __forceinline__ uint64_t lb_load(const uint64_t* row, int64_t idx) {
   return idx >= 0 ? __hip_atomic_load(&row[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
