@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--cpu-elements", type=int, default=16384,
                     help="elements of the snapshot the CPU oracle is timed on")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (a kernel of "
+                         "known HBM traffic for scaling profiler byte counters)")
     return ap.parse_args()
 
 
@@ -110,6 +113,15 @@ def main():
     torch.cuda.synchronize()
     log(args, f"inputs generated on GPU in {time.time() - t0:.1f} s "
               f"({points} points, {args.dtype})")
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=devn).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(args, "copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
 
     sem.init(0)
     k_iso = len(isos)

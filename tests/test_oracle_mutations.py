@@ -1,0 +1,233 @@
+"""Planted mistakes: each plausible error in the oracle must fail a pin.
+
+Every case patches one oracle function with a realistic slip (transposed
+operand, dropped term, wrong sign or index, inconsistent face rule), runs
+the relevant pin check on the CPU and expects it to fail.  The patches are
+undone after each case.
+"""
+
+import contextlib
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import gll, mc, sem
+
+
+@contextlib.contextmanager
+def patched(mod, name, fn):
+    old = getattr(mod, name)
+    setattr(mod, name, fn)
+    try:
+        yield
+    finally:
+        setattr(mod, name, old)
+
+
+def _fails(check):
+    with pytest.raises(AssertionError):
+        check()
+
+
+# --------------------------------------------------------------------------
+# pin checks (the same statements as the pin tests, at small sizes)
+# --------------------------------------------------------------------------
+
+def pin_polynomial():
+    n = 4
+    x, y, z = W.box_mesh((2, 1, 2), n, ((0.0, 1.3), (0.2, 0.9), (-0.5, 0.7)))
+    d = gll.diff_matrix(n)
+    f = x ** 3 * y ** 2 * z ** 4
+    (gx, gy, gz), _ = sem.derivs(x, y, z, f, d)
+    assert np.allclose(gx, 3 * x ** 2 * y ** 2 * z ** 4, atol=1e-10)
+    assert np.allclose(gy, 2 * x ** 3 * y * z ** 4, atol=1e-10)
+    assert np.allclose(gz, 4 * x ** 3 * y ** 2 * z ** 3, atol=1e-10)
+
+
+def pin_coordinate_identity():
+    n = 5
+    x, y, z = W.warp(*W.box_mesh((2, 2, 2), n, ((0, 2.0),) * 3), amp=0.1)
+    d = gll.diff_matrix(n)
+    jinv, _, _ = sem.geometry(x, y, z, d)
+    for i, c in enumerate((x, y, z)):
+        g = sem.physical_gradient(c, jinv, d)
+        for j in range(3):
+            assert np.allclose(g[j], 1.0 if i == j else 0.0, atol=1e-10)
+
+
+def pin_linear_fields():
+    n = 3
+    x, y, z = W.warp(*W.box_mesh((2, 1, 1), n, ((0, 1.5),) * 3), amp=0.08)
+    d = gll.diff_matrix(n)
+    q, om, _ = sem.qcrit(x, y, z, -y, x, 0 * x, d)
+    assert np.allclose(q, 1.0, atol=1e-10) and np.allclose(om, 2.0, atol=1e-10)
+    q, om, _ = sem.qcrit(x, y, z, y, 0 * x, 0 * x, d)
+    assert np.allclose(q, 0.0, atol=1e-10) and np.allclose(om, 1.0, atol=1e-10)
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=(3, 3))
+    u, v, w = (a[i, 0] * x + a[i, 1] * y + a[i, 2] * z for i in range(3))
+    q, om, _ = sem.qcrit(x, y, z, u, v, w, d)
+    assert np.allclose(q, -0.5 * np.trace(a @ a), atol=1e-9)
+    assert np.allclose(om ** 2, np.sum(a * a) - np.trace(a @ a), atol=1e-8)
+
+
+def pin_case_table():
+    mc._TABLE = None
+    ntri, table = mc.case_table()
+    for c in range(256):
+        bit = [(c >> v) & 1 for v in range(8)]
+        crossed = sum(bit[mc.EDGE_CORNERS[e][0]] != bit[mc.EDGE_CORNERS[e][1]]
+                      for e in range(12))
+        assert ntri[c] == crossed - 2 * len(mc.case_loops(c))
+
+
+def pin_watertight_1x1x2():
+    import test_oracle_mc as T
+    mc._TABLE = None
+    dims = (1, 1, 2)
+    pats = np.arange(2 ** 12, dtype=np.int64)
+    bits = (pats[:, None] >> np.arange(12)) & 1
+    vals = np.where(bits == 1, 1.0, -1.0).reshape(-1, 3, 2, 2)
+    x, y, z, f, origin = T._grid_elements(dims, vals)
+    r = mc.extract(x, y, z, f, [0.0], edge_keys=True)
+    gid, _ = T._global_vertex_ids(r["edge_key"].astype(np.int64), origin, dims, 2)
+    T._check_watertight(gid, T._boundary_fn(T._planes_factory(dims, 1)))
+
+
+def pin_sphere_outward():
+    import test_oracle_mc as T
+    mc._TABLE = None
+    r, _ = T._sphere(4)
+    p = r["tri_xyz"]
+    vol = np.sum(np.einsum("ti,ti->t", p[:, 0], np.cross(p[:, 1], p[:, 2]))) / 6.0
+    assert vol > 0
+
+
+def pin_ties():
+    f = np.zeros((1, 2, 2, 2))
+    f[0, 0, 0, 0] = 0.5
+    assert mc.classify(f, 0.5)[0, 0, 0, 0] == 0      # f == c is not above
+
+
+@pytest.fixture(autouse=True)
+def _fresh_table():
+    mc._TABLE = None
+    yield
+    mc._TABLE = None
+
+
+def test_pins_pass_unmutated():
+    for check in (pin_polynomial, pin_coordinate_identity, pin_linear_fields, pin_case_table,
+                  pin_watertight_1x1x2, pin_sphere_outward, pin_ties):
+        check()
+
+
+def test_transposed_derivative_matrix_is_caught():
+    orig = gll.diff_matrix
+    with patched(gll, "diff_matrix", lambda n, xi=None: orig(n, xi).T.copy()):
+        _fails(pin_polynomial)
+
+
+def test_wrong_contraction_index_is_caught():
+    orig = sem.ref_derivs
+
+    def bad(f, d):
+        fr, _, ft = orig(f, d)
+        fs = np.einsum("mj,ekmi->ekji", d, f)   # contracts D's first index
+        return fr, fs, ft
+    with patched(sem, "ref_derivs", bad):
+        _fails(pin_polynomial)
+    # (swapping s and t everywhere is a relabelling of the reference
+    # coordinates and leaves every physical result unchanged -- not a slip)
+
+
+def test_transposed_jacobian_inverse_is_caught():
+    orig = sem.inverse3
+
+    def bad(m):
+        inv, det = orig(m)
+        return np.swapaxes(inv, 0, 1), det
+    with patched(sem, "inverse3", bad):
+        _fails(pin_coordinate_identity)
+
+
+def test_dropped_chain_rule_term_is_caught():
+    def bad(f, jinv, d):
+        fr, fs, ft = sem.ref_derivs(f, d)
+        return tuple(fr * jinv[0, b] + fs * jinv[1, b] for b in range(3))
+    with patched(sem, "physical_gradient", bad):
+        _fails(pin_coordinate_identity)
+
+
+def test_q_sign_and_vorticity_index_are_caught():
+    def bad_sign(a):
+        q, om = (lambda qq: qq)(orig(a))
+        return -q, om
+    orig = sem.q_and_vorticity
+    with patched(sem, "q_and_vorticity", bad_sign):
+        _fails(pin_linear_fields)
+
+    def bad_omega(a):
+        q, _ = orig(a)
+        w1 = a[2, 1] - a[1, 2]
+        w2 = a[0, 2] - a[2, 0]
+        w3 = a[1, 0] + a[0, 1]      # wrong sign
+        return q, np.sqrt(w1 * w1 + w2 * w2 + w3 * w3)
+    with patched(sem, "q_and_vorticity", bad_omega):
+        _fails(pin_linear_fields)
+
+    def bad_q(a):
+        at = np.swapaxes(a, 0, 1)
+        s = 0.5 * (a + at)
+        om = 0.5 * (a - a)          # rotation part lost
+        q = 0.5 * (np.sum(om * om, axis=(0, 1)) - np.sum(s * s, axis=(0, 1)))
+        return q, orig(a)[1]
+    with patched(sem, "q_and_vorticity", bad_q):
+        _fails(pin_linear_fields)
+
+
+def test_smallest_edge_fan_start_is_caught():
+    with patched(mc, "fan_start", lambda loop: 0):
+        _fails(pin_watertight_1x1x2)
+
+
+def test_face_inconsistent_ambiguity_is_caught():
+    orig = mc.face_segments
+
+    def bad(case):
+        segs = orig(case)
+        # resolve ambiguous faces the other way on the z = 1 face only
+        bit = [(case >> v) & 1 for v in range(8)]
+        _, _, corners, edges, normal = mc.FACES[5]
+        crossed = [e for e in edges if bit[mc.EDGE_CORNERS[e][0]] != bit[mc.EDGE_CORNERS[e][1]]]
+        if len(crossed) != 4:
+            return segs
+        segs = [sg for sg in segs if not (sg[0] in edges and sg[1] in edges)]
+        below = [v for v in corners if not bit[v]]
+        for v in below:
+            inc = [e for e in crossed if v in mc.EDGE_CORNERS[e]]
+            p1, p2 = mc._edge_mid(inc[0]), mc._edge_mid(inc[1])
+            left = np.cross(normal, p2 - p1)
+            side = np.dot(left, mc.CORNER_POS[v] - p1)
+            segs.append((inc[1], inc[0]) if side > 0 else (inc[0], inc[1]))
+        return segs
+    with patched(mc, "face_segments", bad):
+        _fails(pin_watertight_1x1x2)
+
+
+def test_reversed_orientation_is_caught():
+    orig = mc.case_triangles
+
+    def bad(case):
+        return [(a, c, b) for a, b, c in orig(case)]
+    with patched(mc, "case_triangles", bad):
+        _fails(pin_sphere_outward)
+
+
+def test_non_strict_comparison_is_caught():
+    def bad(field, iso):
+        field = np.asarray(field)
+        return field >= field.dtype.type(iso)
+    with patched(mc, "above", bad):
+        _fails(pin_ties)
