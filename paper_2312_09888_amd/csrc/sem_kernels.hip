@@ -15,6 +15,7 @@
 // the Jacobian of a small element at a large absolute position accurate.
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "sem_internal.h"
 
@@ -544,6 +545,189 @@ qcrit_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __res
   if (bad && threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
   if (qmm) {
     block_minmax<T, 128>(mn, mx, sm.red);
+    if (threadIdx.x == 0) {
+      qmm[2 * (int64_t)blockIdx.x] = mn;
+      qmm[2 * (int64_t)blockIdx.x + 1] = mx;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// N = 7, FP64: element tiles staged in LDS by direct global->LDS loads
+// ---------------------------------------------------------------------------
+//
+// Each element's six tiles (4 KiB each) are fetched with global_load_lds
+// (16 bytes per lane, 1 KiB per wave instruction, fully coalesced, no
+// registers held while the data is in flight).  A lane may fetch any
+// 16-byte chunk (two neighbouring i) and it lands at LDS slot
+// base + lane, so the chunk placement is chosen freely:
+//   slot(k, j, ip) = 4 (8k + (j ^ (k & 1))) + (ip ^ ((j >> 1) & 3)),
+// i.e. rows j <-> j^1 swapped in odd slabs and the four chunks of a row
+// rotated by j >> 1.  With 32 four-byte banks this makes the r-line reads
+// (16 bytes per lane, fixed chunk, lanes over j), the s-line reads (8 bytes,
+// lanes over i and a pair of k) and the t-line reads (8 bytes, lanes over i
+// and a pair of j) free of bank conflicts.
+
+namespace dma7 {
+__device__ __forceinline__ constexpr int slot(int k, int j, int ip) {
+  return 4 * (8 * k + (j ^ (k & 1))) + (ip ^ ((j >> 1) & 3));
+}
+__device__ __forceinline__ constexpr int at(int i, int j, int k) {
+  return 2 * slot(k, j, i >> 1) + (i & 1);
+}
+}  // namespace dma7
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Fetch one 4 KiB tile: wave h issues the chunk groups h and h + 2.
+__device__ __forceinline__ void dma_tile(const double* __restrict__ src, double* raw, int h,
+                                         int lane) {
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    const int part = 2 * pp + h;
+    const int s = 64 * part + lane;
+    const int row = s >> 2, k = row >> 3, j = (row & 7) ^ (k & 1);
+    const int ip = (s & 3) ^ ((j >> 1) & 3);
+    __builtin_amdgcn_global_load_lds(src + 2 * (ip + 4 * j + 32 * k),
+                                     (lds_ptr_t)(raw + 128 * part), 16, 0, 0);
+  }
+}
+
+struct DmaTiles {
+  double raw[6][512];
+  double S[Pen<7>::SZ];
+  double Tt[Pen<7>::SZ];
+  double red[4];
+};
+
+// One field from its staged tile: the owner gets (f_r, f_s, f_t) at its four
+// nodes.  Wave 0 differentiates the s-lines, wave 1 the t-lines.
+__device__ __forceinline__ void dma_pass(const double* __restrict__ raw,
+                                         const double* __restrict__ d, double* __restrict__ S,
+                                         double* __restrict__ Tt, int h, int p, double (&fr)[4],
+                                         double (&fs)[4], double (&ft)[4]) {
+  using Q = Pen<7>;
+  const int j = p & 7, k = p >> 3;
+  double f[8];
+#pragma unroll
+  for (int ip = 0; ip < 4; ++ip) {
+    const double2 v = *reinterpret_cast<const double2*>(raw + 2 * dma7::slot(k, j, ip));
+    f[2 * ip] = v.x;
+    f[2 * ip + 1] = v.y;
+  }
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) fr[ii] = line_deriv<8>(d, 4 * h + ii, f);
+  double g[8];
+  if (h == 0) {  // s-line at (i, k) = (j, k) of this lane's index
+#pragma unroll
+    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, m, k)];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) S[Q::at(j, jj, k)] = line_deriv<8>(d, jj, g);
+  } else {       // t-line at (i, j) = (j, k) of this lane's index
+#pragma unroll
+    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, k, m)];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) Tt[Q::at(j, k, kk)] = line_deriv<8>(d, kk, g);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    fs[ii] = S[Q::at(4 * h + ii, j, k)];
+    ft[ii] = Tt[Q::at(4 * h + ii, j, k)];
+  }
+  __syncthreads();
+}
+
+// Q and |omega| at the owner's four nodes from the six staged tiles.
+__device__ __forceinline__ bool dma_qcrit(DmaTiles& sm, const double* __restrict__ d, int h,
+                                          int p, double (&qv)[4], double (&om)[4]) {
+  double xr[4], xs[4], xt[4], yr[4], ys[4], yt[4], zr[4], zs[4], zt[4];
+  dma_pass(sm.raw[0], d, sm.S, sm.Tt, h, p, xr, xs, xt);
+  dma_pass(sm.raw[1], d, sm.S, sm.Tt, h, p, yr, ys, yt);
+  dma_pass(sm.raw[2], d, sm.S, sm.Tt, h, p, zr, zs, zt);
+  InvJac<double> kk[4];
+  bool ok = true;
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+    ok = invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii], zt[ii],
+                         kk[ii]) && ok;
+  double fr[4], fs[4], ft[4], a01[4], a02[4], a12[4];
+  dma_pass(sm.raw[3], d, sm.S, sm.Tt, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const InvJac<double>& K = kk[ii];
+    const double a00 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    a01[ii] = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    a02[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = a00 * a00;
+  }
+  dma_pass(sm.raw[4], d, sm.S, sm.Tt, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const InvJac<double>& K = kk[ii];
+    const double a10 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    const double a11 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    a12[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = qv[ii] + a11 * a11 + 2.0 * (a01[ii] * a10);
+    const double w3 = a10 - a01[ii];
+    om[ii] = w3 * w3;
+  }
+  dma_pass(sm.raw[5], d, sm.S, sm.Tt, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const InvJac<double>& K = kk[ii];
+    const double a20 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    const double a21 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    const double a22 = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = -0.5 * (qv[ii] + a22 * a22 + 2.0 * (a02[ii] * a20 + a12[ii] * a21));
+    const double w1 = a21 - a12[ii], w2 = a02[ii] - a20;
+    om[ii] = sqrt(om[ii] + w1 * w1 + w2 * w2);
+  }
+  return ok;
+}
+
+__device__ __forceinline__ void dma_fetch_element(DmaTiles& sm, const double* x, const double* y,
+                                                  const double* z, const double* u,
+                                                  const double* v, const double* w, int64_t base,
+                                                  int h, int lane) {
+  dma_tile(x + base, sm.raw[0], h, lane);
+  dma_tile(y + base, sm.raw[1], h, lane);
+  dma_tile(z + base, sm.raw[2], h, lane);
+  dma_tile(u + base, sm.raw[3], h, lane);
+  dma_tile(v + base, sm.raw[4], h, lane);
+  dma_tile(w + base, sm.raw[5], h, lane);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(128)
+qcrit_dma7(const double* __restrict__ dmat, const double* __restrict__ x,
+           const double* __restrict__ y, const double* __restrict__ z,
+           const double* __restrict__ u, const double* __restrict__ v,
+           const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
+           double* __restrict__ qmm, int32_t* __restrict__ status) {
+  __shared__ DmaTiles sm;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int p = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * 512;
+  dma_fetch_element(sm, x, y, z, u, v, w, base, h, p);
+  double qv[4], ov[4];
+  int bad = !dma_qcrit(sm, dmat, h, p, qv, ov);
+  const int j = p & 7, k = p >> 3;
+  double mn = pos_inf<double>(), mx = neg_inf<double>();
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const int64_t o = base + (k * 8 + j) * 8 + 4 * h + ii;
+    if (q) q[o] = qv[ii];
+    if (om) om[o] = ov[ii];
+    const double c = qv[ii] != qv[ii] ? neg_inf<double>() : qv[ii];
+    mn = c < mn ? c : mn;
+    mx = c > mx ? c : mx;
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  if (qmm) {
+    block_minmax<double, 128>(mn, mx, sm.red);
     if (threadIdx.x == 0) {
       qmm[2 * (int64_t)blockIdx.x] = mn;
       qmm[2 * (int64_t)blockIdx.x + 1] = mx;
@@ -1099,6 +1283,171 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
   }
 }
 
+// Fused extraction for N = 7, FP64, on the direct-load tile layout.  Same
+// steps and output as extract_pencil; the staged x, y, z tiles serve the
+// vertex interpolation and the u tile (free after its pass) holds Q.
+struct DmaExtractLds {
+  DmaTiles t;
+  int64_t prefix[SEM_MAX_ISO];
+  int32_t cnt[SEM_MAX_ISO];
+  int32_t wave[4];
+  uint8_t ntri[256];
+  int8_t tri[256 * kMcMaxTri * 3];
+  uint32_t e;
+};
+
+__device__ __forceinline__ int dma_cell_case(const double* __restrict__ qt, int ci, int cj,
+                                             int ck, double c) {
+  int cs = 0;
+#pragma unroll
+  for (int vtx = 0; vtx < 8; ++vtx)
+    cs |= (qt[dma7::at(ci + (vtx & 1), cj + ((vtx >> 1) & 1), ck + (vtx >> 2))] > c) << vtx;
+  return cs;
+}
+
+__device__ __forceinline__ void dma_emit_cell(int cs, int nt, int ci, int cj, int ck, double c,
+                                              const double* __restrict__ qt,
+                                              const double* __restrict__ sx,
+                                              const double* __restrict__ sy,
+                                              const double* __restrict__ sz,
+                                              const int8_t* __restrict__ s_tri,
+                                              double* __restrict__ out, int64_t g, int64_t cap) {
+  for (int slot = 0; slot < nt; ++slot, ++g) {
+    if (g >= cap) break;
+    double* o = out + g * 9;
+#pragma unroll
+    for (int vtx = 0; vtx < 3; ++vtx) {
+      const int edge = s_tri[(cs * kMcMaxTri + slot) * 3 + vtx];
+      const int v0 = kEdgeLo[edge];
+      const int ax = kEdgeAxis[edge];
+      const int a0 = ci + (v0 & 1), b0 = cj + ((v0 >> 1) & 1), c0 = ck + (v0 >> 2);
+      const int lo = dma7::at(a0, b0, c0);
+      const int hi = dma7::at(a0 + (ax == 0), b0 + (ax == 1), c0 + (ax == 2));
+      {
+#pragma clang fp contract(off)
+        const double f0 = qt[lo], f1 = qt[hi];
+        const double tt = (c - f0) / (f1 - f0);
+        o[3 * vtx + 0] = sx[lo] + tt * (sx[hi] - sx[lo]);
+        o[3 * vtx + 1] = sy[lo] + tt * (sy[hi] - sy[lo]);
+        o[3 * vtx + 2] = sz[lo] + tt * (sz[hi] - sz[lo]);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(128)
+extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __restrict__ x,
+             const double* __restrict__ y, const double* __restrict__ z,
+             const double* __restrict__ u, const double* __restrict__ v,
+             const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
+             double* __restrict__ qmm, int n_iso, IsoList<double> iso, IsoOut<double> out,
+             const uint8_t* __restrict__ ntri_tab, const int8_t* __restrict__ tri_tab,
+             uint64_t* __restrict__ lookback, uint32_t* __restrict__ ticket,
+             int64_t* __restrict__ tri_count, int64_t* __restrict__ active,
+             int32_t* __restrict__ status) {
+  constexpr int NC = 343, ROUNDS = 3;
+  __shared__ DmaExtractLds sm;
+  const int t = threadIdx.x;
+  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int p = t & 63;
+  if (t == 0) sm.e = atomicAdd(ticket, 1u);
+  for (int k = t; k < 256; k += 128) sm.ntri[k] = ntri_tab[k];
+  for (int k = t; k < 256 * kMcMaxTri * 3; k += 128) sm.tri[k] = tri_tab[k];
+  __syncthreads();
+  const int64_t e = sm.e;
+  const int64_t base = e * 512;
+  dma_fetch_element(sm.t, x, y, z, u, v, w, base, h, p);
+
+  double qv[4], ov[4];
+  int bad = !dma_qcrit(sm.t, dmat, h, p, qv, ov);
+  double* QT = sm.t.raw[3];
+  const int j = p & 7, k = p >> 3;
+  double mn = pos_inf<double>(), mx = neg_inf<double>();
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+    const int i = 4 * h + ii;
+    const int64_t o = base + (k * 8 + j) * 8 + i;
+    if (q) q[o] = qv[ii];
+    if (om) om[o] = ov[ii];
+    QT[dma7::at(i, j, k)] = qv[ii];
+    const double c = qv[ii] != qv[ii] ? neg_inf<double>() : qv[ii];
+    mn = c < mn ? c : mn;
+    mx = c > mx ? c : mx;
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  block_minmax<double, 128>(mn, mx, sm.t.red);
+  if (qmm && t == 0) {
+    qmm[2 * e] = mn;
+    qmm[2 * e + 1] = mx;
+  }
+
+  for (int s = 0; s < n_iso; ++s) {
+    const double c = iso.v[s];
+    int nt = 0, act = 0;
+    if ((mx > c) && !(mn > c)) {
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        const int cell = r * 128 + t;
+        if (cell < NC) {
+          const int cs = dma_cell_case(QT, cell % 7, (cell / 7) % 7, cell / 49, c);
+          nt += sm.ntri[cs];
+          act += (cs != 0 && cs != 255);
+        }
+      }
+    }
+    nt = wave_sum(nt);
+    act = wave_sum(act);
+    if (p == 0) {
+      sm.wave[h] = nt;
+      sm.wave[2 + h] = act;
+    }
+    __syncthreads();
+    if (t == 0) {
+      sm.cnt[s] = sm.wave[0] + sm.wave[1];
+      const int a = sm.wave[2] + sm.wave[3];
+      if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
+    }
+    __syncthreads();
+  }
+
+  if (h == 0) {
+    for (int s0 = 0; s0 < n_iso; s0 += kLbGroup) {
+      const int ns = n_iso - s0 < kLbGroup ? n_iso - s0 : kLbGroup;
+      lookback_group(lookback, n_elem, e, s0, ns, sm.cnt, sm.prefix, p);
+    }
+    if (p == 0 && e == n_elem - 1) {
+      for (int s = 0; s < n_iso; ++s) {
+        const int64_t tot = sm.prefix[s] + sm.cnt[s];
+        tri_count[s] = tot;
+        if (status && tot > out.cap[s]) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int s = 0; s < n_iso; ++s) {
+    if (sm.cnt[s] == 0) continue;
+    const double c = iso.v[s];
+    int64_t g0 = sm.prefix[s];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const int cell = r * 128 + t;
+      int cs = 0, nt = 0;
+      const int ci = cell % 7, cj = (cell / 7) % 7, ck = cell / 49;
+      if (cell < NC) {
+        cs = dma_cell_case(QT, ci, cj, ck, c);
+        nt = sm.ntri[cs];
+      }
+      int tot;
+      const int pre = block_count_prefix<128>(nt, sm.wave, &tot);
+      dma_emit_cell(cs, nt, ci, cj, ck, c, QT, sm.t.raw[0], sm.t.raw[1], sm.t.raw[2], sm.tri,
+                    out.ptr[s], g0 + pre, out.cap[s]);
+      g0 += tot;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // dispatch over the order
 // ---------------------------------------------------------------------------
@@ -1148,6 +1497,14 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
                    const void* y, const void* z, const void* u, const void* v, const void* w,
                    void* q, void* om, void* qmm, int32_t* status, hipStream_t s) {
   const T* d = dmat_of<T>(tab, order);
+  if constexpr (std::is_same<T, double>::value) {
+    if (order == 7) {
+      hipLaunchKernelGGL(qcrit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, d, (const T*)x,
+                         (const T*)y, (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q,
+                         (T*)om, (T*)qmm, status);
+      return hipGetLastError();
+    }
+  }
   SEM_ORDER_SWITCH(order, {
     if constexpr (N <= 7) {
       hipLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s, d,
@@ -1241,6 +1598,15 @@ hipError_t extract_t(int order, const DeviceTables& tab, int64_t n_elem, const v
     const int64_t words = (int64_t)n_iso * n_elem;
     hipLaunchKernelGGL(extract_reset, dim3((unsigned)((words + 255) / 256 + 1)), dim3(256), 0,
                        s, ws.lookback, words, ws.ticket, active, n_iso);
+    if constexpr (std::is_same<T, double>::value) {
+      if (order == 7) {
+        hipLaunchKernelGGL(extract_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, n_elem, d,
+                           (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
+                           (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso, iso, out, tab.ntri,
+                           tab.tri, ws.lookback, ws.ticket, tri_count, active, status);
+        return hipGetLastError();
+      }
+    }
     SEM_ORDER_SWITCH(order, {
       if constexpr (N <= 7) {
         hipLaunchKernelGGL((extract_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
