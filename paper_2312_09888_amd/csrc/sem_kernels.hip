@@ -577,6 +577,12 @@ __device__ __forceinline__ constexpr int at(int i, int j, int k) {
 }
 }  // namespace dma7
 
+struct DmaNode {
+  __device__ __forceinline__ int operator()(int i, int j, int k) const {
+    return dma7::at(i, j, k);
+  }
+};
+
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 // Fetch one 4 KiB tile: wave h issues the chunk groups h and h + 2.
@@ -766,43 +772,6 @@ __device__ __forceinline__ int cell_case(const T* __restrict__ sf, int n0, T c) 
   return cell_case_strided<N + 1, (N + 1) * (N + 1)>(sf, n0, c);
 }
 
-// Write the nt triangles of one cell (case cs, lowest node at tile offset n0
-// with tile strides RS, SS) at triangle index g of `out` (capacity cap).
-// Field and coordinates are read from tiles; `key_lo` is the element-global
-// index of the cell's lowest node in the unpadded layout (edge keys).
-template <int P, int RS, int SS, typename T>
-__device__ __forceinline__ void emit_cell(int cs, int nt, int n0, T c, const T* __restrict__ sf,
-                                          const T* __restrict__ sx, const T* __restrict__ sy,
-                                          const T* __restrict__ sz,
-                                          const int8_t* __restrict__ s_tri, T* __restrict__ out,
-                                          int64_t g, int64_t cap, uint64_t* __restrict__ keys,
-                                          int64_t key_lo) {
-  for (int slot = 0; slot < nt; ++slot, ++g) {
-    if (g >= cap) break;
-    T* o = out + g * 9;
-#pragma unroll
-    for (int vtx = 0; vtx < 3; ++vtx) {
-      const int edge = s_tri[(cs * kMcMaxTri + slot) * 3 + vtx];
-      const int corner = kEdgeLo[edge];
-      const int ax = kEdgeAxis[edge];
-      const int lo = n0 + corner_offset<RS, SS>(corner);
-      const int hi = lo + (ax == 0 ? 1 : ax == 1 ? RS : SS);
-      {
-#pragma clang fp contract(off)
-        const T f0 = sf[lo], f1 = sf[hi];
-        const T tt = (c - f0) / (f1 - f0);
-        o[3 * vtx + 0] = sx[lo] + tt * (sx[hi] - sx[lo]);
-        o[3 * vtx + 1] = sy[lo] + tt * (sy[hi] - sy[lo]);
-        o[3 * vtx + 2] = sz[lo] + tt * (sz[hi] - sz[lo]);
-      }
-      if (keys) {
-        const int64_t node = key_lo + corner_offset<P, P * P>(corner);
-        keys[g * 3 + vtx] = (uint64_t)node * 3u + (uint64_t)ax;
-      }
-    }
-  }
-}
-
 // Exclusive prefix over the cells of a block of the per-cell triangle counts
 // nt (0..7): one ballot per bit gives the wave prefix; wave totals go through
 // LDS.  Returns the thread's offset; *block_total receives the block total.
@@ -825,6 +794,82 @@ __device__ __forceinline__ int block_count_prefix(int nt, int32_t* s_wave, int* 
   *block_total = tot;
   return pre;
 }
+
+// Balanced emission of one element's triangles for one isovalue.  First
+// every cell (in rounds of TH threads, cell order) records its case and
+// writes one descriptor (cell << 3 | slot) per triangle into `desc` at its
+// running prefix; then thread v computes vertex v of that list.  Every lane
+// does the same amount of work however unevenly the triangles fall on the
+// cells, and consecutive lanes write consecutive vertices.  `node(i, j, k)`
+// maps a node to its tile index.  Returns the element's triangle count.
+template <int N, int TH, typename T, class NodeFn>
+__device__ __forceinline__ int emit_element(T c, NodeFn node, const T* __restrict__ ft,
+                                            const T* __restrict__ sx, const T* __restrict__ sy,
+                                            const T* __restrict__ sz,
+                                            const uint8_t* __restrict__ s_ntri,
+                                            const int8_t* __restrict__ s_tri,
+                                            uint8_t* __restrict__ cases,
+                                            uint16_t* __restrict__ desc, int32_t* s_wave,
+                                            T* __restrict__ out, int64_t g0, int64_t cap,
+                                            uint64_t* __restrict__ keys, int64_t key_base) {
+  constexpr int P = N + 1, NC = N * N * N, ROUNDS = (NC + TH - 1) / TH;
+  const int t = threadIdx.x;
+  int run = 0;
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int cell = r * TH + t;
+    int cs = 0, nt = 0;
+    if (cell < NC) {
+      const int ci = cell % N, cj = (cell / N) % N, ck = cell / (N * N);
+#pragma unroll
+      for (int vtx = 0; vtx < 8; ++vtx)
+        cs |= (ft[node(ci + (vtx & 1), cj + ((vtx >> 1) & 1), ck + (vtx >> 2))] > c) << vtx;
+      nt = s_ntri[cs];
+      cases[cell] = (uint8_t)cs;
+    }
+    int tot;
+    const int pre = block_count_prefix<TH>(nt, s_wave, &tot);
+    for (int sl = 0; sl < nt; ++sl) desc[run + pre + sl] = (uint16_t)((cell << 3) | sl);
+    run += tot;
+  }
+  __syncthreads();
+  for (int vv = t; vv < 3 * run; vv += TH) {
+    const int tri = vv / 3, vtx = vv - 3 * tri;
+    const int64_t g = g0 + tri;
+    if (g >= cap) continue;
+    const int dsc = desc[tri];
+    const int cell = dsc >> 3, slot = dsc & 7;
+    const int cs = cases[cell];
+    const int ci = cell % N, cj = (cell / N) % N, ck = cell / (N * N);
+    const int edge = s_tri[(cs * kMcMaxTri + slot) * 3 + vtx];
+    const int v0 = kEdgeLo[edge];
+    const int ax = kEdgeAxis[edge];
+    const int a0 = ci + (v0 & 1), b0 = cj + ((v0 >> 1) & 1), c0 = ck + (v0 >> 2);
+    const int lo = node(a0, b0, c0);
+    const int hi = node(a0 + (ax == 0), b0 + (ax == 1), c0 + (ax == 2));
+    T* o = out + g * 9 + 3 * vtx;
+    {
+#pragma clang fp contract(off)
+      const T f0 = ft[lo], f1 = ft[hi];
+      const T tt = (c - f0) / (f1 - f0);
+      o[0] = sx[lo] + tt * (sx[hi] - sx[lo]);
+      o[1] = sy[lo] + tt * (sy[hi] - sy[lo]);
+      o[2] = sz[lo] + tt * (sz[hi] - sz[lo]);
+    }
+    if (keys)
+      keys[g * 3 + vtx] = (uint64_t)(key_base + a0 + P * (b0 + P * c0)) * 3u + (uint64_t)ax;
+  }
+  __syncthreads();
+  return run;
+}
+
+// Tile index functions for emit_element.
+template <int RS, int SS>
+struct StridedNode {
+  __device__ __forceinline__ int operator()(int i, int j, int k) const {
+    return i + RS * j + SS * k;
+  }
+};
 
 // Per (isovalue, element): triangle and active-cell counts; optional case dump.
 template <int N, typename T>
@@ -907,6 +952,8 @@ iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
   __shared__ T sf[S::NP], sx[S::NP], sy[S::NP], sz[S::NP];
   __shared__ uint8_t s_ntri[256];
   __shared__ int8_t s_tri[256 * kMcMaxTri * 3];
+  __shared__ uint8_t s_case[S::NC];
+  __shared__ uint16_t s_desc[S::NC * kMcMaxTri];
   __shared__ int32_t s_wave[TH / 64];
   const int t = threadIdx.x;
   const int64_t e = blockIdx.x;
@@ -923,20 +970,10 @@ iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
     sz[q] = z[base + q];
   }
   __syncthreads();
-  const int i = t % N, j = (t / N) % N, k = t / (N * N);
-  const int n0 = i + P * (j + P * k);
   for (int s = 0; s < n_iso; ++s) {
     const int64_t flat = (int64_t)s * n_elem + e;
     if (cnt[flat] == 0) continue;
-    const T c = iso.v[s];
-    int cs = 0, nt = 0;
-    if (t < S::NC) {
-      cs = cell_case<N>(sf, n0, c);
-      nt = s_ntri[cs];
-    }
-    int tot;
-    const int pre = block_count_prefix<TH>(nt, s_wave, &tot);
-    int64_t g = offs[flat] + pre;
+    int64_t g = offs[flat];
     T* dst = out.ptr[0];
     int64_t cap = out.cap[0];
     if (out.per_iso) {
@@ -944,8 +981,9 @@ iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
       dst = out.ptr[s];
       cap = out.cap[s];
     }
-    emit_cell<P, P, P * P>(cs, nt, n0, c, sf, sx, sy, sz, s_tri, dst, g, cap,
-                           out.per_iso ? nullptr : keys, base + n0);
+    emit_element<N, TH>(iso.v[s], StridedNode<P, P * P>{}, sf, sx, sy, sz, s_ntri, s_tri,
+                        s_case, s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys,
+                        base);
   }
 }
 
@@ -1259,27 +1297,17 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
   }
   __syncthreads();
 
-  // emission in (cell, slot) order at the element's offset
+  // emission in (cell, slot) order at the element's offset; the s- and
+  // t-transpose tiles are free now and hold the case / descriptor lists
+  static_assert(((NC + 15) & ~15) + NC * kMcMaxTri * 2 <= 2 * Q::SZ * (int)sizeof(T),
+                "case and descriptor lists must fit in the transpose tiles");
+  uint8_t* cases = reinterpret_cast<uint8_t*>(sm.pt.S);
+  uint16_t* desc = reinterpret_cast<uint16_t*>(cases + ((NC + 15) & ~15));
   for (int s = 0; s < n_iso; ++s) {
     if (sm.cnt[s] == 0) continue;
-    const T c = iso.v[s];
-    int64_t g0 = sm.prefix[s];
-#pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-      const int cell = r * 128 + t;
-      int cs = 0, nt = 0, n0 = 0;
-      if (cell < NC) {
-        const int ci = cell % N, cj = (cell / N) % N, ck = cell / (N * N);
-        n0 = Q::at(ci, cj, ck);
-        cs = cell_case_strided<RS, SS>(QT, n0, c);
-        nt = sm.ntri[cs];
-      }
-      int tot;
-      const int pre = block_count_prefix<128>(nt, sm.wave, &tot);
-      emit_cell<P, RS, SS>(cs, nt, n0, c, QT, sm.X, sm.Y, sm.Z, sm.tri, out.ptr[s], g0 + pre,
-                           out.cap[s], (uint64_t*)nullptr, 0);
-      g0 += tot;
-    }
+    emit_element<N, 128>(iso.v[s], StridedNode<RS, SS>{}, QT, sm.X, sm.Y, sm.Z, sm.ntri,
+                         sm.tri, cases, desc, sm.wave, out.ptr[s], sm.prefix[s], out.cap[s],
+                         (uint64_t*)nullptr, 0);
   }
 }
 
@@ -1303,36 +1331,6 @@ __device__ __forceinline__ int dma_cell_case(const double* __restrict__ qt, int 
   for (int vtx = 0; vtx < 8; ++vtx)
     cs |= (qt[dma7::at(ci + (vtx & 1), cj + ((vtx >> 1) & 1), ck + (vtx >> 2))] > c) << vtx;
   return cs;
-}
-
-__device__ __forceinline__ void dma_emit_cell(int cs, int nt, int ci, int cj, int ck, double c,
-                                              const double* __restrict__ qt,
-                                              const double* __restrict__ sx,
-                                              const double* __restrict__ sy,
-                                              const double* __restrict__ sz,
-                                              const int8_t* __restrict__ s_tri,
-                                              double* __restrict__ out, int64_t g, int64_t cap) {
-  for (int slot = 0; slot < nt; ++slot, ++g) {
-    if (g >= cap) break;
-    double* o = out + g * 9;
-#pragma unroll
-    for (int vtx = 0; vtx < 3; ++vtx) {
-      const int edge = s_tri[(cs * kMcMaxTri + slot) * 3 + vtx];
-      const int v0 = kEdgeLo[edge];
-      const int ax = kEdgeAxis[edge];
-      const int a0 = ci + (v0 & 1), b0 = cj + ((v0 >> 1) & 1), c0 = ck + (v0 >> 2);
-      const int lo = dma7::at(a0, b0, c0);
-      const int hi = dma7::at(a0 + (ax == 0), b0 + (ax == 1), c0 + (ax == 2));
-      {
-#pragma clang fp contract(off)
-        const double f0 = qt[lo], f1 = qt[hi];
-        const double tt = (c - f0) / (f1 - f0);
-        o[3 * vtx + 0] = sx[lo] + tt * (sx[hi] - sx[lo]);
-        o[3 * vtx + 1] = sy[lo] + tt * (sy[hi] - sy[lo]);
-        o[3 * vtx + 2] = sz[lo] + tt * (sz[hi] - sz[lo]);
-      }
-    }
-  }
 }
 
 __global__ void __launch_bounds__(128)
@@ -1426,25 +1424,16 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
   }
   __syncthreads();
 
+  // emission; the v tile (free since the Q computation) holds the case and
+  // descriptor lists
+  static_assert(352 + NC * kMcMaxTri * 2 <= 512 * (int)sizeof(double), "lists fit one tile");
+  uint8_t* cases = reinterpret_cast<uint8_t*>(sm.t.raw[4]);
+  uint16_t* desc = reinterpret_cast<uint16_t*>(cases + 352);
   for (int s = 0; s < n_iso; ++s) {
     if (sm.cnt[s] == 0) continue;
-    const double c = iso.v[s];
-    int64_t g0 = sm.prefix[s];
-#pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-      const int cell = r * 128 + t;
-      int cs = 0, nt = 0;
-      const int ci = cell % 7, cj = (cell / 7) % 7, ck = cell / 49;
-      if (cell < NC) {
-        cs = dma_cell_case(QT, ci, cj, ck, c);
-        nt = sm.ntri[cs];
-      }
-      int tot;
-      const int pre = block_count_prefix<128>(nt, sm.wave, &tot);
-      dma_emit_cell(cs, nt, ci, cj, ck, c, QT, sm.t.raw[0], sm.t.raw[1], sm.t.raw[2], sm.tri,
-                    out.ptr[s], g0 + pre, out.cap[s]);
-      g0 += tot;
-    }
+    emit_element<7, 128>(iso.v[s], DmaNode{}, QT, sm.t.raw[0], sm.t.raw[1], sm.t.raw[2],
+                         sm.ntri, sm.tri, cases, desc, sm.wave, out.ptr[s], sm.prefix[s],
+                         out.cap[s], (uint64_t*)nullptr, 0);
   }
 }
 
