@@ -599,12 +599,71 @@ __device__ __forceinline__ void dma_tile(const double* __restrict__ src, double*
   }
 }
 
+// The coordinate and velocity tiles are separate LDS objects so that the
+// compiler tracks their direct loads separately (a wait for the coordinate
+// tiles does not have to wait for the velocity tiles).
 struct DmaTiles {
-  double raw[6][512];
+  double (*xyz)[512];   // [3][512]: x, y, z (kept for the vertices)
+  double (*uvw)[512];   // [3][512]: u, v, w (u later holds Q, v the lists)
+  double* S;
+  double* Tt;
+  double* red;
+};
+
+struct DmaWork {
   double S[Pen<7>::SZ];
   double Tt[Pen<7>::SZ];
   double red[4];
 };
+
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt
+// left at their maxima): wait until at most n vector-memory operations of
+// this wave are outstanding.
+constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
+// ... and additionally all LDS operations of this wave (lgkmcnt(0)).
+constexpr int waitcnt_vm_lds(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70; }
+
+// Barrier after an explicit wait: a plain s_barrier (the compiler-level
+// memory clobbers keep LDS accesses on their side of it).  __syncthreads()
+// would add a workgroup fence, which must also wait for every direct load
+// still in flight.
+__device__ __forceinline__ void barrier_after_wait() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Workgroup barrier for ordinary LDS traffic while direct loads may still be
+// in flight: wait for this wave's LDS operations only, then s_barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt untouched
+  barrier_after_wait();
+}
+
+// Issue the six tile fetches of an element.  Each wave issues two 16-byte
+// loads per tile, coordinates first; dma_wait_coords() waits for the
+// coordinate tiles only, so the velocity tiles keep arriving during the
+// geometry passes; dma_wait_all() waits for the rest.
+__device__ __forceinline__ void dma_fetch_element(DmaTiles& sm, const double* x, const double* y,
+                                                  const double* z, const double* u,
+                                                  const double* v, const double* w, int64_t base,
+                                                  int h, int lane) {
+  dma_tile(x + base, sm.xyz[0], h, lane);
+  dma_tile(y + base, sm.xyz[1], h, lane);
+  dma_tile(z + base, sm.xyz[2], h, lane);
+  dma_tile(u + base, sm.uvw[0], h, lane);
+  dma_tile(v + base, sm.uvw[1], h, lane);
+  dma_tile(w + base, sm.uvw[2], h, lane);
+}
+// Six coordinate loads per wave were issued before the six velocity loads.
+__device__ __forceinline__ void dma_wait_coords() {
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(6));
+  barrier_after_wait();
+}
+__device__ __forceinline__ void dma_wait_all() {
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
+  barrier_after_wait();
+}
 
 // One field from its staged tile: the owner gets (f_r, f_s, f_t) at its four
 // nodes.  Wave 0 differentiates the s-lines, wave 1 the t-lines.
@@ -635,22 +694,23 @@ __device__ __forceinline__ void dma_pass(const double* __restrict__ raw,
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) Tt[Q::at(j, k, kk)] = line_deriv<8>(d, kk, g);
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int ii = 0; ii < 4; ++ii) {
     fs[ii] = S[Q::at(4 * h + ii, j, k)];
     ft[ii] = Tt[Q::at(4 * h + ii, j, k)];
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Q and |omega| at the owner's four nodes from the six staged tiles.
 __device__ __forceinline__ bool dma_qcrit(DmaTiles& sm, const double* __restrict__ d, int h,
                                           int p, double (&qv)[4], double (&om)[4]) {
   double xr[4], xs[4], xt[4], yr[4], ys[4], yt[4], zr[4], zs[4], zt[4];
-  dma_pass(sm.raw[0], d, sm.S, sm.Tt, h, p, xr, xs, xt);
-  dma_pass(sm.raw[1], d, sm.S, sm.Tt, h, p, yr, ys, yt);
-  dma_pass(sm.raw[2], d, sm.S, sm.Tt, h, p, zr, zs, zt);
+  dma_wait_coords();
+  dma_pass(sm.xyz[0], d, sm.S, sm.Tt, h, p, xr, xs, xt);
+  dma_pass(sm.xyz[1], d, sm.S, sm.Tt, h, p, yr, ys, yt);
+  dma_pass(sm.xyz[2], d, sm.S, sm.Tt, h, p, zr, zs, zt);
   InvJac<double> kk[4];
   bool ok = true;
 #pragma unroll
@@ -658,7 +718,8 @@ __device__ __forceinline__ bool dma_qcrit(DmaTiles& sm, const double* __restrict
     ok = invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii], zt[ii],
                          kk[ii]) && ok;
   double fr[4], fs[4], ft[4], a01[4], a02[4], a12[4];
-  dma_pass(sm.raw[3], d, sm.S, sm.Tt, h, p, fr, fs, ft);
+  dma_wait_all();
+  dma_pass(sm.uvw[0], d, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < 4; ++ii) {
     const InvJac<double>& K = kk[ii];
@@ -667,7 +728,7 @@ __device__ __forceinline__ bool dma_qcrit(DmaTiles& sm, const double* __restrict
     a02[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
     qv[ii] = a00 * a00;
   }
-  dma_pass(sm.raw[4], d, sm.S, sm.Tt, h, p, fr, fs, ft);
+  dma_pass(sm.uvw[1], d, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < 4; ++ii) {
     const InvJac<double>& K = kk[ii];
@@ -678,7 +739,7 @@ __device__ __forceinline__ bool dma_qcrit(DmaTiles& sm, const double* __restrict
     const double w3 = a10 - a01[ii];
     om[ii] = w3 * w3;
   }
-  dma_pass(sm.raw[5], d, sm.S, sm.Tt, h, p, fr, fs, ft);
+  dma_pass(sm.uvw[2], d, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < 4; ++ii) {
     const InvJac<double>& K = kk[ii];
@@ -692,27 +753,16 @@ __device__ __forceinline__ bool dma_qcrit(DmaTiles& sm, const double* __restrict
   return ok;
 }
 
-__device__ __forceinline__ void dma_fetch_element(DmaTiles& sm, const double* x, const double* y,
-                                                  const double* z, const double* u,
-                                                  const double* v, const double* w, int64_t base,
-                                                  int h, int lane) {
-  dma_tile(x + base, sm.raw[0], h, lane);
-  dma_tile(y + base, sm.raw[1], h, lane);
-  dma_tile(z + base, sm.raw[2], h, lane);
-  dma_tile(u + base, sm.raw[3], h, lane);
-  dma_tile(v + base, sm.raw[4], h, lane);
-  dma_tile(w + base, sm.raw[5], h, lane);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-}
-
 __global__ void __launch_bounds__(128)
 qcrit_dma7(const double* __restrict__ dmat, const double* __restrict__ x,
            const double* __restrict__ y, const double* __restrict__ z,
            const double* __restrict__ u, const double* __restrict__ v,
            const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
            double* __restrict__ qmm, int32_t* __restrict__ status) {
-  __shared__ DmaTiles sm;
+  __shared__ double s_xyz[3][512];
+  __shared__ double s_uvw[3][512];
+  __shared__ DmaWork s_work;
+  DmaTiles sm{s_xyz, s_uvw, s_work.S, s_work.Tt, s_work.red};
   const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int p = threadIdx.x & 63;
   const int64_t base = (int64_t)blockIdx.x * 512;
@@ -1315,7 +1365,7 @@ extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__
 // steps and output as extract_pencil; the staged x, y, z tiles serve the
 // vertex interpolation and the u tile (free after its pass) holds Q.
 struct DmaExtractLds {
-  DmaTiles t;
+  DmaWork w;
   int64_t prefix[SEM_MAX_ISO];
   int32_t cnt[SEM_MAX_ISO];
   int32_t wave[4];
@@ -1344,7 +1394,10 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
              int64_t* __restrict__ tri_count, int64_t* __restrict__ active,
              int32_t* __restrict__ status) {
   constexpr int NC = 343, ROUNDS = 3;
+  __shared__ double s_xyz[3][512];
+  __shared__ double s_uvw[3][512];
   __shared__ DmaExtractLds sm;
+  DmaTiles tiles{s_xyz, s_uvw, sm.w.S, sm.w.Tt, sm.w.red};
   const int t = threadIdx.x;
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int p = t & 63;
@@ -1354,11 +1407,11 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
   __syncthreads();
   const int64_t e = sm.e;
   const int64_t base = e * 512;
-  dma_fetch_element(sm.t, x, y, z, u, v, w, base, h, p);
+  dma_fetch_element(tiles, x, y, z, u, v, w, base, h, p);
 
   double qv[4], ov[4];
-  int bad = !dma_qcrit(sm.t, dmat, h, p, qv, ov);
-  double* QT = sm.t.raw[3];
+  int bad = !dma_qcrit(tiles, dmat, h, p, qv, ov);
+  double* QT = s_uvw[0];
   const int j = p & 7, k = p >> 3;
   double mn = pos_inf<double>(), mx = neg_inf<double>();
 #pragma unroll
@@ -1374,7 +1427,7 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
   }
   bad = __syncthreads_or(bad);
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
-  block_minmax<double, 128>(mn, mx, sm.t.red);
+  block_minmax<double, 128>(mn, mx, sm.w.red);
   if (qmm && t == 0) {
     qmm[2 * e] = mn;
     qmm[2 * e + 1] = mx;
@@ -1427,11 +1480,11 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
   // emission; the v tile (free since the Q computation) holds the case and
   // descriptor lists
   static_assert(352 + NC * kMcMaxTri * 2 <= 512 * (int)sizeof(double), "lists fit one tile");
-  uint8_t* cases = reinterpret_cast<uint8_t*>(sm.t.raw[4]);
+  uint8_t* cases = reinterpret_cast<uint8_t*>(s_uvw[1]);
   uint16_t* desc = reinterpret_cast<uint16_t*>(cases + 352);
   for (int s = 0; s < n_iso; ++s) {
     if (sm.cnt[s] == 0) continue;
-    emit_element<7, 128>(iso.v[s], DmaNode{}, QT, sm.t.raw[0], sm.t.raw[1], sm.t.raw[2],
+    emit_element<7, 128>(iso.v[s], DmaNode{}, QT, s_xyz[0], s_xyz[1], s_xyz[2],
                          sm.ntri, sm.tri, cases, desc, sm.wave, out.ptr[s], sm.prefix[s],
                          out.cap[s], (uint64_t*)nullptr, 0);
   }
