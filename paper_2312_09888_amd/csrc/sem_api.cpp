@@ -53,30 +53,19 @@ IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso) {
   return ws;
 }
 
-ExtractWorkspace extract_workspace_layout(void* base, int64_t n_elem, int n_iso) {
-  const int64_t words = (int64_t)n_iso * n_elem;
-  const size_t b_lb = align256((size_t)words * sizeof(uint64_t));
-  ExtractWorkspace ws;
-  char* p = static_cast<char*>(base);
-  ws.lookback = reinterpret_cast<uint64_t*>(p);
-  ws.ticket = reinterpret_cast<uint32_t*>(p ? p + b_lb : nullptr);
-  ws.bytes = b_lb + 256;
-  return ws;
-}
-
 namespace {
 
-// Orders above 7 run Q and the isosurface as separate passes; Q and its
-// element ranges then need storage, taken from the workspace when the
-// caller does not want them.
-struct ExtractFallback {
+// sem_extract counts triangles per element, scans the counts and emits
+// from the stored Q; Q and its element ranges need storage, taken from the
+// workspace when the caller does not want them.
+struct ExtractLayout {
   size_t iso_bytes, q_off, mm_off, bytes;
 };
 
-ExtractFallback extract_fallback_layout(int64_t n_elem, int order, int n_iso, sem_dtype dt) {
+ExtractLayout extract_layout(int64_t n_elem, int order, int n_iso, sem_dtype dt) {
   const size_t esz = dt == SEM_F64 ? sizeof(double) : sizeof(float);
   const size_t p3 = (size_t)(order + 1) * (order + 1) * (order + 1);
-  ExtractFallback f;
+  ExtractLayout f;
   f.iso_bytes = iso_workspace_layout(nullptr, n_elem, n_iso).bytes;
   f.q_off = f.iso_bytes;
   f.mm_off = f.q_off + align256((size_t)n_elem * p3 * esz);
@@ -211,8 +200,7 @@ int sem_qcrit(int64_t n_elem, int order, sem_dtype dt, const void* x, const void
 
 size_t sem_extract_workspace_bytes(int64_t n_elem, int order, int n_iso, sem_dtype dt) {
   if (check_common(n_elem, order, dt) != SEM_OK || n_iso < 1 || n_iso > SEM_MAX_ISO) return 0;
-  if (order <= 7) return extract_workspace_layout(nullptr, n_elem, n_iso).bytes;
-  return extract_fallback_layout(n_elem, order, n_iso, dt).bytes;
+  return extract_layout(n_elem, order, n_iso, dt).bytes;
 }
 
 int sem_extract(int64_t n_elem, int order, sem_dtype dt, const void* x, const void* y,
@@ -240,15 +228,14 @@ int sem_extract(int64_t n_elem, int order, sem_dtype dt, const void* x, const vo
                                      active_cells, nullptr, IsoWorkspace{}, status_word, s);
     return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
   }
-  if (order > 7) {
-    const ExtractFallback f = extract_fallback_layout(n_elem, order, n_iso, dt);
-    char* b = static_cast<char*>(workspace);
-    if (!q) q = b + f.q_off;
-    if (!q_minmax) q_minmax = b + f.mm_off;
-  }
+  const ExtractLayout f = extract_layout(n_elem, order, n_iso, dt);
+  char* b = static_cast<char*>(workspace);
+  if (!q) q = b + f.q_off;
+  if (!q_minmax) q_minmax = b + f.mm_off;
+  const IsoWorkspace ws = iso_workspace_layout(workspace, n_elem, n_iso);
   hipError_t e = launch_extract(order, dt, *tab, n_elem, x, y, z, u, v, w, q, omega_mag,
                                 q_minmax, n_iso, iso_host, tri_xyz, tri_capacity, tri_count,
-                                active_cells, workspace, status_word, s);
+                                active_cells, ws, status_word, s);
   return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
 }
 

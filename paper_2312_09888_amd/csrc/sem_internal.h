@@ -42,15 +42,6 @@ struct IsoOut {
   int per_iso;
 };
 
-// Fused-extraction workspace: one decoupled look-back word per
-// (isovalue, element) and a ticket counter.
-struct ExtractWorkspace {
-  uint64_t* lookback;   // [n_iso * n_elem]
-  uint32_t* ticket;     // [1]
-  size_t bytes;
-};
-ExtractWorkspace extract_workspace_layout(void* base, int64_t n_elem, int n_iso);
-
 // Isosurface workspace layout (offsets in bytes from the workspace start).
 struct IsoWorkspace {
   int32_t* cnt;       // [n_iso * n_elem] triangles per (isovalue, element)
@@ -78,7 +69,7 @@ hipError_t launch_extract(int order, sem_dtype dt, const DeviceTables& tab, int6
                           const void* v, const void* w, void* q, void* om, void* qmm,
                           int n_iso, const double* iso_host, void* const* tri_xyz,
                           const int64_t* tri_capacity, int64_t* tri_count,
-                          int64_t* active_cells, void* workspace, int32_t* status,
+                          int64_t* active_cells, const IsoWorkspace& ws, int32_t* status,
                           hipStream_t s);
 
 hipError_t launch_isosurface(int order, sem_dtype dt, const DeviceTables& tab,

@@ -1116,263 +1116,16 @@ __global__ void fill_i64(int64_t* __restrict__ p, int n, int64_t value) {
 }
 
 // ---------------------------------------------------------------------------
-// fused single-pass extraction (N <= 7): Q, |omega|, isosurfaces of Q
+// N = 7, FP64 extraction: Q + triangle counts, scan, emission
 // ---------------------------------------------------------------------------
 //
-// One workgroup (two waves) per element, in the order of a ticket taken at
-// start.  After the pencil Q computation the element's Q tile and coordinate
-// tiles are in LDS; each isovalue's triangle count is published with a
-// decoupled look-back word (Merrill & Garland 2016): flag AGGREGATE with
-// the element's own count, then INCLUSIVE with the prefix through it once
-// the predecessors' words are known.  Flag and value share one 64-bit word
-// and nothing else is published through it, so relaxed device-scope atomics
-// suffice (an acquire load would invalidate the CU's L1 on every poll).  Tickets make every predecessor a
-// workgroup that has already started, so every wait ends.  The element then
-// emits its triangles at that prefix, in (cell, slot) order.
-
-constexpr uint64_t kLbAggregate = 1ull << 62;
-constexpr uint64_t kLbInclusive = 2ull << 62;
-constexpr uint64_t kLbValue = (1ull << 62) - 1;
-
-__global__ void extract_reset(uint64_t* __restrict__ lookback, int64_t words,
-                              uint32_t* __restrict__ ticket, int64_t* __restrict__ active,
-                              int n_iso) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < words) lookback[i] = 0;
-  if (i == 0) *ticket = 0u;
-  if (active && i < n_iso) active[i] = 0;
-}
-
-constexpr int kLbGroup = 4;    // isovalues per look-back group
-constexpr int kLbDepth = 8;    // 64-predecessor windows per step
-
-__device__ __forceinline__ uint64_t lb_load(const uint64_t* row, int64_t idx) {
-  return idx >= 0 ? __hip_atomic_load(&row[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                  : kLbInclusive;   // before element 0: inclusive prefix 0
-}
-
-// Decoupled look-back of element e for isovalues [s0, s0 + ns), run by one
-// full wave (lane p).  Publishes AGGREGATE, finds the running prefix from
-// the nearest INCLUSIVE word (all words in between must be published),
-// publishes INCLUSIVE and stores the exclusive prefix in prefix[s].
-__device__ __forceinline__ void lookback_group(uint64_t* __restrict__ lookback, int64_t n_elem,
-                                               int64_t e, int s0, int ns,
-                                               const int32_t* cnt, int64_t* prefix, int p) {
-  uint64_t* row[kLbGroup];
-  uint64_t pre[kLbGroup], own[kLbGroup];
-  int64_t top[kLbGroup];
-  bool done[kLbGroup];
-#pragma unroll
-  for (int g = 0; g < kLbGroup; ++g) {
-    const int s = s0 + (g < ns ? g : 0);
-    row[g] = lookback + (int64_t)s * n_elem;
-    own[g] = (uint64_t)cnt[s];
-    pre[g] = 0;
-    top[g] = e - 1;
-    done[g] = g >= ns || e == 0;
-    if (g < ns && p == 0)
-      __hip_atomic_store(&row[g][e], (e == 0 ? kLbInclusive : kLbAggregate) | own[g],
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  while (true) {
-    bool all = true;
-#pragma unroll
-    for (int g = 0; g < kLbGroup; ++g) all = all && done[g];
-    if (all) break;
-    uint64_t wd[kLbGroup][kLbDepth];
-#pragma unroll
-    for (int g = 0; g < kLbGroup; ++g)
-#pragma unroll
-      for (int k = 0; k < kLbDepth; ++k)
-        wd[g][k] = done[g] ? kLbInclusive : lb_load(row[g], top[g] - p - 64 * k);
-    bool waiting = false;
-#pragma unroll
-    for (int g = 0; g < kLbGroup; ++g) {
-      if (done[g]) continue;
-      // nearest inclusive word, window by window
-      uint64_t add = 0;
-      bool ready = true, found = false;
-#pragma unroll
-      for (int k = 0; k < kLbDepth; ++k) {
-        if (found || !ready) continue;
-        const uint64_t flag = wd[g][k] >> 62;
-        const uint64_t inc = __ballot(flag == 2);
-        const uint64_t inv = __ballot(flag == 0);
-        const int first = inc ? __ffsll((unsigned long long)inc) - 1 : 63;
-        const uint64_t upto = first == 63 ? ~0ull : ((2ull << first) - 1ull);
-        if (inv & upto) {
-          ready = false;
-          continue;
-        }
-        add += (uint64_t)p <= (uint64_t)first ? (wd[g][k] & kLbValue) : 0ull;
-        found = inc != 0;
-      }
-      if (!ready) {
-        waiting = true;
-        continue;
-      }
-      pre[g] += wave_sum<uint64_t>(add);
-      if (found) {
-        done[g] = true;
-        if (p == 0)
-          __hip_atomic_store(&row[g][e], kLbInclusive | (pre[g] + own[g]), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        top[g] -= 64 * kLbDepth;
-      }
-    }
-    if (waiting) __builtin_amdgcn_s_sleep(4);
-  }
-  if (p == 0)
-    for (int g = 0; g < ns; ++g) prefix[s0 + g] = (int64_t)pre[g];
-}
-
-template <int N, typename T>
-struct ExtractLds {
-  T X[Pen<N>::SZ];
-  T Y[Pen<N>::SZ];
-  T Z[Pen<N>::SZ];
-  PencilTiles<N, T> pt;
-  int64_t prefix[SEM_MAX_ISO];
-  int32_t cnt[SEM_MAX_ISO];
-  int32_t wave[4];
-  uint8_t ntri[256];
-  int8_t tri[256 * kMcMaxTri * 3];
-  uint32_t e;
-};
-
-template <int N, typename T>
-__global__ void __launch_bounds__(128)
-extract_pencil(int64_t n_elem, const T* __restrict__ dmat, const T* __restrict__ x,
-               const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
-               const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q,
-               T* __restrict__ om, T* __restrict__ qmm, int n_iso, IsoList<T> iso,
-               IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
-               const int8_t* __restrict__ tri_tab, uint64_t* __restrict__ lookback,
-               uint32_t* __restrict__ ticket, int64_t* __restrict__ tri_count,
-               int64_t* __restrict__ active, int32_t* __restrict__ status) {
-  using Q = Pen<N>;
-  constexpr int P = Q::P, H0 = Q::H0, RS = Q::RS, SS = Q::SS;
-  constexpr int NC = N * N * N;
-  constexpr int ROUNDS = (NC + 127) / 128;
-  __shared__ ExtractLds<N, T> sm;
-  const int t = threadIdx.x;
-  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int p = t & 63;
-  if (t == 0) sm.e = atomicAdd(ticket, 1u);
-  for (int k = t; k < 256; k += 128) sm.ntri[k] = ntri_tab[k];
-  for (int k = t; k < 256 * kMcMaxTri * 3; k += 128) sm.tri[k] = tri_tab[k];
-  __syncthreads();
-  const int64_t e = sm.e;
-  const int64_t base = e * (P * P * P);
-
-  // Q and |omega| (the coordinate tiles stay in LDS for the vertices)
-  T qv[H0], ov[H0];
-  int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
-                             sm.pt, sm.X, sm.Y, sm.Z, h, p, qv, ov);
-  T* QT = sm.pt.F;  // free after the last pass: holds the Q tile from here on
-  T mn = pos_inf<T>(), mx = neg_inf<T>();
-  if (p < Q::NP) {
-    const int j = p % P, k = p / P;
-#pragma unroll
-    for (int ii = 0; ii < H0; ++ii) {
-      const int i = h * H0 + ii;
-      if (i < P) {
-        const int64_t o = base + (k * P + j) * P + i;
-        if (q) q[o] = qv[ii];
-        if (om) om[o] = ov[ii];
-        QT[Q::at(i, j, k)] = qv[ii];
-        const T c = qv[ii] != qv[ii] ? neg_inf<T>() : qv[ii];
-        mn = c < mn ? c : mn;
-        mx = c > mx ? c : mx;
-      }
-    }
-  } else {
-    bad = 0;
-  }
-  bad = __syncthreads_or(bad);
-  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
-  block_minmax<T, 128>(mn, mx, sm.pt.red);
-  if (qmm && t == 0) {
-    qmm[2 * e] = mn;
-    qmm[2 * e + 1] = mx;
-  }
-
-  // triangles and active cells of this element, per isovalue
-  for (int s = 0; s < n_iso; ++s) {
-    const T c = iso.v[s];
-    int nt = 0, act = 0;
-    if ((mx > c) && !(mn > c)) {
-#pragma unroll
-      for (int r = 0; r < ROUNDS; ++r) {
-        const int cell = r * 128 + t;
-        if (cell < NC) {
-          const int ci = cell % N, cj = (cell / N) % N, ck = cell / (N * N);
-          const int cs = cell_case_strided<RS, SS>(QT, Q::at(ci, cj, ck), c);
-          nt += sm.ntri[cs];
-          act += (cs != 0 && cs != 255);
-        }
-      }
-    }
-    nt = wave_sum(nt);
-    act = wave_sum(act);
-    if (p == 0) {
-      sm.wave[h] = nt;
-      sm.wave[2 + h] = act;
-    }
-    __syncthreads();
-    if (t == 0) {
-      sm.cnt[s] = sm.wave[0] + sm.wave[1];
-      const int a = sm.wave[2] + sm.wave[3];
-      if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
-    }
-    __syncthreads();
-  }
-
-  // decoupled look-back (wave 0): every step reads the words of 128
-  // predecessors for up to kLbGroup isovalues at once, so one device-scope
-  // round trip advances all of them
-  if (h == 0) {
-    for (int s0 = 0; s0 < n_iso; s0 += kLbGroup) {
-      const int ns = n_iso - s0 < kLbGroup ? n_iso - s0 : kLbGroup;
-      lookback_group(lookback, n_elem, e, s0, ns, sm.cnt, sm.prefix, p);
-    }
-    if (p == 0 && e == n_elem - 1) {
-      for (int s = 0; s < n_iso; ++s) {
-        const int64_t tot = sm.prefix[s] + sm.cnt[s];
-        tri_count[s] = tot;
-        if (status && tot > out.cap[s]) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
-      }
-    }
-  }
-  __syncthreads();
-
-  // emission in (cell, slot) order at the element's offset; the s- and
-  // t-transpose tiles are free now and hold the case / descriptor lists
-  static_assert(((NC + 15) & ~15) + NC * kMcMaxTri * 2 <= 2 * Q::SZ * (int)sizeof(T),
-                "case and descriptor lists must fit in the transpose tiles");
-  uint8_t* cases = reinterpret_cast<uint8_t*>(sm.pt.S);
-  uint16_t* desc = reinterpret_cast<uint16_t*>(cases + ((NC + 15) & ~15));
-  for (int s = 0; s < n_iso; ++s) {
-    if (sm.cnt[s] == 0) continue;
-    emit_element<N, 128>(iso.v[s], StridedNode<RS, SS>{}, QT, sm.X, sm.Y, sm.Z, sm.ntri,
-                         sm.tri, cases, desc, sm.wave, out.ptr[s], sm.prefix[s], out.cap[s],
-                         (uint64_t*)nullptr, 0);
-  }
-}
-
-// Fused extraction for N = 7, FP64, on the direct-load tile layout.  Same
-// steps and output as extract_pencil; the staged x, y, z tiles serve the
-// vertex interpolation and the u tile (free after its pass) holds Q.
-struct DmaExtractLds {
-  DmaWork w;
-  int64_t prefix[SEM_MAX_ISO];
-  int32_t cnt[SEM_MAX_ISO];
-  int32_t wave[4];
-  uint8_t ntri[256];
-  int8_t tri[256 * kMcMaxTri * 3];
-  uint32_t e;
-};
+// qcount_dma7 computes Q and |omega| from the six staged tiles, keeps Q in
+// LDS and counts every isovalue's triangles and active cells per element.
+// The counts then go through the device-wide exclusive scan, and emit_dma7
+// re-stages the Q and coordinate tiles of the elements that have triangles
+// and writes them at their offsets.  (A single pass with a decoupled
+// look-back saves that re-read, but on MI355X its chain of device-scope
+// polls across the eight XCDs cost more than the re-read does.)
 
 __device__ __forceinline__ int dma_cell_case(const double* __restrict__ qt, int ci, int cj,
                                              int ck, double c) {
@@ -1384,34 +1137,32 @@ __device__ __forceinline__ int dma_cell_case(const double* __restrict__ qt, int 
 }
 
 __global__ void __launch_bounds__(128)
-extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __restrict__ x,
-             const double* __restrict__ y, const double* __restrict__ z,
-             const double* __restrict__ u, const double* __restrict__ v,
-             const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
-             double* __restrict__ qmm, int n_iso, IsoList<double> iso, IsoOut<double> out,
-             const uint8_t* __restrict__ ntri_tab, const int8_t* __restrict__ tri_tab,
-             uint64_t* __restrict__ lookback, uint32_t* __restrict__ ticket,
-             int64_t* __restrict__ tri_count, int64_t* __restrict__ active,
-             int32_t* __restrict__ status) {
+qcount_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __restrict__ x,
+            const double* __restrict__ y, const double* __restrict__ z,
+            const double* __restrict__ u, const double* __restrict__ v,
+            const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
+            double* __restrict__ qmm, int n_iso, IsoList<double> iso,
+            const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
+            int64_t* __restrict__ active, int32_t* __restrict__ status) {
   constexpr int NC = 343, ROUNDS = 3;
   __shared__ double s_xyz[3][512];
   __shared__ double s_uvw[3][512];
-  __shared__ DmaExtractLds sm;
-  DmaTiles tiles{s_xyz, s_uvw, sm.w.S, sm.w.Tt, sm.w.red};
+  __shared__ DmaWork s_work;
+  __shared__ uint8_t s_ntri[256];
+  __shared__ int32_t s_wave[4];
+  DmaTiles sm{s_xyz, s_uvw, s_work.S, s_work.Tt, s_work.red};
   const int t = threadIdx.x;
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int p = t & 63;
-  if (t == 0) sm.e = atomicAdd(ticket, 1u);
-  for (int k = t; k < 256; k += 128) sm.ntri[k] = ntri_tab[k];
-  for (int k = t; k < 256 * kMcMaxTri * 3; k += 128) sm.tri[k] = tri_tab[k];
-  __syncthreads();
-  const int64_t e = sm.e;
+  const int64_t e = blockIdx.x;
   const int64_t base = e * 512;
-  dma_fetch_element(tiles, x, y, z, u, v, w, base, h, p);
+  dma_fetch_element(sm, x, y, z, u, v, w, base, h, p);
+  s_ntri[t] = ntri_tab[t];
+  s_ntri[t + 128] = ntri_tab[t + 128];
 
   double qv[4], ov[4];
-  int bad = !dma_qcrit(tiles, dmat, h, p, qv, ov);
-  double* QT = s_uvw[0];
+  int bad = !dma_qcrit(sm, dmat, h, p, qv, ov);
+  double* QT = s_uvw[0];   // free after the u pass
   const int j = p & 7, k = p >> 3;
   double mn = pos_inf<double>(), mx = neg_inf<double>();
 #pragma unroll
@@ -1427,12 +1178,11 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
   }
   bad = __syncthreads_or(bad);
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
-  block_minmax<double, 128>(mn, mx, sm.w.red);
+  block_minmax<double, 128>(mn, mx, s_work.red);
   if (qmm && t == 0) {
     qmm[2 * e] = mn;
     qmm[2 * e + 1] = mx;
   }
-
   for (int s = 0; s < n_iso; ++s) {
     const double c = iso.v[s];
     int nt = 0, act = 0;
@@ -1442,7 +1192,7 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
         const int cell = r * 128 + t;
         if (cell < NC) {
           const int cs = dma_cell_case(QT, cell % 7, (cell / 7) % 7, cell / 49, c);
-          nt += sm.ntri[cs];
+          nt += s_ntri[cs];
           act += (cs != 0 && cs != 255);
         }
       }
@@ -1450,43 +1200,66 @@ extract_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __re
     nt = wave_sum(nt);
     act = wave_sum(act);
     if (p == 0) {
-      sm.wave[h] = nt;
-      sm.wave[2 + h] = act;
+      s_wave[h] = nt;
+      s_wave[2 + h] = act;
     }
     __syncthreads();
     if (t == 0) {
-      sm.cnt[s] = sm.wave[0] + sm.wave[1];
-      const int a = sm.wave[2] + sm.wave[3];
+      cnt[(int64_t)s * n_elem + e] = s_wave[0] + s_wave[1];
+      const int a = s_wave[2] + s_wave[3];
       if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
     }
     __syncthreads();
   }
+}
 
-  if (h == 0) {
-    for (int s0 = 0; s0 < n_iso; s0 += kLbGroup) {
-      const int ns = n_iso - s0 < kLbGroup ? n_iso - s0 : kLbGroup;
-      lookback_group(lookback, n_elem, e, s0, ns, sm.cnt, sm.prefix, p);
-    }
-    if (p == 0 && e == n_elem - 1) {
-      for (int s = 0; s < n_iso; ++s) {
-        const int64_t tot = sm.prefix[s] + sm.cnt[s];
-        tri_count[s] = tot;
-        if (status && tot > out.cap[s]) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
-      }
-    }
-  }
-  __syncthreads();
-
-  // emission; the v tile (free since the Q computation) holds the case and
-  // descriptor lists
-  static_assert(352 + NC * kMcMaxTri * 2 <= 512 * (int)sizeof(double), "lists fit one tile");
-  uint8_t* cases = reinterpret_cast<uint8_t*>(s_uvw[1]);
-  uint16_t* desc = reinterpret_cast<uint16_t*>(cases + 352);
+// Emission for N = 7, FP64: elements with triangles stage their field and
+// coordinate tiles with direct loads and emit through emit_element.
+__global__ void __launch_bounds__(128)
+emit_dma7(int64_t n_elem, const double* __restrict__ x, const double* __restrict__ y,
+          const double* __restrict__ z, const double* __restrict__ field, int n_iso,
+          IsoList<double> iso, IsoOut<double> out, const uint8_t* __restrict__ ntri_tab,
+          const int8_t* __restrict__ tri_tab, const int32_t* __restrict__ cnt,
+          const int64_t* __restrict__ offs, uint64_t* __restrict__ keys) {
+  constexpr int NC = 343;
+  __shared__ double s_f[512];
+  __shared__ double s_x[512];
+  __shared__ double s_y[512];
+  __shared__ double s_z[512];
+  __shared__ uint8_t s_ntri[256];
+  __shared__ int8_t s_tri[256 * kMcMaxTri * 3];
+  __shared__ uint8_t s_case[NC];
+  __shared__ uint16_t s_desc[NC * kMcMaxTri];
+  __shared__ int32_t s_wave[2];
+  const int t = threadIdx.x;
+  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int p = t & 63;
+  const int64_t e = blockIdx.x;
+  bool any = false;
+  for (int s = 0; s < n_iso; ++s) any = any || cnt[(int64_t)s * n_elem + e] > 0;
+  if (!any) return;
+  const int64_t base = e * 512;
+  dma_tile(field + base, s_f, h, p);
+  dma_tile(x + base, s_x, h, p);
+  dma_tile(y + base, s_y, h, p);
+  dma_tile(z + base, s_z, h, p);
+  for (int q = t; q < 256; q += 128) s_ntri[q] = ntri_tab[q];
+  for (int q = t; q < 256 * kMcMaxTri * 3; q += 128) s_tri[q] = tri_tab[q];
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
+  barrier_after_wait();
   for (int s = 0; s < n_iso; ++s) {
-    if (sm.cnt[s] == 0) continue;
-    emit_element<7, 128>(iso.v[s], DmaNode{}, QT, s_xyz[0], s_xyz[1], s_xyz[2],
-                         sm.ntri, sm.tri, cases, desc, sm.wave, out.ptr[s], sm.prefix[s],
-                         out.cap[s], (uint64_t*)nullptr, 0);
+    const int64_t flat = (int64_t)s * n_elem + e;
+    if (cnt[flat] == 0) continue;
+    int64_t g = offs[flat];
+    double* dst = out.ptr[0];
+    int64_t cap = out.cap[0];
+    if (out.per_iso) {
+      g -= offs[(int64_t)s * n_elem];
+      dst = out.ptr[s];
+      cap = out.cap[s];
+    }
+    emit_element<7, 128>(iso.v[s], DmaNode{}, s_f, s_x, s_y, s_z, s_ntri, s_tri, s_case, s_desc,
+                         s_wave, dst, g, cap, out.per_iso ? nullptr : keys, base);
   }
 }
 
@@ -1569,23 +1342,15 @@ IsoList<T> make_isolist(int n_iso, const double* iso_host) {
   return iso;
 }
 
-// Two-pass isosurface: count, exclusive scan, emit (any supported order).
+// Scan of the per-(isovalue, element) counts, totals, then emission.
 template <typename T>
-hipError_t iso_pipeline(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
-                        const void* y, const void* z, const void* field, const void* mm,
-                        int n_iso, const double* iso_host, const IsoOut<T>& out,
-                        uint64_t* keys, int64_t* tri_count, int64_t* active,
-                        uint8_t* case_idx, const IsoWorkspace& ws, int32_t* status,
-                        hipStream_t s) {
-  const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
-  if (active) hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
+hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
+                         const void* y, const void* z, const void* field, int n_iso,
+                         const IsoList<T>& iso, const IsoOut<T>& out, uint64_t* keys,
+                         int64_t* tri_count, const IsoWorkspace& ws, int32_t* status,
+                         hipStream_t s) {
   const int64_t count = (int64_t)n_iso * n_elem;
   const int64_t nb = scan_blocks(count);
-  SEM_ORDER_SWITCH(order, {
-    hipLaunchKernelGGL((iso_count<N, T>), dim3((unsigned)n_elem),
-                       dim3(Shape<N>::kCellThreads), 0, s, n_elem, (const T*)field,
-                       (const T*)mm, n_iso, iso, tab.ntri, ws.cnt, active, case_idx);
-  });
   hipLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.cnt, count,
                      ws.partial);
   hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, ws.partial, nb);
@@ -1595,15 +1360,40 @@ hipError_t iso_pipeline(int order, const DeviceTables& tab, int64_t n_elem, cons
                      tri_count, out, status);
   bool any_cap = false;
   for (int q = 0; q < (out.per_iso ? n_iso : 1); ++q) any_cap = any_cap || out.cap[q] > 0;
-  if (any_cap) {
-    SEM_ORDER_SWITCH(order, {
-      hipLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem),
-                         dim3(Shape<N>::kCellThreads), 0, s, n_elem, (const T*)x,
-                         (const T*)y, (const T*)z, (const T*)field, n_iso, iso, tab.ntri,
-                         tab.tri, ws.cnt, ws.offs, out, keys);
-    });
+  if (!any_cap) return hipGetLastError();
+  if constexpr (std::is_same<T, double>::value) {
+    if (order == 7) {
+      hipLaunchKernelGGL(emit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, n_elem,
+                         (const T*)x, (const T*)y, (const T*)z, (const T*)field, n_iso, iso, out,
+                         tab.ntri, tab.tri, ws.cnt, ws.offs, keys);
+      return hipGetLastError();
+    }
   }
+  SEM_ORDER_SWITCH(order, {
+    hipLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem), dim3(Shape<N>::kCellThreads),
+                       0, s, n_elem, (const T*)x, (const T*)y, (const T*)z, (const T*)field,
+                       n_iso, iso, tab.ntri, tab.tri, ws.cnt, ws.offs, out, keys);
+  });
   return hipGetLastError();
+}
+
+// Two-pass isosurface of a given field: count, exclusive scan, emit.
+template <typename T>
+hipError_t iso_pipeline(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
+                        const void* y, const void* z, const void* field, const void* mm,
+                        int n_iso, const double* iso_host, const IsoOut<T>& out,
+                        uint64_t* keys, int64_t* tri_count, int64_t* active,
+                        uint8_t* case_idx, const IsoWorkspace& ws, int32_t* status,
+                        hipStream_t s) {
+  const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
+  if (active) hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
+  SEM_ORDER_SWITCH(order, {
+    hipLaunchKernelGGL((iso_count<N, T>), dim3((unsigned)n_elem),
+                       dim3(Shape<N>::kCellThreads), 0, s, n_elem, (const T*)field,
+                       (const T*)mm, n_iso, iso, tab.ntri, ws.cnt, active, case_idx);
+  });
+  return iso_scan_emit<T>(order, tab, n_elem, x, y, z, field, n_iso, iso, out, keys, tri_count,
+                          ws, status, s);
 }
 
 template <typename T>
@@ -1620,13 +1410,15 @@ hipError_t iso_t(int order, const DeviceTables& tab, int64_t n_elem, const void*
                          tri_count, active, case_idx, ws, status, s);
 }
 
+// sem_extract: q and qmm always point at storage (the caller's or the
+// workspace's); `ws` is the isosurface part of the workspace.
 template <typename T>
 hipError_t extract_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
                      const void* y, const void* z, const void* u, const void* v,
                      const void* w, void* q, void* om, void* qmm, int n_iso,
                      const double* iso_host, void* const* tri_xyz, const int64_t* cap,
-                     int64_t* tri_count, int64_t* active, void* workspace, int32_t* status,
-                     hipStream_t s) {
+                     int64_t* tri_count, int64_t* active, const IsoWorkspace& ws,
+                     int32_t* status, hipStream_t s) {
   IsoOut<T> out{};
   for (int k = 0; k < n_iso; ++k) {
     out.ptr[k] = static_cast<T*>(tri_xyz[k]);
@@ -1635,38 +1427,21 @@ hipError_t extract_t(int order, const DeviceTables& tab, int64_t n_elem, const v
   out.per_iso = 1;
   const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
   const T* d = dmat_of<T>(tab, order);
-  if (order <= 7) {
-    const ExtractWorkspace ws = extract_workspace_layout(workspace, n_elem, n_iso);
-    const int64_t words = (int64_t)n_iso * n_elem;
-    hipLaunchKernelGGL(extract_reset, dim3((unsigned)((words + 255) / 256 + 1)), dim3(256), 0,
-                       s, ws.lookback, words, ws.ticket, active, n_iso);
-    if constexpr (std::is_same<T, double>::value) {
-      if (order == 7) {
-        hipLaunchKernelGGL(extract_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, n_elem, d,
-                           (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
-                           (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso, iso, out, tab.ntri,
-                           tab.tri, ws.lookback, ws.ticket, tri_count, active, status);
-        return hipGetLastError();
-      }
+  if constexpr (std::is_same<T, double>::value) {
+    if (order == 7) {
+      if (active)
+        hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
+      hipLaunchKernelGGL(qcount_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, n_elem, d,
+                         (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
+                         (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso, iso, tab.ntri, ws.cnt,
+                         active, status);
+      return iso_scan_emit<T>(order, tab, n_elem, x, y, z, q, n_iso, iso, out, nullptr,
+                              tri_count, ws, status, s);
     }
-    SEM_ORDER_SWITCH(order, {
-      if constexpr (N <= 7) {
-        hipLaunchKernelGGL((extract_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
-                           n_elem, d, (const T*)x, (const T*)y, (const T*)z, (const T*)u,
-                           (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso, iso, out,
-                           tab.ntri, tab.tri, ws.lookback, ws.ticket, tri_count, active,
-                           status);
-      }
-    });
-    return hipGetLastError();
   }
-  // higher orders: Q by the tile kernel, then the two-pass isosurface
-  const IsoWorkspace ws = iso_workspace_layout(workspace, n_elem, n_iso);
-  T* qq = static_cast<T*>(q);
-  T* mmq = static_cast<T*>(qmm);
-  hipError_t err = qcrit_t<T>(order, tab, n_elem, x, y, z, u, v, w, qq, om, mmq, status, s);
+  hipError_t err = qcrit_t<T>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, status, s);
   if (err != hipSuccess) return err;
-  return iso_pipeline<T>(order, tab, n_elem, x, y, z, qq, mmq, n_iso, iso_host, out, nullptr,
+  return iso_pipeline<T>(order, tab, n_elem, x, y, z, q, qmm, n_iso, iso_host, out, nullptr,
                          tri_count, active, nullptr, ws, status, s);
 }
 
@@ -1695,15 +1470,15 @@ hipError_t launch_extract(int order, sem_dtype dt, const DeviceTables& tab, int6
                           const void* v, const void* w, void* q, void* om, void* qmm,
                           int n_iso, const double* iso_host, void* const* tri_xyz,
                           const int64_t* tri_capacity, int64_t* tri_count,
-                          int64_t* active_cells, void* workspace, int32_t* status,
+                          int64_t* active_cells, const IsoWorkspace& ws, int32_t* status,
                           hipStream_t s) {
   return dt == SEM_F64
              ? extract_t<double>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
-                                 iso_host, tri_xyz, tri_capacity, tri_count, active_cells,
-                                 workspace, status, s)
+                                 iso_host, tri_xyz, tri_capacity, tri_count, active_cells, ws,
+                                 status, s)
              : extract_t<float>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
-                                iso_host, tri_xyz, tri_capacity, tri_count, active_cells,
-                                workspace, status, s);
+                                iso_host, tri_xyz, tri_capacity, tri_count, active_cells, ws,
+                                status, s);
 }
 
 hipError_t launch_isosurface(int order, sem_dtype dt, const DeviceTables& tab, int64_t n_elem,

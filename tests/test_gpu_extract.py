@@ -1,4 +1,4 @@
-"""GPU parity of the fused single-pass sem_extract.
+"""GPU parity of sem_extract (Q, |omega| and isosurfaces of Q in one call).
 
 Its triangles per isovalue must equal, bit for bit, isovalue s of
 sem_isosurface applied to sem_qcrit's Q (same kernels' arithmetic), and
