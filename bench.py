@@ -11,9 +11,17 @@ parabolic mean plus a seeded random-phase k^-5/3 velocity field -- with Q
 isosurfaces at the 90th, 95th and 99th percentiles of Q.
 
 Prints ONE JSON line.  `roofline` describes the dominant kernel (its
-average duration measured with HIP events on the launch stream);
+average duration measured with HIP events that the library records on the
+launch stream around each kernel phase, over the timed steps);
 `cpu_baseline` times the CPU FP64 oracle on a bounded sample of the same
 snapshot.  One GPU only: --gpus above 1 exits with a message.
+
+Two helper modes turn rocprofv3 CSV output into the committed summaries:
+  --summarize-trace DIR OUT   kernel-trace statistics (run_kernel_stats.csv)
+  --summarize-pmc FETCH_DIR WRITE_DIR OUT
+                              FETCH_SIZE / WRITE_SIZE runs of
+                              `bench.py --copy-calibration`, scaled by what the
+                              counters read for the 1 GiB calibration copy.
 """
 
 import argparse
@@ -27,8 +35,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "extract_channel65536_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2312_09888_amd", "csrc", "sem_kernels.hip")
+CALIBRATION_BYTES = 1 << 30
+
+
+def traffic_file(kernel, dtype):
+    return os.path.join(ROOT, "profiles", f"{kernel}_channel65536_{dtype}_traffic.json")
+
+
+# kernel that runs the Q phase of sem_extract for order 7
+def q_kernel_name(dtype):
+    return "qcount_dma7" if dtype == "f64" else "qcrit_pencil<7,float>"
 
 
 def parse():
@@ -44,6 +61,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (a kernel of "
                          "known HBM traffic for scaling profiler byte counters)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "OUT"))
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
+    ap.add_argument("--command", default="",
+                    help="command line recorded in a summary (with --summarize-*)")
     return ap.parse_args()
 
 
@@ -57,11 +78,11 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(n_launch_points):
+def measured_traffic(kernel, dtype, n_launch_points):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, or None
     when the kernel source changed after the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(kernel, dtype)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -80,6 +101,12 @@ def load_isovalues():
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace, args.command)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -152,23 +179,16 @@ def main():
     torch.cuda.synchronize()
     log(args, f"warmup {args.warmup} steps done")
 
-    evs = []
-    torch.cuda.synchronize()
+    # timed steps (the headline figure)
     t_begin = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t_begin.record()
     for _ in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
         step()
-        e1.record()
-        evs.append((e0, e1))
     t_end.record()
     torch.cuda.synchronize()
-    total_ms = t_begin.elapsed_time(t_end)
-    ms_step = total_ms / args.steps
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms_step = t_begin.elapsed_time(t_end) / args.steps
     flags = int(status.item())
     if flags:
         print(f"device status flags set: {flags}", file=sys.stderr)
@@ -176,8 +196,27 @@ def main():
     if cnt.cpu().tolist() != counts:
         print("triangle counts changed between steps", file=sys.stderr)
         sys.exit(1)
-    log(args, f"timed {args.steps} steps: {ms_step:.4f} ms/step "
-              f"(sem_extract launch average {k_ms:.4f} ms)")
+    log(args, f"timed {args.steps} steps: {ms_step:.4f} ms/step")
+
+    # the same steps again with kernel-phase timing: the library launches
+    # each phase's kernels with HIP events stamped from their dispatch
+    # timestamps, on the launch stream.  The stamping leaves short gaps
+    # between kernels, so these steps are not the headline figure.
+    torch.cuda.synchronize()
+    sem.timing_begin(4 * args.steps + 16)
+    t_begin.record()
+    for _ in range(args.steps):
+        step()
+    t_end.record()
+    torch.cuda.synchronize()
+    phases, dropped = sem.timing_end()
+    ms_phased = t_begin.elapsed_time(t_end) / args.steps
+    if dropped:
+        print(f"phase timing dropped {dropped} spans", file=sys.stderr)
+        sys.exit(1)
+    phase_ms = {k: (ms / c if c else 0.0) for k, (ms, c) in phases.items()}
+    log(args, f"with phase timing: {ms_phased:.4f} ms/step; per-phase averages "
+              + ", ".join(f"{k} {v:.4f} ms" for k, v in phase_ms.items() if v))
 
     # the same path as two calls (sem_qcrit, then sem_isosurface), for comparison
     iws = torch.empty(sem.workspace_bytes(n_elem, n, k_iso), dtype=torch.uint8, device=devn)
@@ -200,14 +239,18 @@ def main():
     log(args, f"two-call path: sem_qcrit {qc_ms:.4f} ms + sem_isosurface {iso_ms:.4f} ms")
 
     esz = 8 if args.dtype == "f64" else 4
-    # algorithmic bytes of one fused launch: read x,y,z,u,v,w, write Q,
-    # |omega|, the per-element (min, max) and 9 coordinates per triangle
-    k_bytes = points * 8 * esz + n_elem * 2 * esz + total_tri * 9 * esz
+    # dominant kernel: the Q phase of sem_extract.  Algorithmic bytes of one
+    # launch: read x, y, z, u, v, w; write Q and |omega| at every point, the
+    # (min, max) of Q per element and (fused for order 7 FP64) one int32
+    # triangle count per (isovalue, element).
+    kname = q_kernel_name(args.dtype)
+    k_ms = phase_ms["qcrit"]
+    k_bytes = points * 8 * esz + n_elem * 2 * esz + (k_iso * n_elem * 4 if esz == 8 else 0)
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
-    traffic = measured_traffic(points)
+    traffic = measured_traffic(kname, args.dtype, points)
     roof = {
         "bound": "hbm",
-        "kernel": f"extract_pencil<7,{'double' if esz == 8 else 'float'}>",
+        "kernel": kname,
         "achieved": round(k_gbs, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
@@ -215,6 +258,7 @@ def main():
         "traffic": traffic,
         "avg_ms": round(k_ms, 5),
         "algorithmic_bytes_per_launch": k_bytes,
+        "dominant": max(phase_ms, key=phase_ms.get) == "qcrit",
     }
     result = {
         "metric": "GLL points/sec through Q-criterion+isosurface, % HBM roofline, plain vs mixed",
@@ -237,6 +281,8 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": roof,
+        "phase_ms": {k: round(v, 5) for k, v in phase_ms.items() if v},
+        "ms_per_step_with_phase_timing": round(ms_phased, 5),
         "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
     }
 
@@ -274,6 +320,90 @@ def cpu_baseline(args, fields, isos, n, n_elem):
             "sample": f"{k} random elements of the same snapshot ({pts} points), "
                       f"FP64 numpy oracle, Q + |omega| + {len(isos)} isosurfaces, "
                       f"{dt_s:.2f} s"}
+
+
+def _csv(directory, suffix):
+    import csv
+    import glob
+    found = sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True))
+    if not found:
+        sys.exit(f"no *{suffix} under {directory}")
+    with open(found[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name):
+    name = name.replace("sem::(anonymous namespace)::", "")
+    return name.split("(")[0] if not name.startswith("void ") else name[5:].split("(")[0]
+
+
+def summarize_trace(directory, out, command):
+    """Text table of a rocprofv3 --kernel-trace --stats run (library kernels,
+    the copy kernel; torch's input-generation kernels summed in one line)."""
+    rows = _csv(directory, "kernel_stats.csv")
+    lines = [f"{'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>9}  kernel"]
+    other = [0, 0.0]
+    for r in rows:
+        name = r["Name"]
+        if "at::native" in name:
+            other[0] += int(r["Calls"])
+            other[1] += float(r["TotalDurationNs"]) / 1e6
+            continue
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                     f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:9.3f}  {_short(name)}")
+    lines.append(f"{other[0]:6d} {'':10} {'':10} {'':10} {other[1]:9.3f}  "
+                 "(torch kernels: synthetic input generation)")
+    with open(out, "w") as fh:
+        fh.write(f"# rocprofv3 kernel trace, MI355X\n# command: {command}\n"
+                 f"# kernel source sha256: {kernel_sha()}\n\n" + "\n".join(lines) + "\n")
+    print(open(out).read())
+
+
+def summarize_pmc(fetch_dir, write_dir, out, command):
+    """HBM bytes per dispatch of the Q kernel from FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the counter reads for the 1 GiB
+    calibration copy of the same run (a plain copy kernel of known traffic).
+    Writes the JSON `measured_traffic` reads."""
+    import numpy as np
+    res = {}
+    for counter, directory in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = {}
+        for r in _csv(directory, "counter_collection.csv"):
+            if r["Counter_Name"] != counter:
+                continue
+            per.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        copies = [v for v in per.get("__amd_rocclr_copyBuffer", []) if v > 1024.0]
+        scale = CALIBRATION_BYTES / (sum(copies) * 1024.0)
+        res[counter] = (per, scale)
+    dtype = "f64" if "f64" in os.path.basename(out) else "f32"
+    kname = q_kernel_name(dtype)
+    fetch = float(np.mean(res["FETCH_SIZE"][0][kname]))
+    write = float(np.mean(res["WRITE_SIZE"][0][kname]))
+    fs, wsc = res["FETCH_SIZE"][1], res["WRITE_SIZE"][1]
+    rec = {
+        "kernel": kname,
+        "workload": "channel 65,536 order-7 elements, 3 Q isovalues, " + dtype,
+        "kernel_src_sha256": kernel_sha(),
+        "points_per_launch": 65536 * 512,
+        "dispatches": len(res["FETCH_SIZE"][0][kname]),
+        "fetch_kib_per_dispatch": fetch,
+        "write_kib_per_dispatch": write,
+        "fetch_scale": round(fs, 4),
+        "write_scale": round(wsc, 4),
+        "hbm_read_bytes_per_launch": int(fetch * 1024 * fs),
+        "hbm_write_bytes_per_launch": int(write * 1024 * wsc),
+        "hbm_bytes_per_launch": int(fetch * 1024 * fs + write * 1024 * wsc),
+        "command": command,
+        "other_kernels_kib_per_dispatch": {
+            k: {"fetch": float(np.mean(v)),
+                "write": float(np.mean(res["WRITE_SIZE"][0].get(k, [0.0])))}
+            for k, v in res["FETCH_SIZE"][0].items() if "at::native" not in k},
+    }
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec, indent=1))
 
 
 if __name__ == "__main__":

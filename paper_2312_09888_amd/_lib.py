@@ -22,11 +22,14 @@ SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW = 1, 2
 SEM_MIN_ORDER, SEM_MAX_ORDER = 1, 9
 SEM_MAX_ISO = 64
 SEM_MC_MAX_TRI = 5
+SEM_PHASE_QCRIT, SEM_PHASE_COUNT, SEM_PHASE_SCAN, SEM_PHASE_EMIT = 0, 1, 2, 3
+SEM_NUM_PHASES = 4
 
 EXPORTS = (
     "sem_status_str", "sem_gll", "sem_mc_table", "sem_init", "sem_finalize",
     "sem_derivs", "sem_qcrit", "sem_isosurface_workspace_bytes", "sem_isosurface",
     "sem_extract_workspace_bytes", "sem_extract",
+    "sem_phase_name", "sem_timing_begin", "sem_timing_end",
 )
 
 
@@ -75,6 +78,12 @@ def lib():
         L.sem_extract.restype = i32
         L.sem_extract.argtypes = ([i64, i32, i32] + [vp] * 9 + [i32, vp, vp, vp, vp, vp,
                                                                 vp, ctypes.c_size_t, vp, vp])
+        L.sem_phase_name.restype = ctypes.c_char_p
+        L.sem_phase_name.argtypes = [i32]
+        L.sem_timing_begin.restype = i32
+        L.sem_timing_begin.argtypes = [i32]
+        L.sem_timing_end.restype = i64
+        L.sem_timing_end.argtypes = [vp, vp, i32]
         del dbl
         _lib = L
     return _lib
@@ -373,3 +382,29 @@ def extract(x, y, z, u, v, w, isovalues, status=None, want_fields=True):
                  active=act, status=status)
     return {"q": q, "omega_mag": om, "minmax": mm, "tri": tris, "tri_count": cnt,
             "active": act}
+
+
+# ---------------------------------------------------------------------------
+# kernel-phase timing
+# ---------------------------------------------------------------------------
+
+def phase_name(phase):
+    return lib().sem_phase_name(int(phase)).decode()
+
+
+def timing_begin(max_spans=4096):
+    """Start recording HIP events around every kernel phase of later calls on
+    the current device (sem_timing_begin)."""
+    init()
+    _check(lib().sem_timing_begin(int(max_spans)), "sem_timing_begin")
+
+
+def timing_end():
+    """Stop timing; returns ({phase name: (total ms, spans)}, dropped spans)."""
+    tot = np.zeros(SEM_NUM_PHASES)
+    cnt = np.zeros(SEM_NUM_PHASES, dtype=np.int64)
+    rc = lib().sem_timing_end(tot.ctypes.data, cnt.ctypes.data, SEM_NUM_PHASES)
+    if rc < 0:
+        raise SemError(int(rc), "sem_timing_end")
+    return ({phase_name(k): (float(tot[k]), int(cnt[k])) for k in range(SEM_NUM_PHASES)},
+            int(rc))

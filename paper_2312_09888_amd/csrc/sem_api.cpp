@@ -30,6 +30,21 @@ const DeviceTables* current_tables() {
   return g_dev[dev].ready ? &g_dev[dev].tab : nullptr;
 }
 
+// Kernel-phase timing of one device: a pool of events handed out in order,
+// and the (phase, start event, end event) of every timed phase execution.
+struct Span {
+  int phase, ev0, ev1;
+};
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  std::vector<Span> spans;
+  int64_t dropped = 0;
+};
+std::mutex g_tmutex;
+Timing g_timing[kMaxDevices];
+
 int check_common(int64_t n_elem, int order, sem_dtype dt) {
   if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
   if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
@@ -38,6 +53,35 @@ int check_common(int64_t n_elem, int order, sem_dtype dt) {
 }
 
 }  // namespace
+
+PhaseTimer phase_timer(int phase) {
+  PhaseTimer pt;
+  int dev = -1;
+  if (phase < 0 || phase >= SEM_NUM_PHASES) return pt;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return pt;
+  std::lock_guard<std::mutex> lock(g_tmutex);
+  Timing& t = g_timing[dev];
+  if (!t.on) return pt;
+  if (t.used + 2 > t.ev.size()) {
+    ++t.dropped;
+    return pt;
+  }
+  pt.phase = phase;
+  pt.i0 = (int)t.used++;
+  pt.i1 = (int)t.used++;
+  pt.start = t.ev[pt.i0];
+  pt.stop = t.ev[pt.i1];
+  return pt;
+}
+
+void phase_done(const PhaseTimer& pt) {
+  int dev = -1;
+  if (pt.phase < 0) return;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_tmutex);
+  Timing& t = g_timing[dev];
+  if (t.on) t.spans.push_back(Span{pt.phase, pt.i0, pt.i1});
+}
 
 IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso) {
   const int64_t count = (int64_t)n_iso * n_elem;
@@ -266,6 +310,66 @@ int sem_isosurface(int64_t n_elem, int order, sem_dtype dt, const void* x, const
                                    active_cells, case_idx, ws, status_word,
                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+const char* sem_phase_name(int phase) {
+  switch (phase) {
+    case SEM_PHASE_QCRIT: return "qcrit";
+    case SEM_PHASE_COUNT: return "count";
+    case SEM_PHASE_SCAN: return "scan";
+    case SEM_PHASE_EMIT: return "emit";
+    default: return "unknown";
+  }
+}
+
+int sem_timing_begin(int max_spans) {
+  if (max_spans < 1 || max_spans > (1 << 20)) return SEM_ERR_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SEM_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return SEM_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_tmutex);
+  Timing& t = g_timing[dev];
+  if (t.on) return SEM_ERR_ARG;
+  t = Timing{};
+  t.ev.resize((size_t)2 * max_spans);
+  for (size_t k = 0; k < t.ev.size(); ++k) {
+    if (hipEventCreate(&t.ev[k]) != hipSuccess) {
+      for (size_t q = 0; q < k; ++q) (void)hipEventDestroy(t.ev[q]);
+      t = Timing{};
+      return SEM_ERR_HIP;
+    }
+  }
+  t.on = true;
+  return SEM_OK;
+}
+
+int64_t sem_timing_end(double* ms_total, int64_t* spans, int n_phases) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SEM_ERR_HIP;
+  if (dev < 0 || dev >= kMaxDevices || n_phases < 0) return SEM_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_tmutex);
+  Timing& t = g_timing[dev];
+  if (!t.on) return SEM_ERR_ARG;
+  double tot[SEM_NUM_PHASES] = {0, 0, 0, 0};
+  int64_t cnt[SEM_NUM_PHASES] = {0, 0, 0, 0};
+  int64_t rc = t.dropped;
+  for (const Span& sp : t.spans) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.ev[sp.ev1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, t.ev[sp.ev0], t.ev[sp.ev1]) != hipSuccess) {
+      rc = SEM_ERR_HIP;
+      break;
+    }
+    tot[sp.phase] += ms;
+    cnt[sp.phase] += 1;
+  }
+  for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  t = Timing{};
+  for (int q = 0; q < n_phases; ++q) {
+    if (ms_total) ms_total[q] = q < SEM_NUM_PHASES ? tot[q] : 0.0;
+    if (spans) spans[q] = q < SEM_NUM_PHASES ? cnt[q] : 0;
+  }
+  return rc;
 }
 
 }  // extern "C"

@@ -52,6 +52,19 @@ struct IsoWorkspace {
 IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso);
 int64_t scan_blocks(int64_t count);
 
+// Kernel-phase timing (sem_api.cpp).  phase_timer() hands out two events
+// when timing is on for the current device (else two nulls): the phase's
+// first kernel is launched with `start`, its last with `stop`, through
+// hipExtLaunchKernelGGL, which stamps them from the kernels' own dispatch
+// timestamps (no extra packets on the stream); phase_done() then records
+// the span.
+struct PhaseTimer {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int phase = -1, i0 = -1, i1 = -1;
+};
+PhaseTimer phase_timer(int phase);
+void phase_done(const PhaseTimer& t);
+
 // sem_kernels.hip -- launchers return hipSuccess or the launch error.
 hipError_t launch_derivs(int order, sem_dtype dt, const DeviceTables& tab,
                          int64_t n_elem, const void* x, const void* y,

@@ -17,6 +17,8 @@
 #include <cstdint>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "sem_internal.h"
 
 namespace sem {
@@ -1312,26 +1314,32 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
                    const void* y, const void* z, const void* u, const void* v, const void* w,
                    void* q, void* om, void* qmm, int32_t* status, hipStream_t s) {
   const T* d = dmat_of<T>(tab, order);
+  const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
+  bool done = false;
   if constexpr (std::is_same<T, double>::value) {
     if (order == 7) {
-      hipLaunchKernelGGL(qcrit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, d, (const T*)x,
-                         (const T*)y, (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q,
-                         (T*)om, (T*)qmm, status);
-      return hipGetLastError();
+      hipExtLaunchKernelGGL(qcrit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, pt.start,
+                            pt.stop, 0, d, (const T*)x, (const T*)y, (const T*)z, (const T*)u,
+                            (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm, status);
+      done = true;
     }
   }
-  SEM_ORDER_SWITCH(order, {
-    if constexpr (N <= 7) {
-      hipLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s, d,
-                         (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
-                         (const T*)w, (T*)q, (T*)om, (T*)qmm, status);
-    } else {
-      hipLaunchKernelGGL((qcrit_tile<N, T>), dim3((unsigned)n_elem),
-                         dim3(Shape<N>::kNodeThreads), 0, s, d, (const T*)x, (const T*)y,
-                         (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om,
-                         (T*)qmm, status);
-    }
-  });
+  if (!done) {
+    SEM_ORDER_SWITCH(order, {
+      if constexpr (N <= 7) {
+        hipExtLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
+                              pt.start, pt.stop, 0, d, (const T*)x, (const T*)y, (const T*)z,
+                              (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm,
+                              status);
+      } else {
+        hipExtLaunchKernelGGL((qcrit_tile<N, T>), dim3((unsigned)n_elem),
+                              dim3(Shape<N>::kNodeThreads), 0, s, pt.start, pt.stop, 0, d,
+                              (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
+                              (const T*)w, (T*)q, (T*)om, (T*)qmm, status);
+      }
+    });
+  }
+  phase_done(pt);
   return hipGetLastError();
 }
 
@@ -1351,29 +1359,39 @@ hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, con
                          hipStream_t s) {
   const int64_t count = (int64_t)n_iso * n_elem;
   const int64_t nb = scan_blocks(count);
-  hipLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.cnt, count,
-                     ws.partial);
+  const PhaseTimer ps = phase_timer(SEM_PHASE_SCAN);
+  hipExtLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ps.start,
+                        nullptr, 0, ws.cnt, count, ws.partial);
   hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, ws.partial, nb);
   hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.cnt, count,
                      ws.partial, nb, ws.offs);
-  hipLaunchKernelGGL((iso_totals<T>), dim3(1), dim3(SEM_MAX_ISO), 0, s, ws.offs, n_elem, n_iso,
-                     tri_count, out, status);
+  hipExtLaunchKernelGGL((iso_totals<T>), dim3(1), dim3(SEM_MAX_ISO), 0, s, nullptr, ps.stop, 0,
+                        ws.offs, n_elem, n_iso, tri_count, out, status);
+  phase_done(ps);
   bool any_cap = false;
   for (int q = 0; q < (out.per_iso ? n_iso : 1); ++q) any_cap = any_cap || out.cap[q] > 0;
   if (!any_cap) return hipGetLastError();
+  const PhaseTimer pe = phase_timer(SEM_PHASE_EMIT);
+  bool done = false;
   if constexpr (std::is_same<T, double>::value) {
     if (order == 7) {
-      hipLaunchKernelGGL(emit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, n_elem,
-                         (const T*)x, (const T*)y, (const T*)z, (const T*)field, n_iso, iso, out,
-                         tab.ntri, tab.tri, ws.cnt, ws.offs, keys);
-      return hipGetLastError();
+      hipExtLaunchKernelGGL(emit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, pe.start,
+                            pe.stop, 0, n_elem, (const T*)x, (const T*)y, (const T*)z,
+                            (const T*)field, n_iso, iso, out, tab.ntri, tab.tri,
+                            (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys);
+      done = true;
     }
   }
-  SEM_ORDER_SWITCH(order, {
-    hipLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem), dim3(Shape<N>::kCellThreads),
-                       0, s, n_elem, (const T*)x, (const T*)y, (const T*)z, (const T*)field,
-                       n_iso, iso, tab.ntri, tab.tri, ws.cnt, ws.offs, out, keys);
-  });
+  if (!done) {
+    SEM_ORDER_SWITCH(order, {
+      hipExtLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem),
+                            dim3(Shape<N>::kCellThreads), 0, s, pe.start, pe.stop, 0, n_elem,
+                            (const T*)x, (const T*)y, (const T*)z, (const T*)field, n_iso, iso,
+                            tab.ntri, tab.tri, (const int32_t*)ws.cnt, (const int64_t*)ws.offs,
+                            out, keys);
+    });
+  }
+  phase_done(pe);
   return hipGetLastError();
 }
 
@@ -1387,11 +1405,14 @@ hipError_t iso_pipeline(int order, const DeviceTables& tab, int64_t n_elem, cons
                         hipStream_t s) {
   const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
   if (active) hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
+  const PhaseTimer pt = phase_timer(SEM_PHASE_COUNT);
   SEM_ORDER_SWITCH(order, {
-    hipLaunchKernelGGL((iso_count<N, T>), dim3((unsigned)n_elem),
-                       dim3(Shape<N>::kCellThreads), 0, s, n_elem, (const T*)field,
-                       (const T*)mm, n_iso, iso, tab.ntri, ws.cnt, active, case_idx);
+    hipExtLaunchKernelGGL((iso_count<N, T>), dim3((unsigned)n_elem),
+                          dim3(Shape<N>::kCellThreads), 0, s, pt.start, pt.stop, 0, n_elem,
+                          (const T*)field, (const T*)mm, n_iso, iso, tab.ntri, ws.cnt, active,
+                          case_idx);
   });
+  phase_done(pt);
   return iso_scan_emit<T>(order, tab, n_elem, x, y, z, field, n_iso, iso, out, keys, tri_count,
                           ws, status, s);
 }
@@ -1431,10 +1452,12 @@ hipError_t extract_t(int order, const DeviceTables& tab, int64_t n_elem, const v
     if (order == 7) {
       if (active)
         hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
-      hipLaunchKernelGGL(qcount_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, n_elem, d,
-                         (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
-                         (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso, iso, tab.ntri, ws.cnt,
-                         active, status);
+      const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
+      hipExtLaunchKernelGGL(qcount_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, pt.start,
+                            pt.stop, 0, n_elem, d, (const T*)x, (const T*)y, (const T*)z,
+                            (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso,
+                            iso, tab.ntri, ws.cnt, active, status);
+      phase_done(pt);
       return iso_scan_emit<T>(order, tab, n_elem, x, y, z, q, n_iso, iso, out, nullptr,
                               tri_count, ws, status, s);
     }

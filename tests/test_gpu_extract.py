@@ -175,3 +175,29 @@ def test_extract_channel_full_size_fp64():
             o = mc.extract(*(a[k:k + 1] for a in arrs[:3]), gq[k:k + 1], [c])
             got = host(r["tri"][s][int(offs[s][e]):int(offs[s][e]) + nt])
             assert np.abs(got - o["tri_xyz"]).max() <= 1e-10 * 4 * np.pi
+
+
+def test_phase_timing_records_every_phase():
+    n, dt = 7, np.float64
+    arrs = _inputs(n, (3, 2, 2), 5)
+    t = [dev(a, dt) for a in arrs]
+    isos = [0.0, 0.4]
+    sem.timing_begin(64)
+    r = sem.extract(*t, isos)            # two-phase: count-only call, then emission
+    sem.qcrit(*t)
+    torch.cuda.synchronize()
+    phases, dropped = sem.timing_end()
+    assert dropped == 0
+    assert sum(host(r["tri_count"])) > 0
+    ms = {k: v[0] for k, v in phases.items()}
+    spans = {k: v[1] for k, v in phases.items()}
+    assert spans["qcrit"] == 3 and spans["scan"] == 2 and spans["emit"] == 1
+    assert all(ms[k] > 0 for k in ("qcrit", "scan", "emit"))
+    # a second begin while on is refused; timing restarts after end
+    sem.timing_begin(1)
+    with pytest.raises(sem.SemError):
+        sem.timing_begin(1)
+    sem.extract(*t, isos)
+    torch.cuda.synchronize()
+    _, dropped = sem.timing_end()
+    assert dropped > 0                   # one span fits, the rest are dropped

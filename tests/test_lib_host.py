@@ -190,3 +190,19 @@ def test_extract_workspace_sizes():
     assert b >= 1000 * 1000 * 8
     assert sem.extract_workspace_bytes(1000, 9, 3, _lib.SEM_F32) < b
     assert sem.extract_workspace_bytes(10, 0, 1) == 0
+
+
+def test_timing_argument_errors_and_phase_names():
+    L = sem.lib()
+    assert L.sem_timing_begin(0) == _lib.SEM_ERR_ARG
+    assert L.sem_timing_begin((1 << 20) + 1) == _lib.SEM_ERR_ARG
+    assert [sem.phase_name(k) for k in range(_lib.SEM_NUM_PHASES)] == [
+        "qcrit", "count", "scan", "emit"]
+    assert sem.phase_name(9) == "unknown"
+    text = open(HEADER).read()
+    assert re.search(rf"SEM_NUM_PHASES = {_lib.SEM_NUM_PHASES}\b", text)
+
+
+@pytest.mark.skipif(not _no_gpu(), reason="only meaningful where no device exists")
+def test_timing_end_without_device_or_begin_fails():
+    assert sem.lib().sem_timing_end(None, None, 4) < 0
