@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", choices=("f64", "f32"), default="f64")
     ap.add_argument("--cpu-baseline", choices=("on", "off"), default="on")
+    ap.add_argument("--precision-modes", choices=("on", "off"), default="on",
+                    help="also time FP32 and the mixed-precision modes on the same snapshot")
     ap.add_argument("--cpu-elements", type=int, default=16384,
                     help="elements of the snapshot the CPU oracle is timed on")
     ap.add_argument("--quiet", action="store_true")
@@ -286,9 +288,63 @@ def main():
         "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
     }
 
+    if args.precision_modes == "on" and args.dtype == "f64":
+        result["precision_modes"] = precision_modes(args, sem, fields, isos, n_elem, points)
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(args, fields, isos, n, n_elem)
     print(json.dumps(result), flush=True)
+
+
+def precision_modes(args, sem, fields, isos, n_elem, points):
+    """The same sem_extract step in FP32 storage: plain FP32 and the mixed
+    modes (BF16 / FP16 matrix-core contractions, plain and split).  Returns
+    {mode: {ms_per_step, points_per_s, q_phase_ms, triangles}}."""
+    import torch
+    f32 = [f.float().contiguous() for f in fields]
+    k = len(isos)
+    dev = f32[0].device
+    out = {}
+    for mode in ("f32", "bf16", "fp16", "bf16x3", "fp16x3"):
+        prec = None if mode == "f32" else mode
+        code = sem.SEM_F32 if prec is None else sem.MIXED[prec]
+        ws = torch.empty(sem.extract_workspace_bytes(n_elem, 7, k, code), dtype=torch.uint8,
+                         device=dev)
+        cnt = torch.zeros(k, dtype=torch.int64, device=dev)
+        sem.extract_into(*f32, isos, [None] * k, cnt, ws, precision=prec)
+        counts = cnt.cpu().tolist()
+        tris = [torch.empty((c, 3, 3), dtype=torch.float32, device=dev) for c in counts]
+        q = torch.empty_like(f32[3])
+        om = torch.empty_like(f32[3])
+        mm = torch.empty((n_elem, 2), dtype=torch.float32, device=dev)
+
+        def step():
+            sem.extract_into(*f32, isos, tris, cnt, ws, q=q, omega_mag=om, minmax=mm,
+                             precision=prec)
+
+        for _ in range(2):
+            step()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        steps = max(5, args.steps // 2)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        sem.timing_begin(4 * steps + 16)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ph, _ = sem.timing_end()
+        qms = ph["qcrit"][0] / max(ph["qcrit"][1], 1)
+        out[mode] = {"ms_per_step": round(ms, 5), "points_per_s": points / (ms * 1e-3),
+                     "q_phase_ms": round(qms, 5), "triangles": counts}
+        log(args, f"{mode:7s}: {ms:.4f} ms/step ({points / (ms * 1e-3) / 1e9:.1f} G points/s), "
+                  f"Q phase {qms:.4f} ms, triangles {counts}")
+        del ws, tris, q, om, mm
+    return out
 
 
 def cpu_baseline(args, fields, isos, n, n_elem):

@@ -46,7 +46,24 @@
 extern "C" {
 #endif
 
-typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
+/* Precision of a call.  SEM_F64 / SEM_F32: storage and arithmetic in that
+ * type.  SEM_MIXED_*: FP32 storage (every field, output and triangle array
+ * is float); the 1-D derivative contractions run on the matrix cores with
+ * BF16 or FP16 operands and FP32 accumulation -- plain (one rounded product)
+ * or split (x3: hi*hi + lo*hi + hi*lo with x = hi + lo, after Henry, Tang &
+ * Heinecke 2019 and, for FP16 with the lo parts scaled by 2^11, Ootomo &
+ * Yokota 2022); the Jacobian is inverted in FP64; chain rule, Q and |omega|
+ * are FP32.  Mixed modes need N = 7 in sem_derivs, sem_qcrit and
+ * sem_extract (SEM_ERR_ORDER otherwise); sem_isosurface, which takes no
+ * derivative, treats them as SEM_F32. */
+typedef enum {
+  SEM_F64 = 0,
+  SEM_F32 = 1,
+  SEM_MIXED_BF16 = 2,
+  SEM_MIXED_FP16 = 3,
+  SEM_MIXED_BF16X3 = 4,
+  SEM_MIXED_FP16X3 = 5
+} sem_dtype;
 
 enum {
   SEM_OK = 0,
@@ -55,7 +72,7 @@ enum {
   SEM_ERR_NOT_INIT = -3,   /* sem_init was not called for the current device */
   SEM_ERR_HIP = -4,        /* a HIP runtime call or kernel launch failed     */
   SEM_ERR_WORKSPACE = -5,  /* isosurface workspace NULL or too small         */
-  SEM_ERR_DTYPE = -6       /* dtype is neither SEM_F64 nor SEM_F32           */
+  SEM_ERR_DTYPE = -6       /* dtype is not one of the sem_dtype values       */
 };
 
 enum { SEM_FLAG_BAD_JACOBIAN = 1, SEM_FLAG_TRI_OVERFLOW = 2 };

@@ -8,7 +8,7 @@ This package is the thin ctypes binding (``_lib``) and the build script
 """
 
 from ._lib import (  # noqa: F401
-    SEM_F32, SEM_F64, SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_MAX_ORDER,
+    MIXED, SEM_F32, SEM_F64, SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_MAX_ORDER,
     SEM_MIN_ORDER, SemError, derivs, extract, extract_into, extract_workspace_bytes, gll,
     init, isosurface, isosurface_into, lib, mc_table, phase_name, qcrit, status_str,
     timing_begin, timing_end, workspace_bytes,

@@ -15,6 +15,10 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsem.so")
 
 SEM_F64, SEM_F32 = 0, 1
+SEM_MIXED_BF16, SEM_MIXED_FP16, SEM_MIXED_BF16X3, SEM_MIXED_FP16X3 = 2, 3, 4, 5
+# precision names of the mixed modes (FP32 storage, MFMA derivative contractions)
+MIXED = {"bf16": SEM_MIXED_BF16, "fp16": SEM_MIXED_FP16, "bf16x3": SEM_MIXED_BF16X3,
+         "fp16x3": SEM_MIXED_FP16X3}
 SEM_OK = 0
 SEM_ERR_ARG, SEM_ERR_ORDER, SEM_ERR_NOT_INIT = -1, -2, -3
 SEM_ERR_HIP, SEM_ERR_WORKSPACE, SEM_ERR_DTYPE = -4, -5, -6
@@ -145,8 +149,16 @@ def init(device=None):
     return device
 
 
-def _dtype_code(t):
+def _dtype_code(t, precision=None):
+    """SEM_F64 / SEM_F32 from the tensor dtype, or a mixed mode by name
+    (float32 tensors only)."""
     torch = _torch()
+    if precision is not None:
+        if precision not in MIXED:
+            raise ValueError(f"precision must be one of {sorted(MIXED)}")
+        if t.dtype != torch.float32:
+            raise TypeError("mixed precision takes float32 fields")
+        return MIXED[precision]
     if t.dtype == torch.float64:
         return SEM_F64
     if t.dtype == torch.float32:
@@ -189,8 +201,10 @@ def _stream(t):
     return torch.cuda.current_stream(t.device).cuda_stream
 
 
-def derivs(x, y, z, f, status=None):
-    """Physical gradient (df/dx, df/dy, df/dz) of one field."""
+def derivs(x, y, z, f, status=None, precision=None):
+    """Physical gradient (df/dx, df/dy, df/dz) of one field.  `precision`
+    names a mixed mode ("bf16", "fp16", "bf16x3", "fp16x3") for float32
+    fields; None computes in the fields' own dtype."""
     torch = _torch()
     _field_check(x, y, z, f)
     _status_check(status, x)
@@ -198,15 +212,17 @@ def derivs(x, y, z, f, status=None):
     _order_of(x)
     out = [torch.empty_like(f) for _ in range(3)]
     with torch.cuda.device(x.device):
-        _check(lib().sem_derivs(x.shape[0], _order_of(x), _dtype_code(x), _ptr(x), _ptr(y),
+        _check(lib().sem_derivs(x.shape[0], _order_of(x), _dtype_code(x, precision), _ptr(x),
+                                _ptr(y),
                                 _ptr(z), _ptr(f), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
                                 _ptr(status), _stream(x)), "sem_derivs")
     return tuple(out)
 
 
 def qcrit(x, y, z, u, v, w, status=None, q=None, omega_mag=None, minmax=None,
-          want=("q", "omega", "minmax")):
-    """Q-criterion, vorticity magnitude and per-element (min, max) of Q."""
+          want=("q", "omega", "minmax"), precision=None):
+    """Q-criterion, vorticity magnitude and per-element (min, max) of Q
+    (`precision` as in derivs)."""
     torch = _torch()
     _field_check(x, y, z, u, v, w)
     _field_check(x, q, omega_mag)
@@ -224,7 +240,8 @@ def qcrit(x, y, z, u, v, w, status=None, q=None, omega_mag=None, minmax=None,
     if minmax is None and "minmax" in want:
         minmax = torch.empty((e, 2), dtype=u.dtype, device=u.device)
     with torch.cuda.device(x.device):
-        _check(lib().sem_qcrit(e, _order_of(x), _dtype_code(x), _ptr(x), _ptr(y), _ptr(z),
+        _check(lib().sem_qcrit(e, _order_of(x), _dtype_code(x, precision), _ptr(x), _ptr(y),
+                               _ptr(z),
                                _ptr(u), _ptr(v), _ptr(w), _ptr(q), _ptr(omega_mag),
                                _ptr(minmax), _ptr(status), _stream(x)), "sem_qcrit")
     return q, omega_mag, minmax
@@ -315,8 +332,9 @@ def extract_workspace_bytes(n_elem, order, n_iso, dtype_code=SEM_F64):
 
 
 def extract_into(x, y, z, u, v, w, isovalues, tri_list, tri_count, workspace, q=None,
-                 omega_mag=None, minmax=None, active=None, status=None):
-    """Raw fused call: tri_list[s] is a (cap_s, 3, 3) tensor or None (count only)."""
+                 omega_mag=None, minmax=None, active=None, status=None, precision=None):
+    """Raw fused call: tri_list[s] is a (cap_s, 3, 3) tensor or None (count
+    only); `precision` as in derivs."""
     torch = _torch()
     _field_check(x, y, z, u, v, w)
     _field_check(x, q, omega_mag)
@@ -346,20 +364,21 @@ def extract_into(x, y, z, u, v, w, isovalues, tri_list, tri_count, workspace, q=
     if minmax is not None and (minmax.numel() < 2 * e or minmax.dtype != x.dtype
                                or not minmax.is_contiguous() or minmax.device != x.device):
         raise ValueError("minmax must be a contiguous (E, 2) tensor of the field dtype")
-    need = extract_workspace_bytes(e, n, k, _dtype_code(x))
+    code = _dtype_code(x, precision)
+    need = extract_workspace_bytes(e, n, k, code)
     if e > 0 and (workspace is None or workspace.dtype != torch.uint8
                   or workspace.numel() < need or workspace.device != x.device):
         raise ValueError(f"workspace must be a uint8 tensor of >= {need} bytes")
     with torch.cuda.device(x.device):
         _check(lib().sem_extract(
-            e, n, _dtype_code(x), _ptr(x), _ptr(y), _ptr(z), _ptr(u), _ptr(v), _ptr(w),
+            e, n, code, _ptr(x), _ptr(y), _ptr(z), _ptr(u), _ptr(v), _ptr(w),
             _ptr(q), _ptr(omega_mag), _ptr(minmax), k, iso.ctypes.data,
             ctypes.cast(ptrs, ctypes.c_void_p), caps.ctypes.data, _ptr(tri_count),
             _ptr(active), _ptr(workspace), 0 if workspace is None else workspace.numel(),
             _ptr(status), _stream(x)), "sem_extract")
 
 
-def extract(x, y, z, u, v, w, isovalues, status=None, want_fields=True):
+def extract(x, y, z, u, v, w, isovalues, status=None, want_fields=True, precision=None):
     """Fused Q / |omega| / isosurfaces with exact allocation (two calls).
 
     Returns a dict: q, omega_mag, minmax (when want_fields), tri (list of
@@ -368,18 +387,18 @@ def extract(x, y, z, u, v, w, isovalues, status=None, want_fields=True):
     torch = _torch()
     dev = x.device
     k, e, n = len(isovalues), x.shape[0], _order_of(x)
-    ws = torch.empty(max(extract_workspace_bytes(e, n, k, _dtype_code(x)), 1),
+    ws = torch.empty(max(extract_workspace_bytes(e, n, k, _dtype_code(x, precision)), 1),
                      dtype=torch.uint8, device=dev)
     cnt = torch.zeros(k, dtype=torch.int64, device=dev)
     act = torch.zeros(k, dtype=torch.int64, device=dev)
-    extract_into(x, y, z, u, v, w, isovalues, [None] * k, cnt, ws)
+    extract_into(x, y, z, u, v, w, isovalues, [None] * k, cnt, ws, precision=precision)
     counts = cnt.cpu().tolist()
     tris = [torch.empty((c, 3, 3), dtype=x.dtype, device=dev) for c in counts]
     q = torch.empty_like(u) if want_fields else None
     om = torch.empty_like(u) if want_fields else None
     mm = torch.empty((e, 2), dtype=u.dtype, device=dev) if want_fields else None
     extract_into(x, y, z, u, v, w, isovalues, tris, cnt, ws, q=q, omega_mag=om, minmax=mm,
-                 active=act, status=status)
+                 active=act, status=status, precision=precision)
     return {"q": q, "omega_mag": om, "minmax": mm, "tri": tris, "tri_count": cnt,
             "active": act}
 

@@ -45,9 +45,13 @@ struct Timing {
 std::mutex g_tmutex;
 Timing g_timing[kMaxDevices];
 
-int check_common(int64_t n_elem, int order, sem_dtype dt) {
-  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+bool mixed_dtype(sem_dtype dt) { return dt >= SEM_MIXED_BF16 && dt <= SEM_MIXED_FP16X3; }
+
+// `derivatives`: the call differentiates (mixed modes then need N = 7).
+int check_common(int64_t n_elem, int order, sem_dtype dt, bool derivatives = true) {
+  if (dt < SEM_F64 || dt > SEM_MIXED_FP16X3) return SEM_ERR_DTYPE;
   if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+  if (derivatives && mixed_dtype(dt) && order != 7) return SEM_ERR_ORDER;
   if (n_elem < 0 || n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
   return SEM_OK;
 }
@@ -133,7 +137,7 @@ const char* sem_status_str(int status) {
     case SEM_ERR_NOT_INIT: return "sem_init was not called for the current device";
     case SEM_ERR_HIP: return "HIP runtime call or kernel launch failed";
     case SEM_ERR_WORKSPACE: return "isosurface workspace missing or too small";
-    case SEM_ERR_DTYPE: return "dtype must be SEM_F64 or SEM_F32";
+    case SEM_ERR_DTYPE: return "dtype is not a sem_dtype value";
     default: return "unknown status";
   }
 }
@@ -295,8 +299,9 @@ int sem_isosurface(int64_t n_elem, int order, sem_dtype dt, const void* x, const
                    uint64_t* tri_edge_key, int64_t* tri_count, int64_t* active_cells,
                    uint8_t* case_idx, void* workspace, size_t workspace_bytes,
                    int32_t* status_word, void* stream) {
-  int rc = check_common(n_elem, order, dt);
+  int rc = check_common(n_elem, order, dt, false);
   if (rc) return rc;
+  if (mixed_dtype(dt)) dt = SEM_F32;
   if (n_iso < 1 || n_iso > SEM_MAX_ISO || !iso_host || !tri_count) return SEM_ERR_ARG;
   if (n_elem > 0 && (!x || !y || !z || !field)) return SEM_ERR_ARG;
   if (tri_capacity < 0 || (tri_capacity > 0 && !tri_xyz)) return SEM_ERR_ARG;

@@ -1266,6 +1266,281 @@ emit_dma7(int64_t n_elem, const double* __restrict__ x, const double* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// mixed precision, N = 7, FP32 storage: derivative contractions on MFMA
+// ---------------------------------------------------------------------------
+//
+// The 1-D contractions run as v_mfma_f32_16x16x32_{bf16,f16}: low-precision
+// operands, FP32 accumulation.  One workgroup of four waves per element; for
+// each field and direction wave w differentiates the 16 lines 16w..16w+15:
+//   rows     i = output node along the line (rows 8..15 are zero),
+//   columns  the 16 lines,
+//   depth    the 8 line values spread over the four lane groups (group g
+//            holds values m0 = 2g and m1 = 2g + 1), each with the products
+//            the mode needs:
+//   plain            D_hi (f - f_0)_hi
+//   split (x3)       D_hi f_hi + D_lo f_hi + D_hi f_lo   (Henry, Tang &
+//                    Heinecke 2019: the lo*lo term is dropped)
+// where x_hi = round(x) to the operand format and x_lo = round(x - x_hi).
+// In the FP16 split the lo parts are scaled by 2^11 (out of FP16's subnormal
+// range; Ootomo & Yokota 2022) and accumulate separately, then scaled back.
+// Values enter line-shifted (f_m - f_0), which keeps the coordinates'
+// absolute offset out of the rounding.  The Jacobian is inverted in FP64;
+// the chain rule, Q and |omega| are FP32.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+enum MixMode { kMixBF16 = 0, kMixFP16 = 1, kMixBF16x3 = 2, kMixFP16x3 = 3 };
+
+template <int M>
+struct MixT {
+  typedef __bf16 E;
+  typedef bf16x8 V;
+};
+template <>
+struct MixT<kMixFP16> {
+  typedef _Float16 E;
+  typedef f16x8 V;
+};
+template <>
+struct MixT<kMixFP16x3> {
+  typedef _Float16 E;
+  typedef f16x8 V;
+};
+
+constexpr float kF16LoScale = 2048.0f;   // 2^11
+
+template <int M>
+__device__ __forceinline__ f32x4 mfma_line(typename MixT<M>::V a, typename MixT<M>::V b) {
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (M == kMixBF16 || M == kMixBF16x3)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, zero, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, zero, 0, 0, 0);
+}
+
+// A operands of one lane (row i = lane % 16, lane group g = lane / 16).
+template <int M>
+struct MixOps {
+  typename MixT<M>::V a;    // main product
+  typename MixT<M>::V ac;   // scaled correction (FP16 split only)
+};
+
+template <int M>
+__device__ __forceinline__ MixOps<M> mix_ops(const double* __restrict__ d, int lane) {
+  using E = typename MixT<M>::E;
+  MixOps<M> o;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    o.a[q] = E(0.f);
+    o.ac[q] = E(0.f);
+  }
+  const int i = lane & 15, g = lane >> 4;
+  if (i < 8) {
+    const double d0 = d[i * 8 + 2 * g], d1 = d[i * 8 + 2 * g + 1];
+    const E h0 = E((float)d0), h1 = E((float)d1);
+    if constexpr (M == kMixBF16x3) {
+      const E l0 = E((float)(d0 - (double)(float)h0));
+      const E l1 = E((float)(d1 - (double)(float)h1));
+      o.a[0] = h0; o.a[1] = l0; o.a[2] = h0;
+      o.a[3] = h1; o.a[4] = l1; o.a[5] = h1;
+    } else {
+      o.a[0] = h0;
+      o.a[1] = h1;
+      if constexpr (M == kMixFP16x3) {
+        o.ac[0] = E((float)((d0 - (double)(float)h0) * kF16LoScale));
+        o.ac[1] = h0;
+        o.ac[2] = E((float)((d1 - (double)(float)h1) * kF16LoScale));
+        o.ac[3] = h1;
+      }
+    }
+  }
+  return o;
+}
+
+// Derivatives along one line set: v0, v1 are this lane's shifted values
+// f[m0] - f[0], f[m1] - f[0]; lanes 0..31 receive the outputs of rows
+// 4 (lane / 16) .. + 3 for line lane % 16.
+template <int M>
+__device__ __forceinline__ f32x4 mix_contract(const MixOps<M>& o, float v0, float v1) {
+  using E = typename MixT<M>::E;
+  typename MixT<M>::V b;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) b[q] = E(0.f);
+  const E h0 = E(v0), h1 = E(v1);
+  if constexpr (M == kMixBF16x3) {
+    const E l0 = E(v0 - (float)h0), l1 = E(v1 - (float)h1);
+    b[0] = h0; b[1] = h0; b[2] = l0;
+    b[3] = h1; b[4] = h1; b[5] = l1;
+    return mfma_line<M>(o.a, b);
+  } else {
+    b[0] = h0;
+    b[1] = h1;
+    f32x4 acc = mfma_line<M>(o.a, b);
+    if constexpr (M == kMixFP16x3) {
+      typename MixT<M>::V bc;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) bc[q] = E(0.f);
+      bc[0] = h0;
+      bc[1] = E((v0 - (float)h0) * kF16LoScale);
+      bc[2] = h1;
+      bc[3] = E((v1 - (float)h1) * kF16LoScale);
+      const f32x4 c = mfma_line<M>(o.ac, bc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = fmaf(c[r], 1.0f / kF16LoScale, acc[r]);
+    }
+    return acc;
+  }
+}
+
+constexpr int kMixLS = 9;            // derivative tile: line stride (floats)
+constexpr int kMixDT = 64 * kMixLS;  // one derivative tile
+
+// One field (tile `f`, natural layout i + 8j + 64k) -> its three derivative
+// tiles `dt` (line-major: dt[d * kMixDT + line * kMixLS + node along line]).
+template <int M>
+__device__ __forceinline__ void mix_field(const float* __restrict__ f, float* __restrict__ dt,
+                                          const MixOps<M>& o, int wv, int lane) {
+  const int n = lane & 15, g = lane >> 4;
+  const int L = 16 * wv + n;
+  const int lo = L & 7, hi = L >> 3;
+  // line base and stride of direction r, s, t
+  const int base[3] = {8 * L, lo + 64 * hi, L};
+  const int stride[3] = {1, 8, 64};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float* line = f + base[d];
+    const float f0 = line[0];
+    const float v0 = line[(2 * g) * stride[d]] - f0;
+    const float v1 = line[(2 * g + 1) * stride[d]] - f0;
+    const f32x4 acc = mix_contract<M>(o, v0, v1);
+    if (lane < 32) {
+      float* out = dt + d * kMixDT + L * kMixLS + 4 * g;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[r] = acc[r];
+    }
+  }
+}
+
+// (f_r, f_s, f_t) of node (i, j, k) from its field's derivative tiles.
+__device__ __forceinline__ void mix_read(const float* __restrict__ dt, int i, int j, int k,
+                                         float& fr, float& fs, float& ft) {
+  fr = dt[(j + 8 * k) * kMixLS + i];
+  fs = dt[kMixDT + (i + 8 * k) * kMixLS + j];
+  ft = dt[2 * kMixDT + (i + 8 * j) * kMixLS + k];
+}
+
+// QC: Q, |omega| and the element range of Q from (x, y, z, u, v, w);
+// otherwise the physical gradient of f = u into (o0, o1, o2).
+template <int M, bool QC>
+__global__ void __launch_bounds__(256)
+mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
+       const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ u,
+       const float* __restrict__ v, const float* __restrict__ w, float* __restrict__ o0,
+       float* __restrict__ o1, float* __restrict__ o2, float* __restrict__ qmm,
+       int32_t* __restrict__ status) {
+  constexpr int NF = QC ? 6 : 4;
+  __shared__ float s_in[NF][512];
+  __shared__ float s_d[2][3 * kMixDT];
+  __shared__ float s_red[8];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int64_t base = (int64_t)blockIdx.x * 512;
+  const float* src[6] = {x, y, z, u, v, w};
+#pragma unroll
+  for (int c = t; c < NF * 128; c += 256) {
+    const int fi = c >> 7, ch = c & 127;
+    const float4 val = *reinterpret_cast<const float4*>(src[fi] + base + 4 * ch);
+    *reinterpret_cast<float4*>(&s_in[fi][4 * ch]) = val;
+  }
+  const MixOps<M> ops = mix_ops<M>(dmat, lane);
+  __syncthreads();
+
+  // owners: nodes t and t + 256
+  int ni[2], nj[2], nk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int nd = t + 256 * h;
+    ni[h] = nd & 7;
+    nj[h] = (nd >> 3) & 7;
+    nk[h] = nd >> 6;
+  }
+  float gd[3][2][3];   // geometry: [coordinate][node][r, s, t]
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float* dt = s_d[c & 1];
+    mix_field<M>(s_in[c], dt, ops, wv, lane);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) mix_read(dt, ni[h], nj[h], nk[h], gd[c][h][0], gd[c][h][1],
+                                         gd[c][h][2]);
+  }
+  int bad = 0;
+  InvJac<float> kk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    InvJac<double> k64;
+    bad |= !invert_jacobian<double>(gd[0][h][0], gd[0][h][1], gd[0][h][2], gd[1][h][0],
+                                    gd[1][h][1], gd[1][h][2], gd[2][h][0], gd[2][h][1],
+                                    gd[2][h][2], k64);
+    kk[h] = InvJac<float>{(float)k64.rx, (float)k64.ry, (float)k64.rz,
+                          (float)k64.sx, (float)k64.sy, (float)k64.sz,
+                          (float)k64.tx, (float)k64.ty, (float)k64.tz};
+  }
+  float a[2][3][3];
+#pragma unroll
+  for (int c = 0; c < NF - 3; ++c) {
+    float* dt = s_d[(3 + c) & 1];
+    mix_field<M>(s_in[3 + c], dt, ops, wv, lane);
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float fr, fs, ft;
+      mix_read(dt, ni[h], nj[h], nk[h], fr, fs, ft);
+      const InvJac<float>& K = kk[h];
+      a[h][c][0] = fr * K.rx + fs * K.sx + ft * K.tx;
+      a[h][c][1] = fr * K.ry + fs * K.sy + ft * K.ty;
+      a[h][c][2] = fr * K.rz + fs * K.sz + ft * K.tz;
+    }
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  if constexpr (!QC) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t o = base + t + 256 * h;
+      o0[o] = a[h][0][0];
+      o1[o] = a[h][0][1];
+      o2[o] = a[h][0][2];
+    }
+  } else {
+    float mn = pos_inf<float>(), mx = neg_inf<float>();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float(&A)[3][3] = a[h];
+      const float tr2 = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2] +
+                        2.f * (A[0][1] * A[1][0] + A[0][2] * A[2][0] + A[1][2] * A[2][1]);
+      const float w1 = A[2][1] - A[1][2], w2 = A[0][2] - A[2][0], w3 = A[1][0] - A[0][1];
+      const float qv = -0.5f * tr2;
+      const int64_t o = base + t + 256 * h;
+      if (o0) o0[o] = qv;
+      if (o1) o1[o] = sqrtf(w1 * w1 + w2 * w2 + w3 * w3);
+      const float c = qv != qv ? neg_inf<float>() : qv;
+      mn = c < mn ? c : mn;
+      mx = c > mx ? c : mx;
+    }
+    if (qmm) {
+      block_minmax<float, 256>(mn, mx, s_red);
+      if (t == 0) {
+        qmm[2 * (int64_t)blockIdx.x] = mn;
+        qmm[2 * (int64_t)blockIdx.x + 1] = mx;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // dispatch over the order
 // ---------------------------------------------------------------------------
 
@@ -1340,6 +1615,34 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
     });
   }
   phase_done(pt);
+  return hipGetLastError();
+}
+
+bool is_mixed(sem_dtype dt) {
+  return dt == SEM_MIXED_BF16 || dt == SEM_MIXED_FP16 || dt == SEM_MIXED_BF16X3 ||
+         dt == SEM_MIXED_FP16X3;
+}
+
+// Mixed-precision kernels (N = 7, FP32 storage).  QC: Q / |omega| / range
+// into (o0, o1, qmm); otherwise the gradient of u into (o0, o1, o2).
+template <bool QC>
+hipError_t mixed_t(sem_dtype dt, const DeviceTables& tab, int64_t n_elem, const void* x,
+                   const void* y, const void* z, const void* u, const void* v, const void* w,
+                   void* o0, void* o1, void* o2, void* qmm, int32_t* status, hipStream_t s,
+                   const PhaseTimer& pt) {
+  auto go = [&](auto kern) {
+    hipExtLaunchKernelGGL(kern, dim3((unsigned)n_elem), dim3(256), 0, s, pt.start, pt.stop, 0,
+                          tab.d64[7], (const float*)x, (const float*)y, (const float*)z,
+                          (const float*)u, (const float*)v, (const float*)w, (float*)o0,
+                          (float*)o1, (float*)o2, (float*)qmm, status);
+  };
+  switch (dt) {
+    case SEM_MIXED_BF16: go(mixed7<kMixBF16, QC>); break;
+    case SEM_MIXED_FP16: go(mixed7<kMixFP16, QC>); break;
+    case SEM_MIXED_BF16X3: go(mixed7<kMixBF16x3, QC>); break;
+    case SEM_MIXED_FP16X3: go(mixed7<kMixFP16x3, QC>); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1434,7 +1737,8 @@ hipError_t iso_t(int order, const DeviceTables& tab, int64_t n_elem, const void*
 // sem_extract: q and qmm always point at storage (the caller's or the
 // workspace's); `ws` is the isosurface part of the workspace.
 template <typename T>
-hipError_t extract_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
+hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n_elem,
+                     const void* x,
                      const void* y, const void* z, const void* u, const void* v,
                      const void* w, void* q, void* om, void* qmm, int n_iso,
                      const double* iso_host, void* const* tri_xyz, const int64_t* cap,
@@ -1462,7 +1766,14 @@ hipError_t extract_t(int order, const DeviceTables& tab, int64_t n_elem, const v
                               tri_count, ws, status, s);
     }
   }
-  hipError_t err = qcrit_t<T>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, status, s);
+  hipError_t err;
+  if (is_mixed(dt)) {
+    const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
+    err = mixed_t<true>(dt, tab, n_elem, x, y, z, u, v, w, q, om, nullptr, qmm, status, s, pt);
+    phase_done(pt);
+  } else {
+    err = qcrit_t<T>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, status, s);
+  }
   if (err != hipSuccess) return err;
   return iso_pipeline<T>(order, tab, n_elem, x, y, z, q, qmm, n_iso, iso_host, out, nullptr,
                          tri_count, active, nullptr, ws, status, s);
@@ -1475,6 +1786,9 @@ int64_t scan_blocks(int64_t count) { return count <= 0 ? 1 : (count + kScanTile 
 hipError_t launch_derivs(int order, sem_dtype dt, const DeviceTables& tab, int64_t n_elem,
                          const void* x, const void* y, const void* z, const void* f, void* gx,
                          void* gy, void* gz, int32_t* status, hipStream_t s) {
+  if (is_mixed(dt))
+    return mixed_t<false>(dt, tab, n_elem, x, y, z, f, nullptr, nullptr, gx, gy, gz, nullptr,
+                          status, s, PhaseTimer{});
   return dt == SEM_F64 ? derivs_t<double>(order, tab, n_elem, x, y, z, f, gx, gy, gz, status, s)
                        : derivs_t<float>(order, tab, n_elem, x, y, z, f, gx, gy, gz, status, s);
 }
@@ -1483,6 +1797,13 @@ hipError_t launch_qcrit(int order, sem_dtype dt, const DeviceTables& tab, int64_
                         const void* x, const void* y, const void* z, const void* u,
                         const void* v, const void* w, void* q, void* om, void* qmm,
                         int32_t* status, hipStream_t s) {
+  if (is_mixed(dt)) {
+    const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
+    const hipError_t e =
+        mixed_t<true>(dt, tab, n_elem, x, y, z, u, v, w, q, om, nullptr, qmm, status, s, pt);
+    phase_done(pt);
+    return e;
+  }
   return dt == SEM_F64
              ? qcrit_t<double>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, status, s)
              : qcrit_t<float>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, status, s);
@@ -1496,10 +1817,10 @@ hipError_t launch_extract(int order, sem_dtype dt, const DeviceTables& tab, int6
                           int64_t* active_cells, const IsoWorkspace& ws, int32_t* status,
                           hipStream_t s) {
   return dt == SEM_F64
-             ? extract_t<double>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
+             ? extract_t<double>(order, dt, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
                                  iso_host, tri_xyz, tri_capacity, tri_count, active_cells, ws,
                                  status, s)
-             : extract_t<float>(order, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
+             : extract_t<float>(order, dt, tab, n_elem, x, y, z, u, v, w, q, om, qmm, n_iso,
                                 iso_host, tri_xyz, tri_capacity, tri_count, active_cells, ws,
                                 status, s);
 }

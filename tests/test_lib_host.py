@@ -95,7 +95,7 @@ def test_derivs_argument_errors():
     L = sem.lib()
     f = FAKE
     assert L.sem_derivs(4, 0, 0, f, f, f, f, f, f, f, None, None) == _lib.SEM_ERR_ORDER
-    assert L.sem_derivs(4, 7, 2, f, f, f, f, f, f, f, None, None) == _lib.SEM_ERR_DTYPE
+    assert L.sem_derivs(4, 7, 9, f, f, f, f, f, f, f, None, None) == _lib.SEM_ERR_DTYPE
     assert L.sem_derivs(4, 7, 0, f, f, f, None, f, f, f, None, None) == _lib.SEM_ERR_ARG
     assert L.sem_derivs(4, 7, 0, f, f, f, f, f, f, None, None, None) == _lib.SEM_ERR_ARG
     assert L.sem_derivs(0, 7, 0, f, f, f, f, f, f, f, None, None) == _lib.SEM_OK
@@ -113,7 +113,7 @@ def _iso(**kw):
 
 def test_isosurface_argument_errors():
     assert _iso(order=0) == _lib.SEM_ERR_ORDER
-    assert _iso(dt=3) == _lib.SEM_ERR_DTYPE
+    assert _iso(dt=9) == _lib.SEM_ERR_DTYPE
     assert _iso(n_iso=0) == _lib.SEM_ERR_ARG
     assert _iso(n_iso=_lib.SEM_MAX_ISO + 1) == _lib.SEM_ERR_ARG
     assert _iso(iso=None) == _lib.SEM_ERR_ARG
@@ -206,3 +206,24 @@ def test_timing_argument_errors_and_phase_names():
 @pytest.mark.skipif(not _no_gpu(), reason="only meaningful where no device exists")
 def test_timing_end_without_device_or_begin_fails():
     assert sem.lib().sem_timing_end(None, None, 4) < 0
+
+
+def test_mixed_modes_need_order_7_where_they_differentiate():
+    L = sem.lib()
+    f = FAKE
+    for dt in (_lib.SEM_MIXED_BF16, _lib.SEM_MIXED_FP16, _lib.SEM_MIXED_BF16X3,
+               _lib.SEM_MIXED_FP16X3):
+        assert _qcrit(order=5, dt=dt) == _lib.SEM_ERR_ORDER
+        assert L.sem_derivs(4, 6, dt, f, f, f, f, f, f, f, None, None) == _lib.SEM_ERR_ORDER
+        assert _extract(order=8, dt=dt) == _lib.SEM_ERR_ORDER
+        assert _qcrit(dt=dt, x=None) == _lib.SEM_ERR_ARG
+        # the isosurface takes no derivative: any order, FP32 storage
+        assert _iso(order=5, dt=dt, ws=None) == _lib.SEM_ERR_WORKSPACE
+        assert (sem.extract_workspace_bytes(1000, 7, 3, dt)
+                == sem.extract_workspace_bytes(1000, 7, 3, _lib.SEM_F32))
+        assert sem.extract_workspace_bytes(1000, 5, 3, dt) == 0
+    assert set(_lib.MIXED.values()) == {2, 3, 4, 5}
+    text = open(HEADER).read()
+    for name, val in (("SEM_MIXED_BF16", 2), ("SEM_MIXED_FP16", 3), ("SEM_MIXED_BF16X3", 4),
+                      ("SEM_MIXED_FP16X3", 5)):
+        assert re.search(rf"{name} = {val}\b", text), name
