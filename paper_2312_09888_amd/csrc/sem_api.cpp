@@ -168,10 +168,14 @@ int sem_init(int device) {
     off32[n] = bytes;
     bytes += align256(sizeof(float) * (n + 1) * (n + 1));
   }
+  // the case table directly follows the 256 triangle counts: kernels copy
+  // both as one 4 KiB block
   const size_t off_ntri = bytes;
   bytes += align256(256);
   const size_t off_tri = bytes;
   bytes += align256(256 * kMcMaxTri * 3);
+  const size_t off_eo7 = bytes;
+  bytes += align256(sizeof(double) * 32);
   std::vector<unsigned char> host(bytes, 0);
   for (int n = 1; n <= kMaxOrder; ++n) {
     double* d = reinterpret_cast<double*>(host.data() + off64[n]);
@@ -180,6 +184,17 @@ int sem_init(int device) {
     for (int q = 0; q < (n + 1) * (n + 1); ++q) f[q] = (float)d[q];
   }
   build_mc_table(host.data() + off_ntri, reinterpret_cast<int8_t*>(host.data() + off_tri));
+  {
+    // even-odd coefficients of D for N = 7: A = (D[i][m] + D[i][7-m]) / 2,
+    // B = (D[i][m] - D[i][7-m]) / 2 for i, m < 4
+    const double* d = reinterpret_cast<const double*>(host.data() + off64[7]);
+    double* eo = reinterpret_cast<double*>(host.data() + off_eo7);
+    for (int i = 0; i < 4; ++i)
+      for (int m = 0; m < 4; ++m) {
+        eo[4 * i + m] = 0.5 * (d[8 * i + m] + d[8 * i + 7 - m]);
+        eo[16 + 4 * i + m] = 0.5 * (d[8 * i + m] - d[8 * i + 7 - m]);
+      }
+  }
 
   int prev = -1;
   if (hipGetDevice(&prev) != hipSuccess) return SEM_ERR_HIP;
@@ -199,6 +214,7 @@ int sem_init(int device) {
     }
     st.tab.ntri = reinterpret_cast<const uint8_t*>(b + off_ntri);
     st.tab.tri = reinterpret_cast<const int8_t*>(b + off_tri);
+    st.tab.eo7 = reinterpret_cast<const double*>(b + off_eo7);
     st.ready = true;
   }
   (void)hipSetDevice(prev);

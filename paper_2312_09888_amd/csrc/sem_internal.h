@@ -25,6 +25,7 @@ struct DeviceTables {
   const float* d32[kMaxOrder + 1];
   const uint8_t* ntri;                // [256]
   const int8_t* tri;                  // [256][kMcMaxTri][3]
+  const double* eo7;                  // N = 7 even-odd form of D: A[4][4], B[4][4]
 };
 
 template <typename T>

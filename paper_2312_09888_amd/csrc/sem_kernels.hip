@@ -587,6 +587,21 @@ struct DmaNode {
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
+// One 16-byte direct load per lane into LDS at lds + 16 * lane, issued as
+// inline assembly: the compiler then keeps no record of the LDS write and
+// inserts no waits of its own for it (after LDS lowering it cannot tell the
+// tiles apart and would wait for every load in flight before any tile
+// read).  Every consumer waits explicitly (s_waitcnt on vmcnt, then a
+// barrier) before reading the tile.
+__device__ __forceinline__ void lds_load16(const double* src, double* lds) {
+  const uint32_t m0 =
+      __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr_t)lds);
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(m0)
+               : "memory", "m0");
+}
+
 // Fetch one 4 KiB tile: wave h issues the chunk groups h and h + 2.
 __device__ __forceinline__ void dma_tile(const double* __restrict__ src, double* raw, int h,
                                          int lane) {
@@ -596,8 +611,7 @@ __device__ __forceinline__ void dma_tile(const double* __restrict__ src, double*
     const int s = 64 * part + lane;
     const int row = s >> 2, k = row >> 3, j = (row & 7) ^ (k & 1);
     const int ip = (s & 3) ^ ((j >> 1) & 3);
-    __builtin_amdgcn_global_load_lds(src + 2 * (ip + 4 * j + 32 * k),
-                                     (lds_ptr_t)(raw + 128 * part), 16, 0, 0);
+    lds_load16(src + 2 * (ip + 4 * j + 32 * k), raw + 128 * part);
   }
 }
 
@@ -798,8 +812,12 @@ qcrit_dma7(const double* __restrict__ dmat, const double* __restrict__ x,
 // ---------------------------------------------------------------------------
 
 // low corner and axis of each cube edge (edge id = 4*axis + rank)
-__constant__ int8_t kEdgeLo[12] = {0, 2, 4, 6, 0, 1, 4, 5, 0, 1, 2, 3};
-__constant__ int8_t kEdgeAxis[12] = {0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 2};
+// Low corner of edge e, packed as 4-bit fields (edge 0 lowest): edges
+// 0..3 run along r from corners 0, 2, 4, 6; edges 4..7 along s from 0, 1,
+// 4, 5; edges 8..11 along t from 0, 1, 2, 3.  The axis is e >> 2.  Decoded
+// with a shift instead of a table, so the vertex loop reads no memory for it.
+constexpr uint64_t kEdgeLoPacked = 0x321054106420ull;
+__device__ __forceinline__ int edge_lo(int e) { return (int)((kEdgeLoPacked >> (4 * e)) & 15); }
 
 // Node offset of cube corner v in a tile with row stride RS and slab stride SS.
 template <int RS, int SS>
@@ -894,8 +912,8 @@ __device__ __forceinline__ int emit_element(T c, NodeFn node, const T* __restric
     const int cs = cases[cell];
     const int ci = cell % N, cj = (cell / N) % N, ck = cell / (N * N);
     const int edge = s_tri[(cs * kMcMaxTri + slot) * 3 + vtx];
-    const int v0 = kEdgeLo[edge];
-    const int ax = kEdgeAxis[edge];
+    const int v0 = edge_lo(edge);
+    const int ax = edge >> 2;
     const int a0 = ci + (v0 & 1), b0 = cj + ((v0 >> 1) & 1), c0 = ck + (v0 >> 2);
     const int lo = node(a0, b0, c0);
     const int hi = node(a0 + (ax == 0), b0 + (ax == 1), c0 + (ax == 2));
@@ -1215,6 +1233,262 @@ qcount_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __res
   }
 }
 
+// ---------------------------------------------------------------------------
+// N = 7, FP64, four waves per element: two nodes per lane
+// ---------------------------------------------------------------------------
+//
+// The same staging and LDS layout as the two-wave kernels, with wave h
+// (0..3) owning nodes i = h and 7 - h of r-line (j, k) = lane.  Waves 0, 1
+// differentiate the s-lines and waves 2, 3 the t-lines, half a line each,
+// in the even-odd form of D.  A lane holds half the state of the two-wave
+// form, so twice as many waves fit on a SIMD to hide the load and LDS
+// latencies.
+
+// One 4 KiB tile with four waves: wave h issues chunk group h.
+__device__ __forceinline__ void dma_tile4(const double* __restrict__ src, double* raw, int h,
+                                          int lane) {
+  const int s = 64 * h + lane;
+  const int row = s >> 2, k = row >> 3, j = (row & 7) ^ (k & 1);
+  const int ip = (s & 3) ^ ((j >> 1) & 3);
+  lds_load16(src + 2 * (ip + 4 * j + 32 * k), raw + 128 * h);
+}
+
+// Even-odd form of an 8-point line derivative (D[7-i][7-m] = -D[i][m]):
+// with e_m = g_m + g_{7-m}, o_m = g_m - g_{7-m} (m < 4),
+// A[i][m] = (D[i][m] + D[i][7-m]) / 2 and B[i][m] = (D[i][m] - D[i][7-m]) / 2,
+//   (D g)_i = R_i + P_i,  (D g)_{7-i} = R_i - P_i  (i < 4),
+//   P_i = sum_m A[i][m] e_m,  R_i = sum_m B[i][m] o_m.
+// Half the multiplies of the direct form, and a pair of outputs needs one
+// row of A and B only.
+__device__ __forceinline__ void eo_split(const double (&g)[8], double (&e)[4], double (&o)[4]) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    e[m] = g[m] + g[7 - m];
+    o[m] = g[m] - g[7 - m];
+  }
+}
+__device__ __forceinline__ void eo_pair(const double* __restrict__ eo, int i,
+                                        const double (&e)[4], const double (&o)[4],
+                                        double& lo, double& hi) {
+  double P = eo[4 * i] * e[0], R = eo[16 + 4 * i] * o[0];
+#pragma unroll
+  for (int m = 1; m < 4; ++m) {
+    P = fma(eo[4 * i + m], e[m], P);
+    R = fma(eo[16 + 4 * i + m], o[m], R);
+  }
+  lo = R + P;
+  hi = R - P;
+}
+
+// One field with four waves: wave h owns nodes i = h and 7 - h of r-line
+// (j, k) = lane; waves 0, 1 differentiate s-lines, waves 2, 3 t-lines, each
+// the output pairs (r, 7 - r) for r = 2(h&1) and 2(h&1) + 1.
+__device__ __forceinline__ void dma_pass4(const double* __restrict__ raw,
+                                          const double* __restrict__ eo, double* __restrict__ S,
+                                          double* __restrict__ Tt, int h, int p,
+                                          double (&fr)[2], double (&fs)[2], double (&ft)[2]) {
+  using Q = Pen<7>;
+  const int j = p & 7, k = p >> 3;
+  double f[8], e[4], o[4];
+#pragma unroll
+  for (int ip = 0; ip < 4; ++ip) {
+    const double2 v = *reinterpret_cast<const double2*>(raw + 2 * dma7::slot(k, j, ip));
+    f[2 * ip] = v.x;
+    f[2 * ip + 1] = v.y;
+  }
+  eo_split(f, e, o);
+  eo_pair(eo, h, e, o, fr[0], fr[1]);
+  double g[8], out[4];
+  const int r0 = 2 * (h & 1);
+  if (h < 2) {   // s-line at (i, k) = (j, k) of this lane's index
+#pragma unroll
+    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, m, k)];
+  } else {       // t-line at (i, j) = (j, k) of this lane's index
+#pragma unroll
+    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, k, m)];
+  }
+  eo_split(g, e, o);
+  eo_pair(eo, r0, e, o, out[0], out[1]);
+  eo_pair(eo, r0 + 1, e, o, out[2], out[3]);
+  const int idx[4] = {r0, 7 - r0, r0 + 1, 6 - r0};
+  if (h < 2) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) S[Q::at(j, idx[q], k)] = out[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Tt[Q::at(j, k, idx[q])] = out[q];
+  }
+  lds_barrier();
+  fs[0] = S[Q::at(h, j, k)];
+  fs[1] = S[Q::at(7 - h, j, k)];
+  ft[0] = Tt[Q::at(h, j, k)];
+  ft[1] = Tt[Q::at(7 - h, j, k)];
+  lds_barrier();
+}
+
+// Keep a value materialised here (the compiler may not defer its
+// computation past later barriers, which would keep its inputs live).
+__device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
+
+// COUNT: also count every isovalue's triangles and active cells per element
+// from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
+template <bool COUNT>
+__global__ void __launch_bounds__(256)
+qcount4_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restrict__ x,
+             const double* __restrict__ y, const double* __restrict__ z,
+             const double* __restrict__ u, const double* __restrict__ v,
+             const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
+             double* __restrict__ qmm, int n_iso, IsoList<double> iso,
+             const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
+             int64_t* __restrict__ active, int32_t* __restrict__ status) {
+  constexpr int NC = 343;
+  __shared__ double s_xyz[3][512];
+  __shared__ double s_uvw[3][512];
+  __shared__ double s_S[Pen<7>::SZ];
+  __shared__ double s_T[Pen<7>::SZ];
+  __shared__ double s_red[8];
+  __shared__ uint8_t s_ntri[256];
+  __shared__ int32_t s_wave[8];
+  const int t = threadIdx.x;
+  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int p = t & 63;
+  const int64_t e = blockIdx.x;
+  const int64_t base = e * 512;
+  // the case-table entry is loaded first and stored once every load is in
+  const uint8_t nt_own = COUNT ? ntri_tab[t] : 0;
+  dma_tile4(x + base, s_xyz[0], h, p);
+  dma_tile4(y + base, s_xyz[1], h, p);
+  dma_tile4(z + base, s_xyz[2], h, p);
+  dma_tile4(u + base, s_uvw[0], h, p);
+  dma_tile4(v + base, s_uvw[1], h, p);
+  dma_tile4(w + base, s_uvw[2], h, p);
+  // coordinate tiles (the three velocity loads may stay in flight)
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(3));
+  barrier_after_wait();
+  double xr[2], xs[2], xt[2], yr[2], ys[2], yt[2], zr[2], zs[2], zt[2];
+  dma_pass4(s_xyz[0], eo, s_S, s_T, h, p, xr, xs, xt);
+  dma_pass4(s_xyz[1], eo, s_S, s_T, h, p, yr, ys, yt);
+  dma_pass4(s_xyz[2], eo, s_S, s_T, h, p, zr, zs, zt);
+  InvJac<double> kk[2];
+  int bad = 0;
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii)
+    bad |= !invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii],
+                            zt[ii], kk[ii]);
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii) {
+    pin(kk[ii].rx); pin(kk[ii].ry); pin(kk[ii].rz); pin(kk[ii].sx); pin(kk[ii].sy);
+    pin(kk[ii].sz); pin(kk[ii].tx); pin(kk[ii].ty); pin(kk[ii].tz);
+  }
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
+  if (COUNT) s_ntri[t] = nt_own;   // read only after later barriers
+  barrier_after_wait();
+  double fr[2], fs[2], ft[2], a01[2], a02[2], a12[2], qv[2], ov[2];
+  dma_pass4(s_uvw[0], eo, s_S, s_T, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii) {
+    const InvJac<double>& K = kk[ii];
+    const double a00 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    a01[ii] = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    a02[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = a00 * a00;
+    pin(qv[ii]); pin(a01[ii]); pin(a02[ii]);
+  }
+  dma_pass4(s_uvw[1], eo, s_S, s_T, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii) {
+    const InvJac<double>& K = kk[ii];
+    const double a10 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    const double a11 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    a12[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = qv[ii] + a11 * a11 + 2.0 * (a01[ii] * a10);
+    const double w3 = a10 - a01[ii];
+    ov[ii] = w3 * w3;
+    pin(qv[ii]); pin(ov[ii]); pin(a12[ii]);
+  }
+  dma_pass4(s_uvw[2], eo, s_S, s_T, h, p, fr, fs, ft);
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii) {
+    const InvJac<double>& K = kk[ii];
+    const double a20 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
+    const double a21 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
+    const double a22 = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
+    qv[ii] = -0.5 * (qv[ii] + a22 * a22 + 2.0 * (a02[ii] * a20 + a12[ii] * a21));
+    const double w1 = a21 - a12[ii], w2 = a02[ii] - a20;
+    ov[ii] = sqrt(ov[ii] + w1 * w1 + w2 * w2);
+  }
+  const int j = p & 7, k = p >> 3;
+  const int64_t o = base + (k * 8 + j) * 8;
+  if (q) {
+    q[o + h] = qv[0];
+    q[o + 7 - h] = qv[1];
+  }
+  if (om) {
+    om[o + h] = ov[0];
+    om[o + 7 - h] = ov[1];
+  }
+  double* QT = s_uvw[0];   // free after the u pass
+  double mn = pos_inf<double>(), mx = neg_inf<double>();
+#pragma unroll
+  for (int ii = 0; ii < 2; ++ii) {
+    if (COUNT) QT[dma7::at(ii ? 7 - h : h, j, k)] = qv[ii];
+    const double c = qv[ii] != qv[ii] ? neg_inf<double>() : qv[ii];
+    mn = c < mn ? c : mn;
+    mx = c > mx ? c : mx;
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  block_minmax<double, 256>(mn, mx, s_red);   // its barriers also publish the Q tile
+  if (qmm && t == 0) {
+    qmm[2 * e] = mn;
+    qmm[2 * e + 1] = mx;
+  }
+  if constexpr (COUNT) {
+    // the eight corner values of this thread's cells (t and t + 256), once
+    double cv[2][8];
+    bool has[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int cell = r * 256 + t;
+      has[r] = cell < NC;
+      const int cc = has[r] ? cell : 0;
+      const int ci = cc % 7, cj = (cc / 7) % 7, ck = cc / 49;
+#pragma unroll
+      for (int vtx = 0; vtx < 8; ++vtx)
+        cv[r][vtx] = QT[dma7::at(ci + (vtx & 1), cj + ((vtx >> 1) & 1), ck + (vtx >> 2))];
+    }
+    for (int s = 0; s < n_iso; ++s) {
+      const double c = iso.v[s];
+      int nt = 0, act = 0;
+      if ((mx > c) && !(mn > c)) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          int cs = 0;
+#pragma unroll
+          for (int vtx = 0; vtx < 8; ++vtx) cs |= (cv[r][vtx] > c) << vtx;
+          if (has[r]) {
+            nt += s_ntri[cs];
+            act += (cs != 0 && cs != 255);
+          }
+        }
+      }
+      nt = wave_sum(nt);
+      act = wave_sum(act);
+      if (p == 0) {
+        s_wave[h] = nt;
+        s_wave[4 + h] = act;
+      }
+      __syncthreads();
+      if (t == 0) {
+        cnt[(int64_t)s * n_elem + e] = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        const int a = s_wave[4] + s_wave[5] + s_wave[6] + s_wave[7];
+        if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Emission for N = 7, FP64: elements with triangles stage their field and
 // coordinate tiles with direct loads and emit through emit_element.
 __global__ void __launch_bounds__(128)
@@ -1228,11 +1502,13 @@ emit_dma7(int64_t n_elem, const double* __restrict__ x, const double* __restrict
   __shared__ double s_x[512];
   __shared__ double s_y[512];
   __shared__ double s_z[512];
-  __shared__ uint8_t s_ntri[256];
-  __shared__ int8_t s_tri[256 * kMcMaxTri * 3];
+  static_assert(256 + 256 * kMcMaxTri * 3 == 4096, "tables fill one 4 KiB block");
+  __shared__ uint4 s_tab[256];     // triangle counts (256 B), then the case table
   __shared__ uint8_t s_case[NC];
   __shared__ uint16_t s_desc[NC * kMcMaxTri];
   __shared__ int32_t s_wave[2];
+  const uint8_t* s_ntri = reinterpret_cast<const uint8_t*>(s_tab);
+  const int8_t* s_tri = reinterpret_cast<const int8_t*>(s_tab) + 256;
   const int t = threadIdx.x;
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int p = t & 63;
@@ -1241,12 +1517,16 @@ emit_dma7(int64_t n_elem, const double* __restrict__ x, const double* __restrict
   for (int s = 0; s < n_iso; ++s) any = any || cnt[(int64_t)s * n_elem + e] > 0;
   if (!any) return;
   const int64_t base = e * 512;
+  // the two tables (one 4 KiB block: counts, then the case table) and the
+  // four tiles all arrive by direct loads before the one wait below
+  lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * (64 * h + p),
+             reinterpret_cast<double*>(s_tab) + 128 * h);
+  lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * (64 * (h + 2) + p),
+             reinterpret_cast<double*>(s_tab) + 128 * (h + 2));
   dma_tile(field + base, s_f, h, p);
   dma_tile(x + base, s_x, h, p);
   dma_tile(y + base, s_y, h, p);
   dma_tile(z + base, s_z, h, p);
-  for (int q = t; q < 256; q += 128) s_ntri[q] = ntri_tab[q];
-  for (int q = t; q < 256 * kMcMaxTri * 3; q += 128) s_tri[q] = tri_tab[q];
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
   barrier_after_wait();
   for (int s = 0; s < n_iso; ++s) {
@@ -1593,9 +1873,11 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
   bool done = false;
   if constexpr (std::is_same<T, double>::value) {
     if (order == 7) {
-      hipExtLaunchKernelGGL(qcrit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, pt.start,
-                            pt.stop, 0, d, (const T*)x, (const T*)y, (const T*)z, (const T*)u,
-                            (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm, status);
+      hipExtLaunchKernelGGL(qcount4_dma7<false>, dim3((unsigned)n_elem), dim3(256), 0, s,
+                            pt.start, pt.stop, 0, n_elem, tab.eo7, (const T*)x, (const T*)y,
+                            (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om,
+                            (T*)qmm, 0, IsoList<double>{}, (const uint8_t*)nullptr,
+                            (int32_t*)nullptr, (int64_t*)nullptr, status);
       done = true;
     }
   }
@@ -1757,10 +2039,10 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
       if (active)
         hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
       const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
-      hipExtLaunchKernelGGL(qcount_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, pt.start,
-                            pt.stop, 0, n_elem, d, (const T*)x, (const T*)y, (const T*)z,
-                            (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm, n_iso,
-                            iso, tab.ntri, ws.cnt, active, status);
+      hipExtLaunchKernelGGL(qcount4_dma7<true>, dim3((unsigned)n_elem), dim3(256), 0, s,
+                            pt.start, pt.stop, 0, n_elem, tab.eo7, (const T*)x, (const T*)y,
+                            (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om,
+                            (T*)qmm, n_iso, iso, tab.ntri, ws.cnt, active, status);
       phase_done(pt);
       return iso_scan_emit<T>(order, tab, n_elem, x, y, z, q, n_iso, iso, out, nullptr,
                               tri_count, ws, status, s);
