@@ -615,23 +615,6 @@ __device__ __forceinline__ void dma_tile(const double* __restrict__ src, double*
   }
 }
 
-// The coordinate and velocity tiles are separate LDS objects so that the
-// compiler tracks their direct loads separately (a wait for the coordinate
-// tiles does not have to wait for the velocity tiles).
-struct DmaTiles {
-  double (*xyz)[512];   // [3][512]: x, y, z (kept for the vertices)
-  double (*uvw)[512];   // [3][512]: u, v, w (u later holds Q, v the lists)
-  double* S;
-  double* Tt;
-  double* red;
-};
-
-struct DmaWork {
-  double S[Pen<7>::SZ];
-  double Tt[Pen<7>::SZ];
-  double red[4];
-};
-
 // s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt
 // left at their maxima): wait until at most n vector-memory operations of
 // this wave are outstanding.
@@ -654,157 +637,6 @@ __device__ __forceinline__ void barrier_after_wait() {
 __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt untouched
   barrier_after_wait();
-}
-
-// Issue the six tile fetches of an element.  Each wave issues two 16-byte
-// loads per tile, coordinates first; dma_wait_coords() waits for the
-// coordinate tiles only, so the velocity tiles keep arriving during the
-// geometry passes; dma_wait_all() waits for the rest.
-__device__ __forceinline__ void dma_fetch_element(DmaTiles& sm, const double* x, const double* y,
-                                                  const double* z, const double* u,
-                                                  const double* v, const double* w, int64_t base,
-                                                  int h, int lane) {
-  dma_tile(x + base, sm.xyz[0], h, lane);
-  dma_tile(y + base, sm.xyz[1], h, lane);
-  dma_tile(z + base, sm.xyz[2], h, lane);
-  dma_tile(u + base, sm.uvw[0], h, lane);
-  dma_tile(v + base, sm.uvw[1], h, lane);
-  dma_tile(w + base, sm.uvw[2], h, lane);
-}
-// Six coordinate loads per wave were issued before the six velocity loads.
-__device__ __forceinline__ void dma_wait_coords() {
-  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(6));
-  barrier_after_wait();
-}
-__device__ __forceinline__ void dma_wait_all() {
-  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
-  barrier_after_wait();
-}
-
-// One field from its staged tile: the owner gets (f_r, f_s, f_t) at its four
-// nodes.  Wave 0 differentiates the s-lines, wave 1 the t-lines.
-__device__ __forceinline__ void dma_pass(const double* __restrict__ raw,
-                                         const double* __restrict__ d, double* __restrict__ S,
-                                         double* __restrict__ Tt, int h, int p, double (&fr)[4],
-                                         double (&fs)[4], double (&ft)[4]) {
-  using Q = Pen<7>;
-  const int j = p & 7, k = p >> 3;
-  double f[8];
-#pragma unroll
-  for (int ip = 0; ip < 4; ++ip) {
-    const double2 v = *reinterpret_cast<const double2*>(raw + 2 * dma7::slot(k, j, ip));
-    f[2 * ip] = v.x;
-    f[2 * ip + 1] = v.y;
-  }
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) fr[ii] = line_deriv<8>(d, 4 * h + ii, f);
-  double g[8];
-  if (h == 0) {  // s-line at (i, k) = (j, k) of this lane's index
-#pragma unroll
-    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, m, k)];
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj) S[Q::at(j, jj, k)] = line_deriv<8>(d, jj, g);
-  } else {       // t-line at (i, j) = (j, k) of this lane's index
-#pragma unroll
-    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, k, m)];
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) Tt[Q::at(j, k, kk)] = line_deriv<8>(d, kk, g);
-  }
-  lds_barrier();
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    fs[ii] = S[Q::at(4 * h + ii, j, k)];
-    ft[ii] = Tt[Q::at(4 * h + ii, j, k)];
-  }
-  lds_barrier();
-}
-
-// Q and |omega| at the owner's four nodes from the six staged tiles.
-__device__ __forceinline__ bool dma_qcrit(DmaTiles& sm, const double* __restrict__ d, int h,
-                                          int p, double (&qv)[4], double (&om)[4]) {
-  double xr[4], xs[4], xt[4], yr[4], ys[4], yt[4], zr[4], zs[4], zt[4];
-  dma_wait_coords();
-  dma_pass(sm.xyz[0], d, sm.S, sm.Tt, h, p, xr, xs, xt);
-  dma_pass(sm.xyz[1], d, sm.S, sm.Tt, h, p, yr, ys, yt);
-  dma_pass(sm.xyz[2], d, sm.S, sm.Tt, h, p, zr, zs, zt);
-  InvJac<double> kk[4];
-  bool ok = true;
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii)
-    ok = invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii], zt[ii],
-                         kk[ii]) && ok;
-  double fr[4], fs[4], ft[4], a01[4], a02[4], a12[4];
-  dma_wait_all();
-  dma_pass(sm.uvw[0], d, sm.S, sm.Tt, h, p, fr, fs, ft);
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const InvJac<double>& K = kk[ii];
-    const double a00 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
-    a01[ii] = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
-    a02[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
-    qv[ii] = a00 * a00;
-  }
-  dma_pass(sm.uvw[1], d, sm.S, sm.Tt, h, p, fr, fs, ft);
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const InvJac<double>& K = kk[ii];
-    const double a10 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
-    const double a11 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
-    a12[ii] = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
-    qv[ii] = qv[ii] + a11 * a11 + 2.0 * (a01[ii] * a10);
-    const double w3 = a10 - a01[ii];
-    om[ii] = w3 * w3;
-  }
-  dma_pass(sm.uvw[2], d, sm.S, sm.Tt, h, p, fr, fs, ft);
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const InvJac<double>& K = kk[ii];
-    const double a20 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
-    const double a21 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
-    const double a22 = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
-    qv[ii] = -0.5 * (qv[ii] + a22 * a22 + 2.0 * (a02[ii] * a20 + a12[ii] * a21));
-    const double w1 = a21 - a12[ii], w2 = a02[ii] - a20;
-    om[ii] = sqrt(om[ii] + w1 * w1 + w2 * w2);
-  }
-  return ok;
-}
-
-__global__ void __launch_bounds__(128)
-qcrit_dma7(const double* __restrict__ dmat, const double* __restrict__ x,
-           const double* __restrict__ y, const double* __restrict__ z,
-           const double* __restrict__ u, const double* __restrict__ v,
-           const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
-           double* __restrict__ qmm, int32_t* __restrict__ status) {
-  __shared__ double s_xyz[3][512];
-  __shared__ double s_uvw[3][512];
-  __shared__ DmaWork s_work;
-  DmaTiles sm{s_xyz, s_uvw, s_work.S, s_work.Tt, s_work.red};
-  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int p = threadIdx.x & 63;
-  const int64_t base = (int64_t)blockIdx.x * 512;
-  dma_fetch_element(sm, x, y, z, u, v, w, base, h, p);
-  double qv[4], ov[4];
-  int bad = !dma_qcrit(sm, dmat, h, p, qv, ov);
-  const int j = p & 7, k = p >> 3;
-  double mn = pos_inf<double>(), mx = neg_inf<double>();
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const int64_t o = base + (k * 8 + j) * 8 + 4 * h + ii;
-    if (q) q[o] = qv[ii];
-    if (om) om[o] = ov[ii];
-    const double c = qv[ii] != qv[ii] ? neg_inf<double>() : qv[ii];
-    mn = c < mn ? c : mn;
-    mx = c > mx ? c : mx;
-  }
-  bad = __syncthreads_or(bad);
-  if (bad && threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
-  if (qmm) {
-    block_minmax<double, 128>(mn, mx, sm.red);
-    if (threadIdx.x == 0) {
-      qmm[2 * (int64_t)blockIdx.x] = mn;
-      qmm[2 * (int64_t)blockIdx.x + 1] = mx;
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1146,103 +978,12 @@ __global__ void fill_i64(int64_t* __restrict__ p, int n, int64_t value) {
 // and writes them at their offsets.  (A single pass with a decoupled
 // look-back saves that re-read, but on MI355X its chain of device-scope
 // polls across the eight XCDs cost more than the re-read does.)
-
-__device__ __forceinline__ int dma_cell_case(const double* __restrict__ qt, int ci, int cj,
-                                             int ck, double c) {
-  int cs = 0;
-#pragma unroll
-  for (int vtx = 0; vtx < 8; ++vtx)
-    cs |= (qt[dma7::at(ci + (vtx & 1), cj + ((vtx >> 1) & 1), ck + (vtx >> 2))] > c) << vtx;
-  return cs;
-}
-
-__global__ void __launch_bounds__(128)
-qcount_dma7(int64_t n_elem, const double* __restrict__ dmat, const double* __restrict__ x,
-            const double* __restrict__ y, const double* __restrict__ z,
-            const double* __restrict__ u, const double* __restrict__ v,
-            const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
-            double* __restrict__ qmm, int n_iso, IsoList<double> iso,
-            const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
-            int64_t* __restrict__ active, int32_t* __restrict__ status) {
-  constexpr int NC = 343, ROUNDS = 3;
-  __shared__ double s_xyz[3][512];
-  __shared__ double s_uvw[3][512];
-  __shared__ DmaWork s_work;
-  __shared__ uint8_t s_ntri[256];
-  __shared__ int32_t s_wave[4];
-  DmaTiles sm{s_xyz, s_uvw, s_work.S, s_work.Tt, s_work.red};
-  const int t = threadIdx.x;
-  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int p = t & 63;
-  const int64_t e = blockIdx.x;
-  const int64_t base = e * 512;
-  dma_fetch_element(sm, x, y, z, u, v, w, base, h, p);
-  s_ntri[t] = ntri_tab[t];
-  s_ntri[t + 128] = ntri_tab[t + 128];
-
-  double qv[4], ov[4];
-  int bad = !dma_qcrit(sm, dmat, h, p, qv, ov);
-  double* QT = s_uvw[0];   // free after the u pass
-  const int j = p & 7, k = p >> 3;
-  double mn = pos_inf<double>(), mx = neg_inf<double>();
-#pragma unroll
-  for (int ii = 0; ii < 4; ++ii) {
-    const int i = 4 * h + ii;
-    const int64_t o = base + (k * 8 + j) * 8 + i;
-    if (q) q[o] = qv[ii];
-    if (om) om[o] = ov[ii];
-    QT[dma7::at(i, j, k)] = qv[ii];
-    const double c = qv[ii] != qv[ii] ? neg_inf<double>() : qv[ii];
-    mn = c < mn ? c : mn;
-    mx = c > mx ? c : mx;
-  }
-  bad = __syncthreads_or(bad);
-  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
-  block_minmax<double, 128>(mn, mx, s_work.red);
-  if (qmm && t == 0) {
-    qmm[2 * e] = mn;
-    qmm[2 * e + 1] = mx;
-  }
-  for (int s = 0; s < n_iso; ++s) {
-    const double c = iso.v[s];
-    int nt = 0, act = 0;
-    if ((mx > c) && !(mn > c)) {
-#pragma unroll
-      for (int r = 0; r < ROUNDS; ++r) {
-        const int cell = r * 128 + t;
-        if (cell < NC) {
-          const int cs = dma_cell_case(QT, cell % 7, (cell / 7) % 7, cell / 49, c);
-          nt += s_ntri[cs];
-          act += (cs != 0 && cs != 255);
-        }
-      }
-    }
-    nt = wave_sum(nt);
-    act = wave_sum(act);
-    if (p == 0) {
-      s_wave[h] = nt;
-      s_wave[2 + h] = act;
-    }
-    __syncthreads();
-    if (t == 0) {
-      cnt[(int64_t)s * n_elem + e] = s_wave[0] + s_wave[1];
-      const int a = s_wave[2] + s_wave[3];
-      if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// N = 7, FP64, four waves per element: two nodes per lane
-// ---------------------------------------------------------------------------
 //
-// The same staging and LDS layout as the two-wave kernels, with wave h
-// (0..3) owning nodes i = h and 7 - h of r-line (j, k) = lane.  Waves 0, 1
-// differentiate the s-lines and waves 2, 3 the t-lines, half a line each,
-// in the even-odd form of D.  A lane holds half the state of the two-wave
-// form, so twice as many waves fit on a SIMD to hide the load and LDS
-// latencies.
+// qcount_dma7 runs four waves per element on the swizzled tile layout
+// above, wave h (0..3) owning nodes i = h and 7 - h of r-line (j, k) =
+// lane.  Waves 0, 1 differentiate the s-lines and waves 2, 3 the t-lines,
+// half a line each, in the even-odd form of D.  With two nodes per lane
+// (112 VGPRs) four waves fit on a SIMD to hide the load and LDS latencies.
 
 // One 4 KiB tile with four waves: wave h issues chunk group h.
 __device__ __forceinline__ void dma_tile4(const double* __restrict__ src, double* raw, int h,
@@ -1330,11 +1071,43 @@ __device__ __forceinline__ void dma_pass4(const double* __restrict__ raw,
 // computation past later barriers, which would keep its inputs live).
 __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
 
+// Butterfly reductions over a wave through ds_bpermute, with the partner
+// addresses ((lane ^ 2^k) * 4) computed once per thread: one LDS permute
+// per 32 bits and one VALU operation per step.
+struct WaveXor {
+  int a[6];
+};
+__device__ __forceinline__ WaveXor wave_xor_addrs(int lane) {
+  WaveXor w;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) w.a[k] = (lane ^ (1 << k)) << 2;
+  return w;
+}
+__device__ __forceinline__ double bperm_f64(int addr, double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// (no NaN reaches these: callers map NaN to -inf first)
+__device__ __forceinline__ void wave_minmax_f64(const WaveXor& w, double& mn, double& mx) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    mn = fmin(mn, bperm_f64(w.a[k], mn));
+    mx = fmax(mx, bperm_f64(w.a[k], mx));
+  }
+}
+__device__ __forceinline__ int wave_sum_i32(const WaveXor& w, int v) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v += __builtin_amdgcn_ds_bpermute(w.a[k], v);
+  return v;
+}
+
 // COUNT: also count every isovalue's triangles and active cells per element
 // from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
 template <bool COUNT>
 __global__ void __launch_bounds__(256)
-qcount4_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restrict__ x,
+qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restrict__ x,
              const double* __restrict__ y, const double* __restrict__ z,
              const double* __restrict__ u, const double* __restrict__ v,
              const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
@@ -1436,22 +1209,30 @@ qcount4_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __rest
     mn = c < mn ? c : mn;
     mx = c > mx ? c : mx;
   }
-  bad = __syncthreads_or(bad);
+  const WaveXor wx = wave_xor_addrs(p);
+  wave_minmax_f64(wx, mn, mx);
+  if (p == 0) {
+    s_red[h] = mn;
+    s_red[4 + h] = mx;
+  }
+  bad = __syncthreads_or(bad);   // also publishes the Q tile and s_red
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
-  block_minmax<double, 256>(mn, mx, s_red);   // its barriers also publish the Q tile
+  mn = fmin(fmin(s_red[0], s_red[1]), fmin(s_red[2], s_red[3]));
+  mx = fmax(fmax(s_red[4], s_red[5]), fmax(s_red[6], s_red[7]));
   if (qmm && t == 0) {
     qmm[2 * e] = mn;
     qmm[2 * e + 1] = mx;
   }
   if constexpr (COUNT) {
-    // the eight corner values of this thread's cells (t and t + 256), once
+    // the eight corner values of this thread's cells, loaded once: cell t,
+    // and cell t + 256 for the threads t < 87 (waves 0 and 1 only)
+    constexpr int NC2 = NC - 256;
+    const bool two = t < NC2;
     double cv[2][8];
-    bool has[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-      const int cell = r * 256 + t;
-      has[r] = cell < NC;
-      const int cc = has[r] ? cell : 0;
+      if (r == 1 && h >= 2) break;
+      const int cc = r == 0 ? t : (two ? t + 256 : t);
       const int ci = cc % 7, cj = (cc / 7) % 7, ck = cc / 49;
 #pragma unroll
       for (int vtx = 0; vtx < 8; ++vtx)
@@ -1459,29 +1240,25 @@ qcount4_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __rest
     }
     for (int s = 0; s < n_iso; ++s) {
       const double c = iso.v[s];
-      int nt = 0, act = 0;
+      // triangles in the low 16 bits, active cells above (one wave sum)
+      int packed = 0;
       if ((mx > c) && !(mn > c)) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
+          if (r == 1 && h >= 2) break;
           int cs = 0;
 #pragma unroll
-          for (int vtx = 0; vtx < 8; ++vtx) cs |= (cv[r][vtx] > c) << vtx;
-          if (has[r]) {
-            nt += s_ntri[cs];
-            act += (cs != 0 && cs != 255);
-          }
+          for (int vtx = 7; vtx >= 0; --vtx) cs = cs + cs + (cv[r][vtx] > c);
+          if (r == 0 || two) packed += s_ntri[cs] + ((cs != 0 && cs != 255) << 16);
         }
       }
-      nt = wave_sum(nt);
-      act = wave_sum(act);
-      if (p == 0) {
-        s_wave[h] = nt;
-        s_wave[4 + h] = act;
-      }
+      packed = wave_sum_i32(wx, packed);
+      if (p == 0) s_wave[h] = packed;
       __syncthreads();
       if (t == 0) {
-        cnt[(int64_t)s * n_elem + e] = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-        const int a = s_wave[4] + s_wave[5] + s_wave[6] + s_wave[7];
+        const int sum = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        cnt[(int64_t)s * n_elem + e] = sum & 0xffff;
+        const int a = sum >> 16;
         if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
       }
       __syncthreads();
@@ -1873,7 +1650,7 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
   bool done = false;
   if constexpr (std::is_same<T, double>::value) {
     if (order == 7) {
-      hipExtLaunchKernelGGL(qcount4_dma7<false>, dim3((unsigned)n_elem), dim3(256), 0, s,
+      hipExtLaunchKernelGGL(qcount_dma7<false>, dim3((unsigned)n_elem), dim3(256), 0, s,
                             pt.start, pt.stop, 0, n_elem, tab.eo7, (const T*)x, (const T*)y,
                             (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om,
                             (T*)qmm, 0, IsoList<double>{}, (const uint8_t*)nullptr,
@@ -2039,7 +1816,7 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
       if (active)
         hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
       const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
-      hipExtLaunchKernelGGL(qcount4_dma7<true>, dim3((unsigned)n_elem), dim3(256), 0, s,
+      hipExtLaunchKernelGGL(qcount_dma7<true>, dim3((unsigned)n_elem), dim3(256), 0, s,
                             pt.start, pt.stop, 0, n_elem, tab.eo7, (const T*)x, (const T*)y,
                             (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om,
                             (T*)qmm, n_iso, iso, tab.ntri, ws.cnt, active, status);
