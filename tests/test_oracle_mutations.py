@@ -231,3 +231,43 @@ def test_non_strict_comparison_is_caught():
         return field >= field.dtype.type(iso)
     with patched(mc, "above", bad):
         _fails(pin_ties)
+
+
+# --------------------------------------------------------------------------
+# C0 averaging and welding (oracle/c0.py)
+# --------------------------------------------------------------------------
+
+def test_c0_sum_without_division_is_caught():
+    import test_oracle_c0 as T
+    from oracle import c0
+
+    def bad(field, gid):
+        f = np.asarray(field)
+        g = np.asarray(gid).ravel()
+        s = np.zeros(int(g.max()) + 1, dtype=f.dtype)
+        np.add.at(s, g, f.ravel())
+        return s[g].reshape(f.shape)             # dssum, not the average
+    with patched(c0, "dsavg", bad):
+        _fails(T.test_two_element_example_exact)
+
+
+def test_element_local_keys_break_the_weld():
+    import test_oracle_c0 as T
+    from oracle import c0
+
+    def bad(local_keys, gid, order):
+        return np.asarray(local_keys, dtype=np.uint64)   # ids of the element copy
+    with patched(c0, "global_edge_keys", bad):
+        _fails(T.test_welded_sphere_is_closed_manifold_across_elements)
+
+
+def test_last_occurrence_weld_is_caught():
+    import test_oracle_c0 as T
+    from oracle import c0
+    orig = c0.weld
+
+    def bad(tri_xyz, keys):
+        v, i = orig(tri_xyz, keys)
+        return v[::-1].copy(), (v.shape[0] - 1 - i)      # reversed vertex order
+    with patched(c0, "weld", bad):
+        _fails(T.test_welded_sphere_is_closed_manifold_across_elements)

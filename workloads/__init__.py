@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "gll_points", "axis_lattice", "box_mesh", "element_axes", "tgv_velocity",
     "channel_modes", "channel_velocity", "warp", "tgv_config", "channel_config",
-    "CHANNEL_SHAPE", "TGV_SHAPE",
+    "lattice_gid", "CHANNEL_SHAPE", "TGV_SHAPE",
 ]
 
 TGV_SHAPE = (8, 8, 8)          # Taylor-Green box [0, 2 pi]^3, 512 elements
@@ -88,6 +88,22 @@ def box_mesh(shape, n, bounds, stretch=(None, None, None), elements=None,
         import torch
         out = [torch.from_numpy(c).to(device) for c in out]
     return tuple(out)
+
+
+def lattice_gid(shape, n, elements=None):
+    """Global node ids of the box meshes above (int64, shape (E, P, P, P)):
+    stored node (i, j, k) of element (ex, ey, ez) is lattice point
+    (gx, gy, gz) = (ex n + i, ey n + j, ez n + k), numbered
+    gx + Lx (gy + Ly gz) with L = shape * n + 1.  Coincident copies on
+    element faces, edges and corners get equal ids."""
+    ex, ey, ez = element_axes(shape, elements)
+    p = n + 1
+    lx, ly = shape[0] * n + 1, shape[1] * n + 1
+    loc = np.arange(p)
+    gx = (ex[:, None] * n + loc[None, :])[:, None, None, :]
+    gy = (ey[:, None] * n + loc[None, :])[:, None, :, None]
+    gz = (ez[:, None] * n + loc[None, :])[:, :, None, None]
+    return np.ascontiguousarray((gx + lx * (gy + ly * gz)).astype(np.int64))
 
 
 def _lib(a):
