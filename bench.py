@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--cpu-baseline", choices=("on", "off"), default="on")
     ap.add_argument("--precision-modes", choices=("on", "off"), default="on",
                     help="also time FP32 and the mixed-precision modes on the same snapshot")
+    ap.add_argument("--c0", choices=("on", "off"), default="on",
+                    help="also time C0 averaging of Q and welding of the isosurfaces")
     ap.add_argument("--cpu-elements", type=int, default=16384,
                     help="elements of the snapshot the CPU oracle is timed on")
     ap.add_argument("--quiet", action="store_true")
@@ -289,11 +291,63 @@ def main():
         "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
     }
 
+    if args.c0 == "on" and args.dtype == "f64":
+        result["c0"] = c0_timing(args, sem, fields, q, isos, n)
     if args.precision_modes == "on" and args.dtype == "f64":
         result["precision_modes"] = precision_modes(args, sem, fields, isos, n_elem, points)
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(args, fields, isos, n, n_elem)
     print(json.dumps(result), flush=True)
+
+
+def c0_timing(args, sem, fields, q, isos, n):
+    """C0 averaging of Q over the shared GLL nodes (sem_dsavg with a
+    gather-scatter built once by sem_gs_setup), the isosurfaces of the
+    averaged Q with edge keys, their global keys, and welding."""
+    import torch
+
+    import workloads as W
+    dev = q.device
+    gid = torch.from_numpy(W.lattice_gid(W.CHANNEL_SHAPE, n)).to(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    gs = sem.GatherScatter(gid)
+    e1.record()
+    torch.cuda.synchronize()
+    setup_ms = e0.elapsed_time(e1)
+    qa = torch.empty_like(q)
+    reps = max(3, args.steps // 4)
+    sem.dsavg(q, gs, out=qa)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        sem.dsavg(q, gs, out=qa)
+    e1.record()
+    torch.cuda.synchronize()
+    avg_ms = e0.elapsed_time(e1) / reps
+    x, y, z = fields[:3]
+    r = sem.isosurface(x, y, z, qa, isos, edge_keys=True)
+    keys = sem.global_edge_keys(r["edge_key"], gid)
+    sem.weld(r["tri_xyz"], keys)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        keys = sem.global_edge_keys(r["edge_key"], gid)
+        verts, idx = sem.weld(r["tri_xyz"], keys)
+    e1.record()
+    torch.cuda.synchronize()
+    weld_ms = e0.elapsed_time(e1) / reps
+    n_tri = int(r["tri_xyz"].shape[0])
+    log(args, f"C0: gather-scatter setup {setup_ms:.3f} ms, dsavg {avg_ms:.4f} ms, "
+              f"global keys + weld {weld_ms:.4f} ms: {n_tri} triangles -> "
+              f"{int(verts.shape[0])} vertices")
+    n_global = gs.n_global
+    del gid, gs, qa
+    return {"gs_setup_ms": round(setup_ms, 4), "dsavg_ms": round(avg_ms, 5),
+            "keys_weld_ms": round(weld_ms, 5), "triangles": n_tri,
+            "welded_vertices": int(verts.shape[0]), "n_global": n_global}
 
 
 def precision_modes(args, sem, fields, isos, n_elem, points):

@@ -75,7 +75,12 @@ enum {
   SEM_ERR_DTYPE = -6       /* dtype is not one of the sem_dtype values       */
 };
 
-enum { SEM_FLAG_BAD_JACOBIAN = 1, SEM_FLAG_TRI_OVERFLOW = 2 };
+enum {
+  SEM_FLAG_BAD_JACOBIAN = 1,   /* det J <= 0 at some node                         */
+  SEM_FLAG_TRI_OVERFLOW = 2,   /* triangles did not fit (counts stay exact)       */
+  SEM_FLAG_BAD_ID = 4,         /* a node id or edge key outside its valid range   */
+  SEM_FLAG_VERT_OVERFLOW = 8   /* welded vertices did not fit (count stays exact) */
+};
 
 #define SEM_MIN_ORDER 1
 #define SEM_MAX_ORDER 9
@@ -222,6 +227,61 @@ int sem_extract(int64_t n_elem, int order, sem_dtype dt,
                 int64_t* tri_count, int64_t* active_cells,
                 void* workspace, size_t workspace_bytes,
                 int32_t* status_word, void* stream);
+
+/* ---------------------------------------------------------------------
+ * C0 averaging over shared GLL nodes and welded isosurface output
+ * ---------------------------------------------------------------------
+ * Elements store their own copy of every node.  gid[e][node] (DEVICE int64,
+ * the field layout) gives each stored node a global id in [0, n_global);
+ * coincident copies share an id (NekRS keeps such ids for its gather-
+ * scatter).  Derived fields computed per element differ between copies; the
+ * direct-stiffness average (Deville, Fischer & Mund 2002, ch. 4: the
+ * gather-scatter sum divided by the multiplicity) replaces every copy by the
+ * mean over all copies of its node, so isosurfaces close across element
+ * faces. */
+
+/* Bytes of the buffer sem_gs_setup fills (0 for invalid arguments). */
+size_t sem_gs_workspace_bytes(int64_t n_elem, int order, int64_t n_global);
+
+/* Build the gather-scatter structure of gid into the caller's DEVICE buffer
+ * gs (the copies of every global node, in increasing storage order).  The
+ * buffer is read by sem_dsavg until the caller frees or rebuilds it.  Ids
+ * outside [0, n_global) set SEM_FLAG_BAD_ID and are left out.  Requires
+ * n_global < 2^32 - 1. */
+int sem_gs_setup(int64_t n_elem, int order, const int64_t* gid, int64_t n_global, void* gs,
+                 size_t gs_bytes, int32_t* status_word, void* stream);
+
+/* out = direct-stiffness average of field (both [n_elem][(N+1)^3] of dtype
+ * dt; mixed dtypes mean FP32): for each global node, the copies' values are
+ * summed one at a time in increasing storage order in dt, divided by their
+ * number, and written to every copy.  out may equal field. */
+int sem_dsavg(int64_t n_elem, int order, sem_dtype dt, const void* gs, int64_t n_global,
+              const void* field, void* out, void* stream);
+
+/* Global keys of n_ref element-local edge keys (as written by
+ * sem_isosurface: (e (N+1)^3 + n_lo) * 3 + axis):
+ *   key = (min(gid_lo, gid_hi) << 32) | max(gid_lo, gid_hi).
+ * Vertices on the same global edge get the same key in every element.  A
+ * local key outside the n_elem elements, or ids outside [0, 2^32 - 1), give
+ * the key 0xffff...ff and set SEM_FLAG_BAD_ID. */
+int sem_global_edge_keys(int64_t n_ref, int order, int64_t n_elem, const uint64_t* local_keys,
+                         const int64_t* gid, uint64_t* global_keys, int32_t* status_word,
+                         void* stream);
+
+/* Bytes of device workspace sem_weld needs for n_ref = 3 * triangles. */
+size_t sem_weld_workspace_bytes(int64_t n_ref);
+
+/* Weld a triangle soup (tri_xyz [n_ref / 3][3][3] of dtype dt, keys [n_ref]
+ * global edge keys): the distinct keys, numbered in order of first
+ * occurrence (corner r = 3 * triangle + corner), are the vertices; vertex v
+ * gets the coordinates of its first occurrence (vert_xyz [vert_capacity][3]),
+ * and tri_index[r] (DEVICE int64 [n_ref]) the index of corner r's key.
+ * *n_vert (DEVICE int64) is exact even when vertices beyond vert_capacity are
+ * dropped (SEM_FLAG_VERT_OVERFLOW).  A key of all ones sets SEM_FLAG_BAD_ID
+ * and gets index -1.  The result does not depend on scheduling. */
+int sem_weld(int64_t n_ref, sem_dtype dt, const void* tri_xyz, const uint64_t* keys,
+             int64_t* tri_index, void* vert_xyz, int64_t vert_capacity, int64_t* n_vert,
+             void* workspace, size_t workspace_bytes, int32_t* status_word, void* stream);
 
 /* ---------------------------------------------------------------------
  * Kernel-phase timing (a tracing aid, not part of the method)

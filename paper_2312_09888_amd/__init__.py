@@ -11,5 +11,6 @@ from ._lib import (  # noqa: F401
     MIXED, SEM_F32, SEM_F64, SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_MAX_ORDER,
     SEM_MIN_ORDER, SemError, derivs, extract, extract_into, extract_workspace_bytes, gll,
     init, isosurface, isosurface_into, lib, mc_table, phase_name, qcrit, status_str,
-    timing_begin, timing_end, workspace_bytes,
+    timing_begin, timing_end, workspace_bytes, GatherScatter, dsavg, global_edge_keys, weld,
+    SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW,
 )

@@ -22,7 +22,7 @@ MIXED = {"bf16": SEM_MIXED_BF16, "fp16": SEM_MIXED_FP16, "bf16x3": SEM_MIXED_BF1
 SEM_OK = 0
 SEM_ERR_ARG, SEM_ERR_ORDER, SEM_ERR_NOT_INIT = -1, -2, -3
 SEM_ERR_HIP, SEM_ERR_WORKSPACE, SEM_ERR_DTYPE = -4, -5, -6
-SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW = 1, 2
+SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW = 1, 2, 4, 8
 SEM_MIN_ORDER, SEM_MAX_ORDER = 1, 9
 SEM_MAX_ISO = 64
 SEM_MC_MAX_TRI = 5
@@ -34,6 +34,8 @@ EXPORTS = (
     "sem_derivs", "sem_qcrit", "sem_isosurface_workspace_bytes", "sem_isosurface",
     "sem_extract_workspace_bytes", "sem_extract",
     "sem_phase_name", "sem_timing_begin", "sem_timing_end",
+    "sem_gs_workspace_bytes", "sem_gs_setup", "sem_dsavg", "sem_global_edge_keys",
+    "sem_weld_workspace_bytes", "sem_weld",
 )
 
 
@@ -88,6 +90,18 @@ def lib():
         L.sem_timing_begin.argtypes = [i32]
         L.sem_timing_end.restype = i64
         L.sem_timing_end.argtypes = [vp, vp, i32]
+        L.sem_gs_workspace_bytes.restype = ctypes.c_size_t
+        L.sem_gs_workspace_bytes.argtypes = [i64, i32, i64]
+        L.sem_gs_setup.restype = i32
+        L.sem_gs_setup.argtypes = [i64, i32, vp, i64, vp, ctypes.c_size_t, vp, vp]
+        L.sem_dsavg.restype = i32
+        L.sem_dsavg.argtypes = [i64, i32, i32, vp, i64, vp, vp, vp]
+        L.sem_global_edge_keys.restype = i32
+        L.sem_global_edge_keys.argtypes = [i64, i32, i64, vp, vp, vp, vp, vp]
+        L.sem_weld_workspace_bytes.restype = ctypes.c_size_t
+        L.sem_weld_workspace_bytes.argtypes = [i64]
+        L.sem_weld.restype = i32
+        L.sem_weld.argtypes = [i64, i32, vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp, vp]
         del dbl
         _lib = L
     return _lib
@@ -427,3 +441,82 @@ def timing_end():
         raise SemError(int(rc), "sem_timing_end")
     return ({phase_name(k): (float(tot[k]), int(cnt[k])) for k in range(SEM_NUM_PHASES)},
             int(rc))
+
+
+# ---------------------------------------------------------------------------
+# C0 averaging and welded output
+# ---------------------------------------------------------------------------
+
+class GatherScatter:
+    """Device gather-scatter structure of a global node numbering
+    (sem_gs_setup); keeps the buffer it was built in."""
+
+    def __init__(self, gid, n_global=None, status=None):
+        torch = _torch()
+        if gid.dtype != torch.int64 or not gid.is_cuda or not gid.is_contiguous():
+            raise ValueError("gid must be a contiguous int64 tensor on a GPU")
+        self.order = _order_of(gid)
+        self.n_elem = gid.shape[0]
+        self.device = gid.device
+        if n_global is None:
+            n_global = int(gid.max().item()) + 1 if gid.numel() else 0
+        self.n_global = int(n_global)
+        init(gid.device.index)
+        nb = int(lib().sem_gs_workspace_bytes(self.n_elem, self.order, self.n_global))
+        if nb == 0 and self.n_elem > 0:
+            raise SemError(SEM_ERR_ARG, "sem_gs_workspace_bytes")
+        self.buf = torch.empty(max(nb, 1), dtype=torch.uint8, device=gid.device)
+        _status_check(status, gid)
+        with torch.cuda.device(gid.device):
+            _check(lib().sem_gs_setup(self.n_elem, self.order, _ptr(gid), self.n_global,
+                                      _ptr(self.buf), self.buf.numel(), _ptr(status),
+                                      _stream(gid)), "sem_gs_setup")
+
+
+def dsavg(field, gs, out=None):
+    """Direct-stiffness average of a field over the gather-scatter's nodes."""
+    torch = _torch()
+    _field_check(field, out)
+    if tuple(field.shape) != (gs.n_elem,) + (gs.order + 1,) * 3 or field.device != gs.device:
+        raise ValueError("field does not match the gather-scatter's mesh")
+    if out is None:
+        out = torch.empty_like(field)
+    with torch.cuda.device(field.device):
+        _check(lib().sem_dsavg(gs.n_elem, gs.order, _dtype_code(field), _ptr(gs.buf),
+                               gs.n_global, _ptr(field), _ptr(out), _stream(field)),
+               "sem_dsavg")
+    return out
+
+
+def global_edge_keys(local_keys, gid, status=None):
+    """Global keys (uint64 stored as int64) of element-local edge keys."""
+    torch = _torch()
+    order = _order_of(gid)
+    out = torch.empty_like(local_keys)
+    with torch.cuda.device(gid.device):
+        _check(lib().sem_global_edge_keys(local_keys.numel(), order, gid.shape[0],
+                                          _ptr(local_keys), _ptr(gid), _ptr(out),
+                                          _ptr(status), _stream(gid)),
+               "sem_global_edge_keys")
+    return out
+
+
+def weld(tri_xyz, keys, status=None):
+    """(vertices (V, 3), indices (T, 3) int64) of a soup with global keys."""
+    torch = _torch()
+    n_ref = keys.numel()
+    if tri_xyz.numel() != 3 * n_ref:
+        raise ValueError("tri_xyz must hold 3 coordinates per key")
+    dev = keys.device
+    init(dev.index)
+    ws = torch.empty(max(int(lib().sem_weld_workspace_bytes(n_ref)), 1), dtype=torch.uint8,
+                     device=dev)
+    idx = torch.empty((n_ref // 3, 3), dtype=torch.int64, device=dev)
+    verts = torch.empty((max(n_ref, 1), 3), dtype=tri_xyz.dtype, device=dev)
+    n_vert = torch.zeros(1, dtype=torch.int64, device=dev)
+    code = SEM_F64 if tri_xyz.dtype == torch.float64 else SEM_F32
+    with torch.cuda.device(dev):
+        _check(lib().sem_weld(n_ref, code, _ptr(tri_xyz), _ptr(keys), _ptr(idx), _ptr(verts),
+                              n_ref, _ptr(n_vert), _ptr(ws), ws.numel(), _ptr(status),
+                              _stream(keys)), "sem_weld")
+    return verts[:int(n_vert.item())], idx

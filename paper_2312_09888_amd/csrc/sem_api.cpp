@@ -333,6 +333,81 @@ int sem_isosurface(int64_t n_elem, int order, sem_dtype dt, const void* x, const
   return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
 }
 
+size_t sem_gs_workspace_bytes(int64_t n_elem, int order, int64_t n_global) {
+  if (n_elem < 0 || order < SEM_MIN_ORDER || order > SEM_MAX_ORDER || n_global < 0 ||
+      n_global >= (int64_t)0xffffffffll)
+    return 0;
+  const int64_t p = order + 1;
+  return gs_layout(nullptr, n_elem * p * p * p, n_global).bytes;
+}
+
+int sem_gs_setup(int64_t n_elem, int order, const int64_t* gid, int64_t n_global, void* gs,
+                 size_t gs_bytes, int32_t* status_word, void* stream) {
+  if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+  if (n_elem < 0 || n_elem > (int64_t)0x7fffffff || n_global < 0 ||
+      n_global >= (int64_t)0xffffffffll)
+    return SEM_ERR_ARG;
+  if (n_elem > 0 && !gid) return SEM_ERR_ARG;
+  const int64_t p = order + 1;
+  const GsLayout l = gs_layout(gs, n_elem * p * p * p, n_global);
+  if (!gs || gs_bytes < l.bytes) return SEM_ERR_WORKSPACE;
+  if (!current_tables()) return SEM_ERR_NOT_INIT;
+  const hipError_t e = launch_gs_setup(n_elem * p * p * p, gid, n_global, l, status_word,
+                                       static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+int sem_dsavg(int64_t n_elem, int order, sem_dtype dt, const void* gs, int64_t n_global,
+              const void* field, void* out, void* stream) {
+  const int rc = check_common(n_elem, order, dt, false);
+  if (rc) return rc;
+  if (n_global < 0 || n_global >= (int64_t)0xffffffffll) return SEM_ERR_ARG;
+  if (n_global == 0) return SEM_OK;
+  if (!gs || !field || !out) return SEM_ERR_ARG;
+  if (!current_tables()) return SEM_ERR_NOT_INIT;
+  const int64_t p = order + 1;
+  const GsLayout l = gs_layout(const_cast<void*>(gs), n_elem * p * p * p, n_global);
+  const hipError_t e = launch_dsavg(dt == SEM_F64 ? SEM_F64 : SEM_F32, n_global, l, field, out,
+                                    static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+int sem_global_edge_keys(int64_t n_ref, int order, int64_t n_elem, const uint64_t* local_keys,
+                         const int64_t* gid, uint64_t* global_keys, int32_t* status_word,
+                         void* stream) {
+  if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+  if (n_ref < 0 || n_elem < 0) return SEM_ERR_ARG;
+  if (n_ref == 0) return SEM_OK;
+  if (!local_keys || !gid || !global_keys) return SEM_ERR_ARG;
+  if (!current_tables()) return SEM_ERR_NOT_INIT;
+  const hipError_t e = launch_global_keys(n_ref, order, n_elem, local_keys, gid, global_keys,
+                                          status_word, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+size_t sem_weld_workspace_bytes(int64_t n_ref) {
+  if (n_ref < 0 || n_ref > (int64_t)0x3fffffff) return 0;
+  return weld_layout(nullptr, n_ref).bytes;
+}
+
+int sem_weld(int64_t n_ref, sem_dtype dt, const void* tri_xyz, const uint64_t* keys,
+             int64_t* tri_index, void* vert_xyz, int64_t vert_capacity, int64_t* n_vert,
+             void* workspace, size_t workspace_bytes, int32_t* status_word, void* stream) {
+  if (dt < SEM_F64 || dt > SEM_MIXED_FP16X3) return SEM_ERR_DTYPE;
+  if (n_ref < 0 || n_ref % 3 != 0 || n_ref > (int64_t)0x3fffffff || vert_capacity < 0 ||
+      !n_vert)
+    return SEM_ERR_ARG;
+  if (n_ref > 0 && (!tri_xyz || !keys || !tri_index)) return SEM_ERR_ARG;
+  if (vert_capacity > 0 && !vert_xyz) return SEM_ERR_ARG;
+  const WeldLayout w = weld_layout(workspace, n_ref);
+  if (!workspace || workspace_bytes < w.bytes) return SEM_ERR_WORKSPACE;
+  if (!current_tables()) return SEM_ERR_NOT_INIT;
+  const hipError_t e = launch_weld(n_ref, dt == SEM_F64 ? SEM_F64 : SEM_F32, tri_xyz, keys,
+                                   tri_index, vert_xyz, vert_capacity, n_vert, w, status_word,
+                                   static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
 const char* sem_phase_name(int phase) {
   switch (phase) {
     case SEM_PHASE_QCRIT: return "qcrit";

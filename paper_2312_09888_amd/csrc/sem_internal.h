@@ -53,6 +53,43 @@ struct IsoWorkspace {
 IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso);
 int64_t scan_blocks(int64_t count);
 
+// Exclusive prefix of count int32 values into offs[0..count] (offs[count] =
+// total); partial holds scan_blocks(count) + 1 int64.
+hipError_t launch_exclusive_scan(const int32_t* cnt, int64_t count, int64_t* partial,
+                                 int64_t* offs, hipStream_t s);
+
+// sem_c0.hip: gather-scatter structure built by sem_gs_setup in the
+// caller's buffer, C0 averaging, global edge keys, welding.
+struct GsLayout {
+  int32_t* cnt;       // [n_global] copies per global node (then a fill cursor)
+  int64_t* rowptr;    // [n_global + 1] first copy of each global node
+  int64_t* partial;   // scan partials
+  int64_t* col;       // [n_nodes] storage index of each copy, by node, ascending
+  size_t bytes;
+};
+GsLayout gs_layout(void* base, int64_t n_nodes, int64_t n_global);
+hipError_t launch_gs_setup(int64_t n_nodes, const int64_t* gid, int64_t n_global,
+                           const GsLayout& gs, int32_t* status, hipStream_t s);
+hipError_t launch_dsavg(sem_dtype dt, int64_t n_global, const GsLayout& gs, const void* in,
+                        void* out, hipStream_t s);
+hipError_t launch_global_keys(int64_t n_ref, int order, int64_t n_elem, const uint64_t* local,
+                              const int64_t* gid, uint64_t* global, int32_t* status,
+                              hipStream_t s);
+struct WeldLayout {
+  uint64_t* key;      // [cap] hash table keys (all ones = empty)
+  uint64_t* pos;      // [cap] first corner holding the key
+  int32_t* slot;      // [n_ref] table slot of each corner
+  int32_t* flag;      // [n_ref] 1 at a key's first corner
+  int64_t* offs;      // [n_ref + 1] exclusive prefix of flag
+  int64_t* partial;
+  int64_t cap;
+  size_t bytes;
+};
+WeldLayout weld_layout(void* base, int64_t n_ref);
+hipError_t launch_weld(int64_t n_ref, sem_dtype dt, const void* tri_xyz, const uint64_t* keys,
+                       int64_t* tri_index, void* vert_xyz, int64_t vert_cap, int64_t* n_vert,
+                       const WeldLayout& w, int32_t* status, hipStream_t s);
+
 // Kernel-phase timing (sem_api.cpp).  phase_timer() hands out two events
 // when timing is on for the current device (else two nulls): the phase's
 // first kernel is launched with `start`, its last with `stop`, through

@@ -1842,6 +1842,17 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
 
 int64_t scan_blocks(int64_t count) { return count <= 0 ? 1 : (count + kScanTile - 1) / kScanTile; }
 
+hipError_t launch_exclusive_scan(const int32_t* cnt, int64_t count, int64_t* partial,
+                                 int64_t* offs, hipStream_t s) {
+  const int64_t nb = scan_blocks(count);
+  hipLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cnt, count,
+                     partial);
+  hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, partial, nb);
+  hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cnt, count,
+                     partial, nb, offs);
+  return hipGetLastError();
+}
+
 hipError_t launch_derivs(int order, sem_dtype dt, const DeviceTables& tab, int64_t n_elem,
                          const void* x, const void* y, const void* z, const void* f, void* gx,
                          void* gy, void* gz, int32_t* status, hipStream_t s) {

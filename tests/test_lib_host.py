@@ -227,3 +227,29 @@ def test_mixed_modes_need_order_7_where_they_differentiate():
     for name, val in (("SEM_MIXED_BF16", 2), ("SEM_MIXED_FP16", 3), ("SEM_MIXED_BF16X3", 4),
                       ("SEM_MIXED_FP16X3", 5)):
         assert re.search(rf"{name} = {val}\b", text), name
+
+
+def test_c0_argument_errors():
+    L = sem.lib()
+    f = FAKE
+    assert L.sem_gs_setup(4, 0, f, 10, f, 1 << 20, None, None) == _lib.SEM_ERR_ORDER
+    assert L.sem_gs_setup(4, 3, None, 10, f, 1 << 20, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_gs_setup(4, 3, f, -1, f, 1 << 20, None, None) == _lib.SEM_ERR_ARG
+    need = L.sem_gs_workspace_bytes(4, 3, 100)
+    assert need >= 4 * 64 * 8 + 100 * 12
+    assert L.sem_gs_setup(4, 3, f, 100, f, need - 1, None, None) == _lib.SEM_ERR_WORKSPACE
+    assert L.sem_gs_workspace_bytes(4, 3, 1 << 33) == 0
+    assert L.sem_dsavg(4, 3, 9, f, 100, f, f, None) == _lib.SEM_ERR_DTYPE
+    assert L.sem_dsavg(4, 3, 0, None, 100, f, f, None) == _lib.SEM_ERR_ARG
+    assert L.sem_dsavg(4, 3, 0, f, 0, f, f, None) == _lib.SEM_OK      # nothing to average
+    assert L.sem_global_edge_keys(6, 0, 4, f, f, f, None, None) == _lib.SEM_ERR_ORDER
+    assert L.sem_global_edge_keys(6, 3, 4, None, f, f, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_global_edge_keys(0, 3, 4, None, None, None, None, None) == _lib.SEM_OK
+    wb = L.sem_weld_workspace_bytes(300)
+    assert wb >= 300 * (4 + 4 + 8) + 2 * 600 * 8
+    n = ctypes.c_void_p(0x2000)
+    assert L.sem_weld(301, 0, f, f, f, f, 10, n, f, wb, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_weld(300, 9, f, f, f, f, 10, n, f, wb, None, None) == _lib.SEM_ERR_DTYPE
+    assert L.sem_weld(300, 0, f, f, f, None, 10, n, f, wb, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_weld(300, 0, f, f, f, f, 10, None, f, wb, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_weld(300, 0, f, f, f, f, 10, n, f, wb - 1, None, None) == _lib.SEM_ERR_WORKSPACE
