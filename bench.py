@@ -59,6 +59,9 @@ def parse():
                     help="also time FP32 and the mixed-precision modes on the same snapshot")
     ap.add_argument("--c0", choices=("on", "off"), default="on",
                     help="also time C0 averaging of Q and welding of the isosurfaces")
+    ap.add_argument("--batched", choices=("on", "off"), default="on",
+                    help="also time 16 uneven snapshots (orders 5/7/9) in one persistent "
+                         "launch, and the whole batched step replayed as a HIP graph")
     ap.add_argument("--cpu-elements", type=int, default=16384,
                     help="elements of the snapshot the CPU oracle is timed on")
     ap.add_argument("--quiet", action="store_true")
@@ -291,6 +294,8 @@ def main():
         "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
     }
 
+    if args.batched == "on" and args.dtype == "f64":
+        result["batched"] = batched_timing(args, sem)
     if args.c0 == "on" and args.dtype == "f64":
         result["c0"] = c0_timing(args, sem, fields, q, isos, n)
     if args.precision_modes == "on" and args.dtype == "f64":
@@ -298,6 +303,122 @@ def main():
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(args, fields, isos, n, n_elem)
     print(json.dumps(result), flush=True)
+
+
+def batched_timing(args, sem):
+    """16 uneven FP32 snapshots (orders 5/7/9, 4,096-200,000 elements,
+    stretched boxes; velocity plus a random-Fourier-feature scalar theta).
+    Times: sem_qcrit per snapshot (16 launches) against sem_qcrit_batch (one
+    persistent launch per order: with the default forms, then with the
+    autotuned ones); and the whole step -- batched Q, then the
+    isosurfaces of Q, |omega| and theta at 4 isovalues each per snapshot --
+    eager against replayed as one captured HIP graph."""
+    import torch
+
+    import workloads as W
+    dev = "cuda:0"
+    t0 = time.time()
+    snaps, theta, specs = [], [], []
+    for seed in range(16):
+        spec, arrs = W.batch_snapshot(seed, dev, dtype=torch.float32)
+        x, y, z, u, v, w, th = arrs
+        e = x.shape[0]
+        snaps.append({"x": x, "y": y, "z": z, "u": u, "v": v, "w": w,
+                      "q": torch.empty_like(u), "omega_mag": torch.empty_like(u),
+                      "minmax": torch.empty((e, 2), dtype=torch.float32, device=dev)})
+        theta.append(th)
+        specs.append(spec)
+    torch.cuda.synchronize()
+    points = sum(sn["x"].numel() for sn in snaps)
+    log(args, f"batched: 16 snapshots, {points} points generated in {time.time() - t0:.1f} s")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps // 4)
+    # default forms (those of sem_qcrit), then the autotuned ones
+    plan_default = sem.BatchPlan(snaps)
+    default_variants = {n: sem.batch_variant(n, sem.SEM_F32) for n in (5, 7, 9)}
+    tuned = {}
+    for n in (5, 7, 9):
+        var, ms = sem.autotune(n, sem.SEM_F32)
+        tuned[n] = {"variant": var, "ms_variants": [round(m, 4) for m in ms]}
+    plan = sem.BatchPlan(snaps)
+
+    def per_snapshot():
+        for sn in snaps:
+            sem.qcrit(sn["x"], sn["y"], sn["z"], sn["u"], sn["v"], sn["w"], q=sn["q"],
+                      omega_mag=sn["omega_mag"], minmax=sn["minmax"])
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    per_ms = timed(per_snapshot)
+    default_ms = timed(lambda: sem.qcrit_batch(plan_default))
+    batch_ms = timed(lambda: sem.qcrit_batch(plan))
+    # isovalues of each field: quantiles 0.9 / 0.95 / 0.99 / 0.999 of a sample
+    gen = torch.Generator(device=dev).manual_seed(0)
+    isos, work = [], []
+    sem.qcrit_batch(plan)
+    for sn, th in zip(snaps, theta):
+        per = []
+        for f in (sn["q"], sn["omega_mag"], th):
+            flat = f.reshape(-1)
+            idx = torch.randint(0, flat.numel(), (1 << 20,), device=dev, generator=gen)
+            qs = torch.quantile(flat[idx].double(), torch.tensor(
+                [0.9, 0.95, 0.99, 0.999], dtype=torch.float64, device=dev))
+            iv = [float(c) for c in qs.cpu()]
+            r = sem.isosurface(sn["x"], sn["y"], sn["z"], f, iv)
+            cap = int(r["tri_count"].sum().item())
+            e = sn["x"].shape[0]
+            ws = torch.empty(max(sem.workspace_bytes(e, sn["x"].shape[1] - 1, 4), 1),
+                             dtype=torch.uint8, device=dev)
+            per.append((f, iv, torch.empty((max(cap, 1), 3, 3), dtype=torch.float32,
+                                           device=dev),
+                        torch.zeros(4, dtype=torch.int64, device=dev), ws))
+        isos.append(per)
+    total_tri = sum(int(t[2].shape[0]) for per in isos for t in per)
+
+    def step():
+        sem.qcrit_batch(plan)
+        for sn, per in zip(snaps, isos):
+            for f, iv, tri, cnt, ws in per:
+                sem.isosurface_into(sn["x"], sn["y"], sn["z"], f, iv, tri, cnt, ws)
+
+    eager_ms = timed(step)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph_ms = timed(g.replay)
+    log(args, f"batched: sem_qcrit x16 {per_ms:.3f} ms, sem_qcrit_batch default forms "
+              f"{default_ms:.3f} ms, tuned {batch_ms:.3f} ms "
+              f"({points / (batch_ms * 1e-3) / 1e9:.1f} G points/s); whole step (Q + 48 "
+              f"isosurface calls) eager {eager_ms:.3f} ms, graph {graph_ms:.3f} ms; "
+              f"variants {({n: t['variant'] for n, t in tuned.items()})}")
+    out = {"snapshots": 16, "points": points,
+           "orders": [sp[0] for sp in specs], "elements": [sp[1][0] * sp[1][1] * sp[1][2]
+                                                           for sp in specs],
+           "default_variants": default_variants, "tuned": tuned,
+           "qcrit_per_snapshot_ms": round(per_ms, 4),
+           "qcrit_batch_default_ms": round(default_ms, 4),
+           "qcrit_batch_ms": round(batch_ms, 4),
+           "qcrit_batch_points_per_s": points / (batch_ms * 1e-3),
+           "step_eager_ms": round(eager_ms, 4), "step_graph_ms": round(graph_ms, 4),
+           "step_graph_points_per_s": points / (graph_ms * 1e-3),
+           "triangles": total_tri}
+    del snaps, theta, isos, plan, plan_default, g
+    torch.cuda.empty_cache()
+    return out
 
 
 def c0_timing(args, sem, fields, q, isos, n):

@@ -229,6 +229,69 @@ int sem_extract(int64_t n_elem, int order, sem_dtype dt,
                 int32_t* status_word, void* stream);
 
 /* ---------------------------------------------------------------------
+ * Batched snapshots: one persistent launch over many snapshots
+ * ---------------------------------------------------------------------
+ * Snapshots of different order and size (all in one precision, F64 or F32)
+ * go through one persistent kernel per order present (per-order
+ * instantiations, each with its own register budget), all launched by one
+ * call: its workgroups walk the work items -- one or a few consecutive
+ * elements of one snapshot -- of every snapshot of that order, each
+ * computing Q, |omega| and the element ranges exactly as sem_qcrit defines
+ * them.  How a work item is computed is the variant set for its (order,
+ * precision), by default the form sem_qcrit uses, or the one sem_autotune
+ * measured fastest on this device:
+ *   0, 1, 2  LDS-tile form, 256 threads, 1, 2 or 4 elements per work item
+ *            (if the kernel's LDS tile holds them);
+ *   3        register-pencil form, 128 threads, one element (N <= 7;
+ *            default for N <= 7 except FP64 N = 7);
+ *   4        direct-to-LDS form, 256 threads, one element (N = 7, FP64
+ *            only; its default);
+ *   5        one thread per node, one element (default for N >= 8).
+ * A plan (device buffer) holds the snapshot descriptors, so sem_qcrit_batch
+ * takes no host data and can be captured in a HIP graph and replayed. */
+typedef struct {
+  int64_t n_elem;
+  int order;
+  const void *x, *y, *z, *u, *v, *w;   /* DEVICE inputs, sem layout      */
+  void *q, *omega_mag, *q_minmax;      /* DEVICE outputs, any may be NULL
+                                          (not all three)                */
+} sem_snapshot;
+
+/* Bytes of a plan for n_snap snapshots (1 <= n_snap <= 4096; else 0). */
+size_t sem_batch_plan_bytes(int n_snap);
+
+/* Write the plan of n_snap snapshots (HOST array) into the DEVICE buffer
+ * plan, and into *launch_code (may be NULL) the kernels it needs: 3 bits
+ * per order N at bit 3N, 0 = no snapshot of that order, else 1 + the form
+ * of its work items.  A setup call: it copies synchronously (not
+ * capturable).  The plan records the pointers and the variants set at this
+ * moment. */
+int sem_batch_plan(int n_snap, const sem_snapshot* snaps, sem_dtype dt, void* plan,
+                   size_t plan_bytes, unsigned* launch_code);
+
+/* Q, |omega| and element ranges of every snapshot of the plan: one
+ * persistent launch per order in launch_code (the code sem_batch_plan
+ * returned for this plan), on `stream`; dt must be the plan's.
+ * Asynchronous; capturable in a HIP graph. */
+int sem_qcrit_batch(const void* plan, unsigned launch_code, sem_dtype dt, int32_t* status_word,
+                    void* stream);
+
+/* Time the batched kernel on 8,192 synthetic elements of this order with
+ * every variant that applies, keep the fastest for (order, dt) on the
+ * current device and return it in *variant_out (may be NULL); ms_out (may
+ * be NULL) receives the six timings in ms (-1 = variant not applicable).
+ * A setup call: allocates temporary device memory and synchronises the
+ * device. */
+int sem_autotune(int order, sem_dtype dt, int* variant_out, float* ms_out);
+
+/* Variant the next plans use for (order, dt) on the current device. */
+int sem_batch_variant(int order, sem_dtype dt);
+
+/* Set the variant for (order, dt) on the current device without timing
+ * (SEM_ERR_ARG if it does not apply to the order). */
+int sem_batch_set_variant(int order, sem_dtype dt, int variant);
+
+/* ---------------------------------------------------------------------
  * C0 averaging over shared GLL nodes and welded isosurface output
  * ---------------------------------------------------------------------
  * Elements store their own copy of every node.  gid[e][node] (DEVICE int64,

@@ -12,5 +12,6 @@ from ._lib import (  # noqa: F401
     SEM_MIN_ORDER, SemError, derivs, extract, extract_into, extract_workspace_bytes, gll,
     init, isosurface, isosurface_into, lib, mc_table, phase_name, qcrit, status_str,
     timing_begin, timing_end, workspace_bytes, GatherScatter, dsavg, global_edge_keys, weld,
-    SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW,
+    SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW, BatchPlan, qcrit_batch, autotune, batch_variant,
+    batch_set_variant, BATCH_VARIANTS,
 )

@@ -25,6 +25,7 @@ SEM_ERR_HIP, SEM_ERR_WORKSPACE, SEM_ERR_DTYPE = -4, -5, -6
 SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW = 1, 2, 4, 8
 SEM_MIN_ORDER, SEM_MAX_ORDER = 1, 9
 SEM_MAX_ISO = 64
+BATCH_VARIANTS = 6          # variants of the batched kernel (sem_autotune)
 SEM_MC_MAX_TRI = 5
 SEM_PHASE_QCRIT, SEM_PHASE_COUNT, SEM_PHASE_SCAN, SEM_PHASE_EMIT = 0, 1, 2, 3
 SEM_NUM_PHASES = 4
@@ -36,7 +37,16 @@ EXPORTS = (
     "sem_phase_name", "sem_timing_begin", "sem_timing_end",
     "sem_gs_workspace_bytes", "sem_gs_setup", "sem_dsavg", "sem_global_edge_keys",
     "sem_weld_workspace_bytes", "sem_weld",
+    "sem_batch_plan_bytes", "sem_batch_plan", "sem_qcrit_batch", "sem_autotune",
+    "sem_batch_variant", "sem_batch_set_variant",
 )
+
+
+class _Snapshot(ctypes.Structure):
+    """sem_snapshot of include/sem.h."""
+    _fields_ = [("n_elem", ctypes.c_int64), ("order", ctypes.c_int)] + [
+        (k, ctypes.c_void_p) for k in ("x", "y", "z", "u", "v", "w", "q", "omega_mag",
+                                       "q_minmax")]
 
 
 class SemError(RuntimeError):
@@ -102,6 +112,18 @@ def lib():
         L.sem_weld_workspace_bytes.argtypes = [i64]
         L.sem_weld.restype = i32
         L.sem_weld.argtypes = [i64, i32, vp, vp, vp, vp, i64, vp, vp, ctypes.c_size_t, vp, vp]
+        L.sem_batch_plan_bytes.restype = ctypes.c_size_t
+        L.sem_batch_plan_bytes.argtypes = [i32]
+        L.sem_batch_plan.restype = i32
+        L.sem_batch_plan.argtypes = [i32, vp, i32, vp, ctypes.c_size_t, vp]
+        L.sem_qcrit_batch.restype = i32
+        L.sem_qcrit_batch.argtypes = [vp, ctypes.c_uint, i32, vp, vp]
+        L.sem_autotune.restype = i32
+        L.sem_autotune.argtypes = [i32, i32, vp, vp]
+        L.sem_batch_variant.restype = i32
+        L.sem_batch_variant.argtypes = [i32, i32]
+        L.sem_batch_set_variant.restype = i32
+        L.sem_batch_set_variant.argtypes = [i32, i32, i32]
         del dbl
         _lib = L
     return _lib
@@ -520,3 +542,91 @@ def weld(tri_xyz, keys, status=None):
                               n_ref, _ptr(n_vert), _ptr(ws), ws.numel(), _ptr(status),
                               _stream(keys)), "sem_weld")
     return verts[:int(n_vert.item())], idx
+
+
+# ---------------------------------------------------------------------------
+# batched snapshots
+# ---------------------------------------------------------------------------
+
+class BatchPlan:
+    """Device plan of several snapshots (sem_batch_plan).  Each snapshot is a
+    dict with x, y, z, u, v, w and the outputs q, omega_mag, minmax (any may
+    be None but not all); all tensors share one precision and device.  The
+    plan keeps references to the tensors it points at."""
+
+    def __init__(self, snapshots):
+        torch = _torch()
+        if not snapshots:
+            raise ValueError("no snapshots")
+        ref = snapshots[0]["x"]
+        self.dtype_code = _dtype_code(ref)
+        self.device = ref.device
+        init(ref.device.index)
+        arr = (_Snapshot * len(snapshots))()
+        self._keep = []
+        for i, sn in enumerate(snapshots):
+            x = sn["x"]
+            _field_check(x, sn["y"], sn["z"], sn["u"], sn["v"], sn["w"])
+            _field_check(x, sn.get("q"), sn.get("omega_mag"))
+            if x.dtype != ref.dtype or x.device != ref.device:
+                raise ValueError("all snapshots share one dtype and device")
+            mm = sn.get("minmax")
+            if mm is not None and (mm.numel() < 2 * x.shape[0] or mm.dtype != x.dtype):
+                raise ValueError("minmax must hold (E, 2) values of the field dtype")
+            arr[i].n_elem = x.shape[0]
+            arr[i].order = _order_of(x)
+            for k in ("x", "y", "z", "u", "v", "w"):
+                setattr(arr[i], k, _ptr(sn[k]))
+            arr[i].q = _ptr(sn.get("q"))
+            arr[i].omega_mag = _ptr(sn.get("omega_mag"))
+            arr[i].q_minmax = _ptr(mm)
+            self._keep.append(sn)
+        nb = int(lib().sem_batch_plan_bytes(len(snapshots)))
+        if nb == 0:
+            raise SemError(SEM_ERR_ARG, "sem_batch_plan_bytes")
+        self.buf = torch.empty(nb, dtype=torch.uint8, device=ref.device)
+        code = ctypes.c_uint(0)
+        with torch.cuda.device(ref.device):
+            torch.cuda.current_stream(ref.device).synchronize()
+            _check(lib().sem_batch_plan(len(snapshots), ctypes.addressof(arr), self.dtype_code,
+                                        _ptr(self.buf), nb, ctypes.addressof(code)),
+                   "sem_batch_plan")
+        self.launch_code = code.value
+
+
+def qcrit_batch(plan, status=None):
+    """One persistent launch per order over every snapshot of the plan
+    (capturable)."""
+    torch = _torch()
+    with torch.cuda.device(plan.device):
+        _check(lib().sem_qcrit_batch(_ptr(plan.buf), plan.launch_code, plan.dtype_code,
+                                     _ptr(status),
+                                     torch.cuda.current_stream(plan.device).cuda_stream),
+               "sem_qcrit_batch")
+
+
+def autotune(order, dtype_code=SEM_F64, device=None):
+    """Measure the batched kernel's variants for (order, dtype); returns
+    (chosen variant, [ms of variants 0..5], -1 where not applicable).
+    Variants 0, 1, 2: LDS-tile form with 1, 2, 4 elements per work item;
+    3: register-pencil form (N <= 7); 4: direct-to-LDS form (N = 7, FP64);
+    5: one thread per node."""
+    init(device)
+    var = ctypes.c_int(0)
+    ms = (ctypes.c_float * BATCH_VARIANTS)()
+    _check(lib().sem_autotune(int(order), int(dtype_code), ctypes.addressof(var),
+                              ctypes.addressof(ms)), "sem_autotune")
+    return var.value, [float(v) for v in ms]
+
+
+def batch_variant(order, dtype_code=SEM_F64):
+    rc = lib().sem_batch_variant(int(order), int(dtype_code))
+    if rc < 0:
+        raise SemError(rc, "sem_batch_variant")
+    return rc
+
+
+def batch_set_variant(order, dtype_code, variant, device=None):
+    init(device)
+    _check(lib().sem_batch_set_variant(int(order), int(dtype_code), int(variant)),
+           "sem_batch_set_variant")

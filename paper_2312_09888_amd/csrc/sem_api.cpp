@@ -215,6 +215,11 @@ int sem_init(int device) {
     st.tab.ntri = reinterpret_cast<const uint8_t*>(b + off_ntri);
     st.tab.tri = reinterpret_cast<const int8_t*>(b + off_tri);
     st.tab.eo7 = reinterpret_cast<const double*>(b + off_eo7);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) !=
+            hipSuccess || cus <= 0)
+      cus = 256;
+    st.tab.cu_count = cus;
     st.ready = true;
   }
   (void)hipSetDevice(prev);
@@ -331,6 +336,181 @@ int sem_isosurface(int64_t n_elem, int order, sem_dtype dt, const void* x, const
                                    active_cells, case_idx, ws, status_word,
                                    static_cast<hipStream_t>(stream));
   return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+size_t sem_batch_plan_bytes(int n_snap) {
+  if (n_snap < 1 || n_snap > kBatchMaxSnap) return 0;
+  return batch_plan_bytes(n_snap);
+}
+
+int sem_batch_variant(int order, sem_dtype dt) {
+  if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  const int v = tab->tuned_variant[dt == SEM_F64 ? 0 : 1][order] - 1;
+  return v >= 0 ? v : batch_default_variant(order, dt);
+}
+
+int sem_batch_set_variant(int order, sem_dtype dt, int variant) {
+  if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+  if (!batch_variant_ok(order, dt, variant)) return SEM_ERR_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SEM_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_mutex);
+  if (!g_dev[dev].ready) return SEM_ERR_NOT_INIT;
+  g_dev[dev].tab.tuned_variant[dt == SEM_F64 ? 0 : 1][order] = variant + 1;
+  return SEM_OK;
+}
+
+int sem_batch_plan(int n_snap, const sem_snapshot* snaps, sem_dtype dt, void* plan,
+                   size_t plan_bytes, unsigned* launch_code) {
+  if (n_snap < 1 || n_snap > kBatchMaxSnap || !snaps) return SEM_ERR_ARG;
+  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+  if (!plan || plan_bytes < batch_plan_bytes(n_snap)) return SEM_ERR_WORKSPACE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  for (int i = 0; i < n_snap; ++i) {
+    const sem_snapshot& sn = snaps[i];
+    if (sn.order < SEM_MIN_ORDER || sn.order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+    if (sn.n_elem < 0 || sn.n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
+    if (sn.n_elem > 0 && (!sn.x || !sn.y || !sn.z || !sn.u || !sn.v || !sn.w)) return SEM_ERR_ARG;
+    if (sn.n_elem > 0 && !sn.q && !sn.omega_mag && !sn.q_minmax) return SEM_ERR_ARG;
+  }
+  std::vector<unsigned char> host(batch_plan_bytes(n_snap), 0);
+  BatchHeader* hdr = reinterpret_cast<BatchHeader*>(host.data());
+  BatchSnap* bs = reinterpret_cast<BatchSnap*>(host.data() + 256);
+  unsigned code = 0;
+  int next = 0;
+  // descriptors grouped by order; items numbered within each order
+  for (int n = SEM_MIN_ORDER; n <= kMaxOrder; ++n) {
+    hdr->snap_begin[n] = next;
+    int var = tab->tuned_variant[dt == SEM_F64 ? 0 : 1][n] - 1;
+    if (!batch_variant_ok(n, dt, var)) var = batch_default_variant(n, dt);
+    const int chunk = batch_variant_chunk(var), form = batch_variant_form(var);
+    int64_t items = 0;
+    for (int i = 0; i < n_snap; ++i) {
+      const sem_snapshot& sn = snaps[i];
+      if (sn.order != n) continue;
+      BatchSnap& b = bs[next++];
+      b.n_elem = sn.n_elem;
+      b.item_begin = items;
+      b.order = n;
+      b.chunk = chunk;
+      b.form = form;
+      b.pad = 0;
+      const void* f[6] = {sn.x, sn.y, sn.z, sn.u, sn.v, sn.w};
+      for (int k = 0; k < 6; ++k) b.f[k] = f[k];
+      b.q = sn.q;
+      b.om = sn.omega_mag;
+      b.qmm = sn.q_minmax;
+      b.dmat = tab->d64[n];   // line sums run in FP64 for either precision
+      b.eo = tab->eo7;
+      items += (sn.n_elem + chunk - 1) / chunk;
+    }
+    hdr->items[n] = items;
+    if (items > 0) code |= (unsigned)(form + 1) << (3 * n);
+  }
+  hdr->snap_begin[0] = 0;
+  hdr->snap_begin[kMaxOrder + 1] = next;
+  hdr->n_snap = n_snap;
+  hdr->dt = dt;
+  if (launch_code) *launch_code = code;
+  return hipMemcpy(plan, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+int sem_qcrit_batch(const void* plan, unsigned launch_code, sem_dtype dt, int32_t* status_word,
+                    void* stream) {
+  if (!plan) return SEM_ERR_ARG;
+  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
+  const hipError_t e =
+      launch_qcrit_batch(dt, plan, launch_code, 8 * tab->cu_count, status_word,
+                         static_cast<hipStream_t>(stream), pt.start, pt.stop);
+  phase_done(pt);
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+int sem_autotune(int order, sem_dtype dt, int* variant_out, float* ms_out) {
+  if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SEM_ERR_HIP;
+  if (!current_tables()) return SEM_ERR_NOT_INIT;
+  const int64_t n_elem = 8192;
+  const int64_t p = order + 1, pts = n_elem * p * p * p;
+  const size_t esz = dt == SEM_F64 ? 8 : 4;
+  const size_t fb = (pts * esz + 255) & ~size_t(255);
+  const size_t mmb = (2 * n_elem * esz + 255) & ~size_t(255);
+  const size_t plan_b = batch_plan_bytes(1);
+  void* buf = nullptr;
+  if (hipMalloc(&buf, 8 * fb + mmb + plan_b) != hipSuccess) return SEM_ERR_HIP;
+  char* b = static_cast<char*>(buf);
+  void* f[6];
+  for (int k = 0; k < 6; ++k) f[k] = b + k * fb;
+  void* plan = b + 8 * fb + mmb;
+  sem_snapshot sn{};
+  sn.n_elem = n_elem;
+  sn.order = order;
+  sn.x = f[0]; sn.y = f[1]; sn.z = f[2]; sn.u = f[3]; sn.v = f[4]; sn.w = f[5];
+  sn.q = b + 6 * fb;
+  sn.omega_mag = b + 7 * fb;
+  sn.q_minmax = b + 8 * fb;
+  int rc = SEM_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best_ms = 0.f;
+  int best = -1;
+  const int ti = dt == SEM_F64 ? 0 : 1;
+  if (launch_tune_fill(dt, order, n_elem, f, nullptr) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = SEM_ERR_HIP;
+  for (int var = 0; var < kBatchVariants && rc == SEM_OK; ++var) {
+    if (ms_out) ms_out[var] = -1.f;
+    if (!batch_variant_ok(order, dt, var)) continue;
+    {
+      std::lock_guard<std::mutex> lock(g_mutex);
+      g_dev[dev].tab.tuned_variant[ti][order] = var + 1;
+    }
+    unsigned mask = 0;
+    rc = sem_batch_plan(1, &sn, dt, plan, plan_b, &mask);
+    if (rc != SEM_OK) break;
+    const int grid = 8 * current_tables()->cu_count;
+    float ms = 0.f;
+    if (launch_qcrit_batch(dt, plan, mask, grid, nullptr, nullptr, nullptr, nullptr) !=
+            hipSuccess ||
+        hipEventRecord(e0, nullptr) != hipSuccess) {
+      rc = SEM_ERR_HIP;
+      break;
+    }
+    for (int r = 0; r < 5; ++r)
+      (void)launch_qcrit_batch(dt, plan, mask, grid, nullptr, nullptr, nullptr, nullptr);
+    if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = SEM_ERR_HIP;
+      break;
+    }
+    ms /= 5.f;
+    if (ms_out) ms_out[var] = ms;
+    if (best < 0 || ms < best_ms) {
+      best_ms = ms;
+      best = var;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(buf);
+  {
+    std::lock_guard<std::mutex> lock(g_mutex);
+    g_dev[dev].tab.tuned_variant[ti][order] = (rc == SEM_OK && best >= 0) ? best + 1 : 0;
+  }
+  if (rc == SEM_OK && variant_out) *variant_out = best;
+  return rc;
 }
 
 size_t sem_gs_workspace_bytes(int64_t n_elem, int order, int64_t n_global) {

@@ -26,6 +26,8 @@ struct DeviceTables {
   const uint8_t* ntri;                // [256]
   const int8_t* tri;                  // [256][kMcMaxTri][3]
   const double* eo7;                  // N = 7 even-odd form of D: A[4][4], B[4][4]
+  int cu_count;                       // compute units (persistent grids)
+  int tuned_variant[2][kMaxOrder + 1];  // batch variant + 1 per (dtype, order); 0 = not tuned
 };
 
 template <typename T>
@@ -57,6 +59,50 @@ int64_t scan_blocks(int64_t count);
 // total); partial holds scan_blocks(count) + 1 int64.
 hipError_t launch_exclusive_scan(const int32_t* cnt, int64_t count, int64_t* partial,
                                  int64_t* offs, hipStream_t s);
+
+// Batched snapshots: a plan (device) holds a header and one descriptor per
+// snapshot; one persistent kernel walks the work items (chunks of `chunk`
+// elements of one snapshot) of all snapshots.
+struct BatchHeader {
+  int32_t n_snap;
+  int32_t dt;
+  int32_t snap_begin[kMaxOrder + 2];   // descriptors sorted by order: [begin(N), begin(N+1))
+  int64_t items[kMaxOrder + 1];        // work items of each order
+};
+struct BatchSnap {
+  int64_t n_elem;
+  int64_t item_begin;   // first work item of this snapshot among those of its order
+  int32_t order;
+  int32_t chunk;        // elements per work item
+  int32_t form;         // BatchForm of this order's work items
+  int32_t pad;
+  const void* f[6];     // x, y, z, u, v, w
+  void* q;
+  void* om;
+  void* qmm;
+  const void* dmat;     // FP64 D of this order
+  const void* eo;       // even-odd halves of D (order 7)
+};
+constexpr int kBatchMaxSnap = 4096;
+size_t batch_plan_bytes(int n_snap);
+// Batch variants: 0, 1, 2 = LDS-tile form with 1, 2, 4 elements per work
+// item (256 threads); 3 = register-pencil form (N <= 7); 4 = direct-to-LDS
+// form (N = 7, FP64); 5 = one thread per node.  Variants 3-5 take one
+// element per work item and are the per-element kernels of sem_qcrit.
+constexpr int kBatchVariants = 6;
+enum BatchForm { kBatchChunk = 0, kBatchPencil = 1, kBatchDma7 = 2, kBatchNodeTile = 3 };
+bool batch_variant_ok(int order, sem_dtype dt, int variant);
+int batch_variant_chunk(int variant);
+int batch_variant_form(int variant);
+int batch_default_variant(int order, sem_dtype dt);
+// Launch code of a plan: 3 bits per order at bit 3N, 0 = no snapshot of
+// that order, else 1 + the form its work items use.
+inline int launch_code_form(unsigned code, int n) { return (int)((code >> (3 * n)) & 7u) - 1; }
+hipError_t launch_qcrit_batch(sem_dtype dt, const void* plan, unsigned launch_code, int grid,
+                              int32_t* status, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// synthetic well-shaped elements for timing (x, y, z, u, v, w)
+hipError_t launch_tune_fill(sem_dtype dt, int order, int64_t n_elem, void* const* f,
+                            hipStream_t s);
 
 // sem_c0.hip: gather-scatter structure built by sem_gs_setup in the
 // caller's buffer, C0 averaging, global edge keys, welding.

@@ -15,6 +15,8 @@
 // the Jacobian of a small element at a large absolute position accurate.
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <unordered_map>
 #include <type_traits>
 
 #include <hip/hip_ext.h>
@@ -130,25 +132,29 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* scra
   return before + inc - v;
 }
 
-// 1-D contractions at node (i, j, k) of a tile in LDS, line-shifted.
+// 1-D contractions at node (i, j, k) of a tile in LDS, line-shifted.  The
+// sums run in FP64 with the FP64 D for either field precision: in FP32 the
+// rounding of D and of an FP32 running sum would cost up to 3e-5 normwise
+// in Q at N = 9, and FP64 FMAs issue at the unpacked FP32 rate.
 template <int N, typename T>
-__device__ __forceinline__ void ref_derivs(const T* __restrict__ f, const T* __restrict__ d,
-                                           int i, int j, int k, T& fr, T& fs, T& ft) {
+__device__ __forceinline__ void ref_derivs(const T* __restrict__ f,
+                                           const double* __restrict__ d, int i, int j, int k,
+                                           T& fr, T& fs, T& ft) {
   constexpr int P = N + 1;
   const T* lr = f + (k * P + j) * P;   // line along i
   const T* ls = f + k * P * P + i;     // along j, stride P
   const T* lt = f + j * P + i;         // along k, stride P^2
-  const T r0 = lr[0], s0 = ls[0], t0 = lt[0];
-  T ar = T(0), as = T(0), at = T(0);
+  const double r0 = lr[0], s0 = ls[0], t0 = lt[0];
+  double ar = 0.0, as = 0.0, at = 0.0;
 #pragma unroll
   for (int m = 1; m < P; ++m) {
-    ar = fma(d[i * P + m], lr[m] - r0, ar);
-    as = fma(d[j * P + m], ls[m * P] - s0, as);
-    at = fma(d[k * P + m], lt[m * P * P] - t0, at);
+    ar = fma(d[i * P + m], (double)lr[m] - r0, ar);
+    as = fma(d[j * P + m], (double)ls[m * P] - s0, as);
+    at = fma(d[k * P + m], (double)lt[m * P * P] - t0, at);
   }
-  fr = ar;
-  fs = as;
-  ft = at;
+  fr = (T)ar;
+  fs = (T)as;
+  ft = (T)at;
 }
 
 template <typename T>
@@ -183,11 +189,11 @@ __device__ __forceinline__ bool invert_jacobian(T xr, T xs, T xt, T yr, T ys, T 
 
 template <int N, typename T>
 __global__ void __launch_bounds__(Shape<N>::kNodeThreads)
-derivs_tile(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+derivs_tile(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
             const T* __restrict__ z, const T* __restrict__ f, T* __restrict__ gx,
             T* __restrict__ gy, T* __restrict__ gz, int32_t* __restrict__ status) {
   using S = Shape<N>;
-  __shared__ T sd[S::P * S::P];
+  __shared__ double sd[S::P * S::P];
   __shared__ T sf[4][S::NP];
   const int t = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * S::NP;
@@ -218,17 +224,16 @@ derivs_tile(const T* __restrict__ dmat, const T* __restrict__ x, const T* __rest
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(Shape<N>::kNodeThreads)
-qcrit_tile(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
-           const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
-           const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
-           T* __restrict__ qmm, int32_t* __restrict__ status) {
+__device__ __forceinline__ void qcrit_tile_elem(
+    int64_t e, int t, const double* __restrict__ dmat, const T* __restrict__ x,
+    const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
+    const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
+    T* __restrict__ qmm, int32_t* __restrict__ status) {
   using S = Shape<N>;
-  __shared__ T sd[S::P * S::P];
+  __shared__ double sd[S::P * S::P];
   __shared__ T sf[6][S::NP];
   __shared__ T red[2 * (S::kNodeThreads / 64)];
-  const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * S::NP;
+  const int64_t base = e * S::NP;
   if (t < S::P * S::P) sd[t] = dmat[t];
   if (t < S::NP) {
     sf[0][t] = x[base + t];
@@ -273,10 +278,19 @@ qcrit_tile(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restr
     T mx = qv;
     block_minmax<T, S::kNodeThreads>(mn, mx, red);
     if (t == 0) {
-      qmm[2 * (int64_t)blockIdx.x] = mn;
-      qmm[2 * (int64_t)blockIdx.x + 1] = mx;
+      qmm[2 * e] = mn;
+      qmm[2 * e + 1] = mx;
     }
   }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(Shape<N>::kNodeThreads)
+qcrit_tile(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+           const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
+           const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
+           T* __restrict__ qmm, int32_t* __restrict__ status) {
+  qcrit_tile_elem<N, T>(blockIdx.x, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -308,13 +322,23 @@ struct Pen {
   __device__ static constexpr int at(int i, int j, int k) { return i + RS * j + SS * k; }
 };
 
-// Line-shifted derivative of a P-point line: out[i] = sum_m D[i][m] (g_m - g_0).
+// Coefficient tables (D, its even-odd halves) are read through the
+// constant address space: the index is wave-uniform, so every read is a
+// scalar load whatever stores precede it in the kernel.
+using const_f64 = const __attribute__((address_space(4))) double*;
+__device__ __forceinline__ double coef(const double* p, int idx) {
+  return ((const_f64)p)[idx];
+}
+
+// Line-shifted derivative of a P-point line: out[i] = sum_m D[i][m] (g_m - g_0),
+// summed in FP64 with the FP64 D for either field precision (as ref_derivs).
 template <int P, typename T>
-__device__ __forceinline__ T line_deriv(const T* __restrict__ d, int i, const T (&g)[P]) {
-  T acc = T(0);
+__device__ __forceinline__ T line_deriv(const double* __restrict__ d, int i, const T (&g)[P]) {
+  double acc = 0.0;
+  const double g0 = g[0];
 #pragma unroll
-  for (int m = 1; m < P; ++m) acc = fma(d[i * P + m], g[m] - g[0], acc);
-  return acc;
+  for (int m = 1; m < P; ++m) acc = fma(coef(d, i * P + m), (double)g[m] - g0, acc);
+  return (T)acc;
 }
 
 // One field through the pencil scheme; owner gets (f_r, f_s, f_t) at its
@@ -333,7 +357,7 @@ __device__ __forceinline__ void pencil_load(const T* __restrict__ gf, int p, T (
 }
 
 template <int N, typename T>
-__device__ __forceinline__ void pencil_pass(const T (&f)[N + 1], const T* __restrict__ d,
+__device__ __forceinline__ void pencil_pass(const T (&f)[N + 1], const double* __restrict__ d,
                                             T* __restrict__ F, T* __restrict__ S,
                                             T* __restrict__ Tt, int h, int p,
                                             T (&fr)[Pen<N>::H0], T (&fs)[Pen<N>::H0],
@@ -395,7 +419,7 @@ struct PencilTiles {
 // needed afterwards).
 template <int N, typename T>
 __device__ __forceinline__ bool pencil_geometry(const T (&lx)[N + 1], const T (&ly)[N + 1],
-                                                const T (&lz)[N + 1], const T* __restrict__ d,
+                                                const T (&lz)[N + 1], const double* __restrict__ d,
                                                 PencilTiles<N, T>& sm, T* FX, T* FY, T* FZ,
                                                 int h, int p, InvJac<T> (&kk)[Pen<N>::H0]) {
   constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
@@ -415,7 +439,7 @@ __device__ __forceinline__ bool pencil_geometry(const T (&lx)[N + 1], const T (&
 
 template <int N, typename T>
 __global__ void __launch_bounds__(128)
-derivs_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+derivs_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
               const T* __restrict__ z, const T* __restrict__ f, T* __restrict__ gx,
               T* __restrict__ gy, T* __restrict__ gz, int32_t* __restrict__ status) {
   using Q = Pen<N>;
@@ -457,7 +481,7 @@ derivs_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __re
 template <int N, typename T>
 __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* gz,
                                              const T* gu, const T* gv, const T* gw,
-                                             const T* __restrict__ d, PencilTiles<N, T>& sm,
+                                             const double* __restrict__ d, PencilTiles<N, T>& sm,
                                              T* FX, T* FY, T* FZ, int h, int p,
                                              T (&qv)[Pen<N>::H0], T (&om)[Pen<N>::H0]) {
   constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
@@ -511,17 +535,17 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(128)
-qcrit_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
-             const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
-             const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
-             T* __restrict__ qmm, int32_t* __restrict__ status) {
+__device__ __forceinline__ void qcrit_pencil_elem(
+    int64_t e, int t, const double* __restrict__ dmat, const T* __restrict__ x,
+    const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
+    const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
+    T* __restrict__ qmm, int32_t* __restrict__ status) {
   using Q = Pen<N>;
   constexpr int P = Q::P, H0 = Q::H0;
   __shared__ PencilTiles<N, T> sm;
-  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int p = threadIdx.x & 63;
-  const int64_t base = (int64_t)blockIdx.x * (P * P * P);
+  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int p = t & 63;
+  const int64_t base = e * (P * P * P);
   T qv[H0], ov[H0];
   int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
                              sm, sm.F, sm.F, sm.F, h, p, qv, ov);
@@ -544,14 +568,24 @@ qcrit_pencil(const T* __restrict__ dmat, const T* __restrict__ x, const T* __res
     }
   }
   bad = __syncthreads_or(bad);
-  if (bad && threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
   if (qmm) {
     block_minmax<T, 128>(mn, mx, sm.red);
-    if (threadIdx.x == 0) {
-      qmm[2 * (int64_t)blockIdx.x] = mn;
-      qmm[2 * (int64_t)blockIdx.x + 1] = mx;
+    if (t == 0) {
+      qmm[2 * e] = mn;
+      qmm[2 * e + 1] = mx;
     }
   }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+qcrit_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+             const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
+             const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
+             T* __restrict__ qmm, int32_t* __restrict__ status) {
+  qcrit_pencil_elem<N, T>(blockIdx.x, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm,
+                          status);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,11 +1045,11 @@ __device__ __forceinline__ void eo_split(const double (&g)[8], double (&e)[4], d
 __device__ __forceinline__ void eo_pair(const double* __restrict__ eo, int i,
                                         const double (&e)[4], const double (&o)[4],
                                         double& lo, double& hi) {
-  double P = eo[4 * i] * e[0], R = eo[16 + 4 * i] * o[0];
+  double P = coef(eo, 4 * i) * e[0], R = coef(eo, 16 + 4 * i) * o[0];
 #pragma unroll
   for (int m = 1; m < 4; ++m) {
-    P = fma(eo[4 * i + m], e[m], P);
-    R = fma(eo[16 + 4 * i + m], o[m], R);
+    P = fma(coef(eo, 4 * i + m), e[m], P);
+    R = fma(coef(eo, 16 + 4 * i + m), o[m], R);
   }
   lo = R + P;
   hi = R - P;
@@ -1106,14 +1140,15 @@ __device__ __forceinline__ int wave_sum_i32(const WaveXor& w, int v) {
 // COUNT: also count every isovalue's triangles and active cells per element
 // from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
 template <bool COUNT>
-__global__ void __launch_bounds__(256)
-qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restrict__ x,
-             const double* __restrict__ y, const double* __restrict__ z,
-             const double* __restrict__ u, const double* __restrict__ v,
-             const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
-             double* __restrict__ qmm, int n_iso, IsoList<double> iso,
-             const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
-             int64_t* __restrict__ active, int32_t* __restrict__ status) {
+__device__ __forceinline__ void qcount_dma7_elem(
+    int64_t e, int t, int64_t n_elem, const double* __restrict__ eo, const double* __restrict__ x,
+    const double* __restrict__ y, const double* __restrict__ z, const double* __restrict__ u,
+    const double* __restrict__ v, const double* __restrict__ w, double* __restrict__ q,
+    double* __restrict__ om, double* __restrict__ qmm, int n_iso, const IsoList<double>& iso,
+    const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
+    int64_t* __restrict__ active, int32_t* __restrict__ status) {
+  __builtin_assume(t >= 0 && t < 256);
+  __builtin_assume(e >= 0);
   constexpr int NC = 343;
   __shared__ double s_xyz[3][512];
   __shared__ double s_uvw[3][512];
@@ -1122,10 +1157,8 @@ qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restr
   __shared__ double s_red[8];
   __shared__ uint8_t s_ntri[256];
   __shared__ int32_t s_wave[8];
-  const int t = threadIdx.x;
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int p = t & 63;
-  const int64_t e = blockIdx.x;
   const int64_t base = e * 512;
   // the case-table entry is loaded first and stored once every load is in
   const uint8_t nt_own = COUNT ? ntri_tab[t] : 0;
@@ -1264,6 +1297,19 @@ qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restr
       __syncthreads();
     }
   }
+}
+
+template <bool COUNT>
+__global__ void __launch_bounds__(256)
+qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restrict__ x,
+             const double* __restrict__ y, const double* __restrict__ z,
+             const double* __restrict__ u, const double* __restrict__ v,
+             const double* __restrict__ w, double* __restrict__ q, double* __restrict__ om,
+             double* __restrict__ qmm, int n_iso, IsoList<double> iso,
+             const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
+             int64_t* __restrict__ active, int32_t* __restrict__ status) {
+  qcount_dma7_elem<COUNT>(blockIdx.x, threadIdx.x, n_elem, eo, x, y, z, u, v, w, q, om, qmm, n_iso, iso,
+                          ntri_tab, cnt, active, status);
 }
 
 // Emission for N = 7, FP64: elements with triangles stage their field and
@@ -1598,6 +1644,207 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
+// batched snapshots: one persistent launch over every snapshot's elements
+// ---------------------------------------------------------------------------
+//
+// Work item = `chunk` consecutive elements of one snapshot; snapshots may
+// differ in order N and element count.  Each workgroup takes items
+// blockIdx.x, blockIdx.x + gridDim.x, ... ; for an item it finds the
+// snapshot (binary search over the items' prefix), stages the chunk's six
+// tiles and D in LDS and computes Q, |omega| and the element ranges with
+// the order's instantiation.  The chunk per (order, precision) is what the
+// autotuner measured fastest: small elements leave threads idle unless
+// several share a workgroup.
+
+constexpr int kBatchThreads = 256;
+constexpr int kBatchTile = 6144;   // LDS values for 6 fields x chunk x (N+1)^3
+
+template <int N, typename T>
+__device__ __forceinline__ int batch_chunk(const double* dmat, const T* const (&fp)[6], T* oq,
+                                           T* oom, T* oqmm, int64_t e0, int ne, T* tiles,
+                                           double* sd) {
+  constexpr int P = N + 1, P3 = P * P * P;
+  constexpr int MAXQ = kBatchTile / 6 / kBatchThreads;   // node values per thread
+  const int t = threadIdx.x;
+  const int nn = ne * P3;
+  for (int q = t; q < P * P; q += kBatchThreads) sd[q] = dmat[q];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const T* src = fp[f] + e0 * P3;
+    for (int q = t; q < nn; q += kBatchThreads) tiles[f * nn + q] = src[q];
+  }
+  __syncthreads();
+  int bad = 0;
+  T qkeep[MAXQ];
+#pragma unroll
+  for (int r = 0; r < MAXQ; ++r) {
+    const int q = t + r * kBatchThreads;
+    qkeep[r] = neg_inf<T>();
+    if (q >= nn) continue;
+    const int c = q / P3, node = q - c * P3;
+    const int i = node % P, j = (node / P) % P, k = node / (P * P);
+    const T* tl[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) tl[f] = tiles + f * nn + c * P3;
+    T xr, xs, xt, yr, ys, yt, zr, zs, zt;
+    ref_derivs<N>(tl[0], sd, i, j, k, xr, xs, xt);
+    ref_derivs<N>(tl[1], sd, i, j, k, yr, ys, yt);
+    ref_derivs<N>(tl[2], sd, i, j, k, zr, zs, zt);
+    InvJac<T> kk;
+    bad |= !invert_jacobian(xr, xs, xt, yr, ys, yt, zr, zs, zt, kk);
+    T a[3][3];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      T fr, fs, ft;
+      ref_derivs<N>(tl[3 + cc], sd, i, j, k, fr, fs, ft);
+      a[cc][0] = fr * kk.rx + fs * kk.sx + ft * kk.tx;
+      a[cc][1] = fr * kk.ry + fs * kk.sy + ft * kk.ty;
+      a[cc][2] = fr * kk.rz + fs * kk.sz + ft * kk.tz;
+    }
+    const T tr2 = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2] +
+                  T(2) * (a[0][1] * a[1][0] + a[0][2] * a[2][0] + a[1][2] * a[2][1]);
+    const T w1 = a[2][1] - a[1][2], w2 = a[0][2] - a[2][0], w3 = a[1][0] - a[0][1];
+    const T qv = T(-0.5) * tr2;
+    const int64_t o = e0 * P3 + q;
+    if (oq) oq[o] = qv;
+    if (oom) oom[o] = sqrt(w1 * w1 + w2 * w2 + w3 * w3);
+    qkeep[r] = qv != qv ? neg_inf<T>() : qv;
+    // one node at a time: no overlap of the unrolled iterations (which
+    // would multiply the live registers)
+    asm volatile("" ::: "memory");
+  }
+  if (oqmm) {
+    __syncthreads();                     // every tile read is done
+#pragma unroll
+    for (int r = 0; r < MAXQ; ++r) {
+      const int q = t + r * kBatchThreads;
+      if (q < nn) tiles[q] = qkeep[r];
+    }
+    __syncthreads();
+    const int wv = t >> 6, lane = t & 63;
+    if (wv < ne) {                       // wave c reduces element c
+      T mn = pos_inf<T>(), mx = neg_inf<T>();
+      for (int q = lane; q < P3; q += 64) {
+        const T v = tiles[wv * P3 + q];
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+      }
+      mn = wave_min(mn);
+      mx = wave_max(mx);
+      if (lane == 0) {
+        oqmm[2 * (e0 + wv)] = mn;
+        oqmm[2 * (e0 + wv) + 1] = mx;
+      }
+    }
+  }
+  return bad;
+}
+
+// A descriptor field read inside the persistent loop comes through vector
+// loads (the loop's stores precede it); moving it to a scalar register keeps
+// every pointer and address computation off the VGPRs.
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<P*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t x) {
+  const uint64_t v = (uint64_t)x;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// One instantiation per (order, precision, form), so that no form's register
+// demand limits another's occupancy.  kBatchNodeTile, kBatchPencil and
+// kBatchDma7 run the per-element bodies of qcrit_tile, qcrit_pencil and
+// qcount_dma7 on one element per work item.
+template <int N, int FORM>
+constexpr int batch_threads() {
+  return FORM == kBatchPencil ? 128 : FORM == kBatchNodeTile ? Shape<N>::kNodeThreads
+                                                             : kBatchThreads;
+}
+
+template <int N, typename T, int FORM>
+__global__ void __launch_bounds__((batch_threads<N, FORM>()))
+qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ snaps,
+            int32_t* __restrict__ status) {
+  const int s0 = hdr->snap_begin[N], s1 = hdr->snap_begin[N + 1];
+  const int64_t total = hdr->items[N];
+  int bad = 0;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int lo = s0, hi = s1 - 1;          // last snapshot of this order with item_begin <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (snaps[mid].item_begin <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchSnap& sn = snaps[lo];
+    const int64_t e0 = uniform_i64((item - sn.item_begin) * sn.chunk);
+    // the thread index is made opaque per item, so that no index arithmetic
+    // of the body is hoisted out of the loop and held in registers across it
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const double* dmat = uniform_ptr(static_cast<const double*>(sn.dmat));
+    const T* f0 = uniform_ptr(static_cast<const T*>(sn.f[0]));
+    const T* f1 = uniform_ptr(static_cast<const T*>(sn.f[1]));
+    const T* f2 = uniform_ptr(static_cast<const T*>(sn.f[2]));
+    const T* f3 = uniform_ptr(static_cast<const T*>(sn.f[3]));
+    const T* f4 = uniform_ptr(static_cast<const T*>(sn.f[4]));
+    const T* f5 = uniform_ptr(static_cast<const T*>(sn.f[5]));
+    T* oq = uniform_ptr(static_cast<T*>(sn.q));
+    T* oom = uniform_ptr(static_cast<T*>(sn.om));
+    T* oqmm = uniform_ptr(static_cast<T*>(sn.qmm));
+    if constexpr (FORM == kBatchChunk) {
+      __shared__ T tiles[kBatchTile];
+      __shared__ double sd[(kMaxOrder + 1) * (kMaxOrder + 1)];
+      const int64_t left = sn.n_elem - e0;
+      const int ne = __builtin_amdgcn_readfirstlane((int)(left < sn.chunk ? left : sn.chunk));
+      const T* fp[6] = {f0, f1, f2, f3, f4, f5};
+      bad |= batch_chunk<N, T>(dmat, fp, oq, oom, oqmm, e0, ne, tiles, sd);
+    } else if constexpr (FORM == kBatchNodeTile) {
+      qcrit_tile_elem<N, T>(e0, t, dmat, f0, f1, f2, f3, f4, f5, oq, oom, oqmm, status);
+    } else if constexpr (FORM == kBatchPencil) {
+      qcrit_pencil_elem<N, T>(e0, t, dmat, f0, f1, f2, f3, f4, f5, oq, oom, oqmm, status);
+    } else {
+      static_assert(N == 7 && std::is_same<T, double>::value, "direct-to-LDS form: N = 7, FP64");
+      qcount_dma7_elem<false>(e0, t, 0, uniform_ptr(static_cast<const double*>(sn.eo)), f0, f1, f2,
+                              f3, f4, f5, oq, oom, oqmm, 0, IsoList<double>{}, nullptr, nullptr,
+                              nullptr, status);
+    }
+    __syncthreads();                   // the next item reuses the LDS
+  }
+  if constexpr (FORM == kBatchChunk) {
+    bad = __syncthreads_or(bad);
+    if (bad && threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  }
+}
+
+// Synthetic unit-cube elements on a 16 x 16 x ... lattice with node
+// spacing 1/N and a smooth velocity: timing input for the autotuner.
+template <typename T>
+__global__ void tune_fill(int order, int64_t n_elem, T* x, T* y, T* z, T* u, T* v, T* w) {
+  const int p = order + 1;
+  const int64_t p3 = (int64_t)p * p * p;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n_elem * p3) return;
+  const int64_t e = idx / p3;
+  const int node = (int)(idx - e * p3);
+  const int i = node % p, j = (node / p) % p, k = node / (p * p);
+  const T xv = T(e % 16) + T(i) / T(order), yv = T((e / 16) % 16) + T(j) / T(order);
+  const T zv = T(e / 256) + T(k) / T(order);
+  x[idx] = xv;
+  y[idx] = yv;
+  z[idx] = zv;
+  u[idx] = sin(xv + T(2) * yv);
+  v[idx] = cos(yv - zv);
+  w[idx] = sin(zv + T(0.5) * xv);
+}
+
+// ---------------------------------------------------------------------------
 // dispatch over the order
 // ---------------------------------------------------------------------------
 
@@ -1616,17 +1863,17 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
   }
 
 template <typename T>
-const T* dmat_of(const DeviceTables& tab, int order);
+const double* dmat_of(const DeviceTables& tab, int order);
 template <>
 const double* dmat_of<double>(const DeviceTables& tab, int order) { return tab.d64[order]; }
 template <>
-const float* dmat_of<float>(const DeviceTables& tab, int order) { return tab.d32[order]; }
+const double* dmat_of<float>(const DeviceTables& tab, int order) { return tab.d64[order]; }
 
 template <typename T>
 hipError_t derivs_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
                     const void* y, const void* z, const void* f, void* gx, void* gy, void* gz,
                     int32_t* status, hipStream_t s) {
-  const T* d = dmat_of<T>(tab, order);
+  const double* d = dmat_of<T>(tab, order);
   SEM_ORDER_SWITCH(order, {
     if constexpr (N <= 7) {
       hipLaunchKernelGGL((derivs_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s, d,
@@ -1645,7 +1892,7 @@ template <typename T>
 hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
                    const void* y, const void* z, const void* u, const void* v, const void* w,
                    void* q, void* om, void* qmm, int32_t* status, hipStream_t s) {
-  const T* d = dmat_of<T>(tab, order);
+  const double* d = dmat_of<T>(tab, order);
   const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
   bool done = false;
   if constexpr (std::is_same<T, double>::value) {
@@ -1810,7 +2057,7 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
   }
   out.per_iso = 1;
   const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
-  const T* d = dmat_of<T>(tab, order);
+  const double* d = dmat_of<T>(tab, order);
   if constexpr (std::is_same<T, double>::value) {
     if (order == 7) {
       if (active)
@@ -1841,6 +2088,135 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
 }  // namespace
 
 int64_t scan_blocks(int64_t count) { return count <= 0 ? 1 : (count + kScanTile - 1) / kScanTile; }
+
+size_t batch_plan_bytes(int n_snap) {
+  return 256 + (((size_t)n_snap * sizeof(BatchSnap) + 255) & ~size_t(255));
+}
+
+int batch_variant_chunk(int variant) { return variant < 3 ? 1 << variant : 1; }
+
+int batch_variant_form(int variant) {
+  static const int form[kBatchVariants] = {kBatchChunk, kBatchChunk, kBatchChunk, kBatchPencil,
+                                           kBatchDma7, kBatchNodeTile};
+  return form[variant];
+}
+
+bool batch_variant_ok(int order, sem_dtype dt, int variant) {
+  if (variant < 0 || variant >= kBatchVariants) return false;
+  if (order < 1 || order > kMaxOrder) return false;
+  const int p3 = (order + 1) * (order + 1) * (order + 1);
+  switch (batch_variant_form(variant)) {
+    case kBatchChunk: return batch_variant_chunk(variant) * p3 <= kBatchTile / 6;
+    case kBatchPencil: return order <= 7;
+    case kBatchNodeTile: return true;
+    default: return order == 7 && dt == SEM_F64;
+  }
+}
+
+// untuned: the form sem_qcrit itself uses for this order and precision
+int batch_default_variant(int order, sem_dtype dt) {
+  if (order == 7 && dt == SEM_F64) return 4;
+  return order <= 7 ? 3 : 5;
+}
+
+template <int N, typename T>
+const void* batch_kernel_nt(int form) {
+  if constexpr (N <= 7) {
+    if (form == kBatchPencil) return reinterpret_cast<const void*>(&qcrit_batch<N, T, kBatchPencil>);
+  }
+  if constexpr (N == 7 && std::is_same<T, double>::value) {
+    if (form == kBatchDma7) return reinterpret_cast<const void*>(&qcrit_batch<7, double, kBatchDma7>);
+  }
+  if (form == kBatchNodeTile)
+    return reinterpret_cast<const void*>(&qcrit_batch<N, T, kBatchNodeTile>);
+  return form == kBatchChunk ? reinterpret_cast<const void*>(&qcrit_batch<N, T, kBatchChunk>)
+                             : nullptr;
+}
+
+int batch_threads_of(int n, int form) {
+  if (form == kBatchPencil) return 128;
+  if (form == kBatchNodeTile) return (((n + 1) * (n + 1) * (n + 1) + 63) / 64) * 64;
+  return kBatchThreads;
+}
+
+template <int N>
+const void* batch_kernel_n(bool f64, int form) {
+  return f64 ? batch_kernel_nt<N, double>(form) : batch_kernel_nt<N, float>(form);
+}
+
+const void* batch_kernel(int n, bool f64, int form) {
+  switch (n) {
+    case 1: return batch_kernel_n<1>(f64, form);
+    case 2: return batch_kernel_n<2>(f64, form);
+    case 3: return batch_kernel_n<3>(f64, form);
+    case 4: return batch_kernel_n<4>(f64, form);
+    case 5: return batch_kernel_n<5>(f64, form);
+    case 6: return batch_kernel_n<6>(f64, form);
+    case 7: return batch_kernel_n<7>(f64, form);
+    case 8: return batch_kernel_n<8>(f64, form);
+    case 9: return batch_kernel_n<9>(f64, form);
+    default: return nullptr;
+  }
+}
+
+// Workgroups of a persistent launch: every CU filled to the kernel's
+// occupancy (queried once per kernel).
+int batch_grid(const void* fn, int threads, int cu_count) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, int> occ;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = occ.find(fn);
+  if (it == occ.end()) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, threads, 0) != hipSuccess ||
+        blocks < 1)
+      blocks = 2;
+    it = occ.emplace(fn, blocks).first;
+  }
+  return it->second * cu_count;
+}
+
+hipError_t launch_qcrit_batch(sem_dtype dt, const void* plan, unsigned launch_code, int cu_count,
+                              int32_t* status, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const BatchHeader* hdr = static_cast<const BatchHeader*>(plan);
+  const BatchSnap* snaps =
+      reinterpret_cast<const BatchSnap*>(static_cast<const char*>(plan) + 256);
+  int first = -1, last = -1;
+  for (int n = 1; n <= kMaxOrder; ++n)
+    if (launch_code_form(launch_code, n) >= 0) {
+      if (first < 0) first = n;
+      last = n;
+    }
+  if (first < 0) return hipSuccess;
+  for (int n = first; n <= last; ++n) {
+    const int form = launch_code_form(launch_code, n);
+    if (form < 0) continue;
+    const void* fn = batch_kernel(n, dt == SEM_F64, form);
+    if (!fn) return hipErrorInvalidValue;
+    hipEvent_t a = n == first ? e0 : nullptr, b = n == last ? e1 : nullptr;
+    void* args[] = {const_cast<BatchHeader**>(&hdr), const_cast<BatchSnap**>(&snaps), &status};
+    const int threads = batch_threads_of(n, form);
+    const hipError_t err = hipExtLaunchKernel(fn, dim3(batch_grid(fn, threads, cu_count)),
+                                              dim3(threads), args, 0, s, a, b, 0);
+    if (err != hipSuccess) return err;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tune_fill(sem_dtype dt, int order, int64_t n_elem, void* const* f,
+                            hipStream_t s) {
+  const int64_t p = order + 1, n = n_elem * p * p * p;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (dt == SEM_F64)
+    hipLaunchKernelGGL(tune_fill<double>, dim3(blocks), dim3(256), 0, s, order, n_elem,
+                       (double*)f[0], (double*)f[1], (double*)f[2], (double*)f[3],
+                       (double*)f[4], (double*)f[5]);
+  else
+    hipLaunchKernelGGL(tune_fill<float>, dim3(blocks), dim3(256), 0, s, order, n_elem,
+                       (float*)f[0], (float*)f[1], (float*)f[2], (float*)f[3], (float*)f[4],
+                       (float*)f[5]);
+  return hipGetLastError();
+}
 
 hipError_t launch_exclusive_scan(const int32_t* cnt, int64_t count, int64_t* partial,
                                  int64_t* offs, hipStream_t s) {

@@ -253,3 +253,26 @@ def test_c0_argument_errors():
     assert L.sem_weld(300, 0, f, f, f, None, 10, n, f, wb, None, None) == _lib.SEM_ERR_ARG
     assert L.sem_weld(300, 0, f, f, f, f, 10, None, f, wb, None, None) == _lib.SEM_ERR_ARG
     assert L.sem_weld(300, 0, f, f, f, f, 10, n, f, wb - 1, None, None) == _lib.SEM_ERR_WORKSPACE
+
+
+def test_batch_argument_errors_and_struct_layout():
+    L = sem.lib()
+    assert L.sem_batch_plan_bytes(0) == 0 and L.sem_batch_plan_bytes(5000) == 0
+    assert L.sem_batch_plan_bytes(3) >= 256 + 3 * ctypes.sizeof(_lib._Snapshot)
+    # sem_snapshot: int64 n_elem, int order, then nine pointers
+    assert ctypes.sizeof(_lib._Snapshot) == 8 + 8 + 9 * 8
+    assert _lib._Snapshot.x.offset == 16
+    arr = (_lib._Snapshot * 1)()
+    assert L.sem_batch_plan(0, ctypes.addressof(arr), 0, FAKE, 1 << 20, None) == _lib.SEM_ERR_ARG
+    assert L.sem_batch_plan(1, ctypes.addressof(arr), 2, FAKE, 1 << 20, None) == \
+        _lib.SEM_ERR_DTYPE
+    assert L.sem_batch_plan(1, ctypes.addressof(arr), 0, FAKE, 10, None) == \
+        _lib.SEM_ERR_WORKSPACE
+    assert L.sem_qcrit_batch(None, 0, 0, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_qcrit_batch(FAKE, 0, 7, None, None) == _lib.SEM_ERR_DTYPE
+    assert L.sem_autotune(0, 0, None, None) == _lib.SEM_ERR_ORDER
+    assert L.sem_autotune(5, 3, None, None) == _lib.SEM_ERR_DTYPE
+    assert L.sem_batch_variant(10, 0) == _lib.SEM_ERR_ORDER
+    assert L.sem_batch_set_variant(9, 0, 3) == _lib.SEM_ERR_ARG     # pencil needs N <= 7
+    assert L.sem_batch_set_variant(9, 0, 1) == _lib.SEM_ERR_ARG     # 2 x 1000 nodes > tile
+    assert L.sem_batch_set_variant(5, 1, 7) == _lib.SEM_ERR_ARG

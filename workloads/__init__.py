@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "gll_points", "axis_lattice", "box_mesh", "element_axes", "tgv_velocity",
     "channel_modes", "channel_velocity", "warp", "tgv_config", "channel_config",
-    "lattice_gid", "CHANNEL_SHAPE", "TGV_SHAPE",
+    "lattice_gid", "batch_spec", "batch_snapshot", "CHANNEL_SHAPE", "TGV_SHAPE",
 ]
 
 TGV_SHAPE = (8, 8, 8)          # Taylor-Green box [0, 2 pi]^3, 512 elements
@@ -205,3 +205,57 @@ def channel_config(n=7, shape=CHANNEL_SHAPE, elements=None, device=None,
         out = tuple(a.astype(dtype) if isinstance(a, np.ndarray) else a.to(dtype)
                     for a in out)
     return out
+
+
+# --------------------------------------------------------------------------
+# batched uneven snapshots
+# --------------------------------------------------------------------------
+
+def batch_spec(seed, orders=(5, 7, 9), e_min=4096, e_max=200000):
+    """(order, shape, stretch) of batch snapshot `seed`: order drawn from
+    `orders`, element count log-uniform in [e_min, e_max] arranged as a
+    near-cubic box, per-axis tanh stretching beta uniform in [1, 3]."""
+    rng = np.random.default_rng(10_000 + seed)
+    n = int(rng.choice(orders))
+    e = int(round(math.exp(rng.uniform(math.log(e_min), math.log(e_max)))))
+    a = max(1, int(round(e ** (1.0 / 3.0))))
+    shape = (a, a, max(1, int(math.ceil(e / (a * a)))))
+    beta = tuple(float(b) for b in rng.uniform(1.0, 3.0, size=3))
+    return n, shape, beta
+
+
+def batch_snapshot(seed, device, dtype=None, features=256, chunk=1 << 22):
+    """Batch snapshot `seed` on `device` (torch): unit box mesh with the
+    spec's order, shape and stretching; velocity = channel-style random
+    solenoidal modes (8 shells x 4 directions, seeded); scalar theta = a
+    Gaussian random field by random Fourier features (Rahimi & Recht 2007):
+    theta = sqrt(2 / F) sum_f cos(k_f . x + b_f), k_f ~ N(0, 1 / l^2),
+    l = 0.1 of the domain, b_f ~ U(0, 2 pi).  Returns (spec, (x, y, z, u,
+    v, w, theta))."""
+    import torch
+    n, shape, beta = batch_spec(seed)
+    lat = [torch.from_numpy(axis_lattice(shape[a], n, 0.0, 1.0, beta[a])).to(device)
+           for a in range(3)]
+    ex, ey, ez = (torch.from_numpy(c).to(device) for c in element_axes(shape))
+    loc = torch.arange(n + 1, device=device)
+    p = n + 1
+    e_cnt = ex.shape[0]
+    xs = lat[0][ex[:, None] * n + loc[None, :]]
+    ys = lat[1][ey[:, None] * n + loc[None, :]]
+    zs = lat[2][ez[:, None] * n + loc[None, :]]
+    x = xs[:, None, None, :].expand(e_cnt, p, p, p).contiguous()
+    y = ys[:, None, :, None].expand(e_cnt, p, p, p).contiguous()
+    z = zs[:, :, None, None].expand(e_cnt, p, p, p).contiguous()
+    u, v, w = channel_velocity(x, y, z, channel_modes(seed, shells=8, per_shell=4))
+    rng = np.random.default_rng(20_000 + seed)
+    kf = torch.from_numpy(rng.normal(0.0, 1.0 / 0.1, size=(features, 3))).to(device)
+    bf = torch.from_numpy(rng.uniform(0.0, 2.0 * np.pi, size=features)).to(device)
+    pts = torch.stack([x.reshape(-1), y.reshape(-1), z.reshape(-1)], dim=1)
+    theta = torch.empty(pts.shape[0], dtype=x.dtype, device=device)
+    for c0 in range(0, pts.shape[0], chunk):
+        ph = pts[c0:c0 + chunk] @ kf.T + bf
+        theta[c0:c0 + chunk] = torch.cos(ph).sum(dim=1) * math.sqrt(2.0 / features)
+    out = (x, y, z, u, v, w, theta.reshape(x.shape))
+    if dtype is not None:
+        out = tuple(t.to(dtype).contiguous() for t in out)
+    return (n, shape, beta), out
