@@ -418,6 +418,53 @@ def batched_timing(args, sem):
            "triangles": total_tri}
     del snaps, theta, isos, plan, plan_default, g
     torch.cuda.empty_cache()
+    out["small"] = batched_small(args, sem, timed)
+    return out
+
+
+def batched_small(args, sem, timed):
+    """256 small FP32 snapshots (orders 5/7/9, 64-2,048 elements each):
+    where launches dominate, sem_qcrit per snapshot (256 launches) against
+    sem_qcrit_batch (one launch per order), eager and replayed as a graph."""
+    import torch
+
+    import workloads as W
+    dev = "cuda:0"
+    snaps = []
+    for seed in range(1000, 1256):
+        _, arrs = W.batch_snapshot(seed, dev, dtype=torch.float32, features=16, e_min=64,
+                                   e_max=2048)
+        x, y, z, u, v, w, _ = arrs
+        snaps.append({"x": x, "y": y, "z": z, "u": u, "v": v, "w": w,
+                      "q": torch.empty_like(u), "omega_mag": torch.empty_like(u),
+                      "minmax": torch.empty((x.shape[0], 2), dtype=torch.float32, device=dev)})
+    torch.cuda.synchronize()
+    points = sum(sn["x"].numel() for sn in snaps)
+    plan = sem.BatchPlan(snaps)
+
+    def per_snapshot():
+        for sn in snaps:
+            sem.qcrit(sn["x"], sn["y"], sn["z"], sn["u"], sn["v"], sn["w"], q=sn["q"],
+                      omega_mag=sn["omega_mag"], minmax=sn["minmax"])
+
+    per_ms = timed(per_snapshot)
+    batch_ms = timed(lambda: sem.qcrit_batch(plan))
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            sem.qcrit_batch(plan)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph_ms = timed(g.replay)
+    log(args, f"batched small: 256 snapshots, {points} points: sem_qcrit x256 {per_ms:.3f} ms, "
+              f"sem_qcrit_batch {batch_ms:.3f} ms, graph {graph_ms:.3f} ms")
+    out = {"snapshots": 256, "points": points, "qcrit_per_snapshot_ms": round(per_ms, 4),
+           "qcrit_batch_ms": round(batch_ms, 4), "qcrit_batch_graph_ms": round(graph_ms, 4),
+           "qcrit_batch_graph_points_per_s": points / (graph_ms * 1e-3)}
+    del snaps, plan, g
+    torch.cuda.empty_cache()
     return out
 
 

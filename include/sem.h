@@ -242,11 +242,11 @@ int sem_extract(int64_t n_elem, int order, sem_dtype dt,
  * measured fastest on this device:
  *   0, 1, 2  LDS-tile form, 256 threads, 1, 2 or 4 elements per work item
  *            (if the kernel's LDS tile holds them);
- *   3        register-pencil form, 128 threads, one element (N <= 7;
- *            default for N <= 7 except FP64 N = 7);
+ *   3        register-pencil form, 128 threads (256 for N >= 8), one
+ *            element (default for FP32, and for FP64 N <= 6);
  *   4        direct-to-LDS form, 256 threads, one element (N = 7, FP64
  *            only; its default);
- *   5        one thread per node, one element (default for N >= 8).
+ *   5        one thread per node, one element (default for FP64 N >= 8).
  * A plan (device buffer) holds the snapshot descriptors, so sem_qcrit_batch
  * takes no host data and can be captured in a HIP graph and replayed. */
 typedef struct {

@@ -294,31 +294,37 @@ qcrit_tile(const double* __restrict__ dmat, const T* __restrict__ x, const T* __
 }
 
 // ---------------------------------------------------------------------------
-// gradient / Q-criterion, pencil form (N <= 7): two waves per element
+// gradient / Q-criterion, pencil form: two halves of LT threads per element
 // ---------------------------------------------------------------------------
 //
-// Lane p < (N+1)^2 of each wave owns the r-line (j, k) = (p % P, p / P) of
-// the element; wave h owns the nodes i in [h*H0, h*H0 + H0) of that line,
-// so every node belongs to exactly one lane.  Per field:
-//   1. each lane loads its whole r-line from HBM (both waves read the same
-//      line; the second read hits the cache) and applies D along r for its
-//      half -- D entries are uniform across the wave;
+// A half is one wave for N <= 7 ((N+1)^2 <= 64 lines) and two waves for
+// N = 8, 9.  Thread p < (N+1)^2 of each half owns the r-line
+// (j, k) = (p % P, p / P) of the element; half h owns the nodes i in
+// [h*H0, h*H0 + H0) of that line, so every node belongs to exactly one
+// thread.  Per field:
+//   1. each thread loads its whole r-line from HBM (both halves read the
+//      same line; the second read hits the cache) and applies D along r for
+//      its half -- D entries are uniform across the wave;
 //   2. the owners write their nodes to an LDS tile;
-//   3. wave 0 applies D along s (lane p owns the s-line (i, k)), wave 1
-//      along t (lane p owns the t-line (i, j)); results go to two LDS tiles;
+//   3. half 0 applies D along s (thread p owns the s-line (i, k)), half 1
+//      along t (thread p owns the t-line (i, j)); results go to two LDS
+//      tiles;
 //   4. the owners read back f_s, f_t at their nodes.
 // Each line is read once and each derivative crosses LDS once, instead of
-// eight LDS reads per output.  LDS tiles use a padded row stride of P + 1.
+// P LDS reads of the field and P of D per output.  LDS tiles use a padded
+// row stride of P + 1.
 
 template <int N>
 struct Pen {
   static constexpr int P = N + 1;
-  static constexpr int NP = P * P;        // lines per direction (<= 64)
-  static constexpr int H0 = (P + 1) / 2;  // nodes per lane and wave
+  static constexpr int NP = P * P;        // lines per direction
+  static constexpr int LT = 64 * ((NP + 63) / 64);  // threads per half
+  static constexpr int TH = 2 * LT;       // threads per element
+  static constexpr int H0 = (P + 1) / 2;  // nodes per thread and half
   static constexpr int RS = P + 1;        // LDS row stride (j)
   static constexpr int SS = P * RS;       // LDS slab stride (k)
   static constexpr int SZ = P * SS;       // padded tile
-  static_assert(NP <= 64, "pencil kernels need (N+1)^2 <= 64");
+  static_assert(NP <= LT && TH <= 256, "one line per thread of a half");
   __device__ static constexpr int at(int i, int j, int k) { return i + RS * j + SS * k; }
 };
 
@@ -410,7 +416,7 @@ struct PencilTiles {
   T F[Pen<N>::SZ];
   T S[Pen<N>::SZ];
   T Tt[Pen<N>::SZ];
-  T red[4];
+  T red[2 * Pen<N>::TH / 64];
   int flag;
 };
 
@@ -432,21 +438,21 @@ __device__ __forceinline__ bool pencil_geometry(const T (&lx)[N + 1], const T (&
   for (int ii = 0; ii < H0; ++ii) {
     const bool good = invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii],
                                       zs[ii], zt[ii], kk[ii]);
-    if (h * H0 + ii < P) ok = ok && good;   // odd P: wave 1 owns one node fewer
+    if (h * H0 + ii < P) ok = ok && good;   // odd P: half 1 owns one node fewer
   }
   return ok;
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(Pen<N>::TH)
 derivs_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
               const T* __restrict__ z, const T* __restrict__ f, T* __restrict__ gx,
               T* __restrict__ gy, T* __restrict__ gz, int32_t* __restrict__ status) {
   using Q = Pen<N>;
   constexpr int P = Q::P, H0 = Q::H0;
   __shared__ PencilTiles<N, T> sm;
-  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int p = threadIdx.x & 63;
+  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / Q::LT);
+  const int p = threadIdx.x % Q::LT;
   const int64_t base = (int64_t)blockIdx.x * (P * P * P);
   T lx[P], ly[P], lz[P], lf[P];
   pencil_load<N>(x + base, p, lx);
@@ -485,19 +491,25 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
                                              T* FX, T* FY, T* FZ, int h, int p,
                                              T (&qv)[Pen<N>::H0], T (&om)[Pen<N>::H0]) {
   constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
-  // all six lines are requested before any arithmetic
+  // N <= 7: all six lines are requested before any arithmetic; N = 8, 9:
+  // the velocity lines are requested just before their pass (ten values a
+  // line would otherwise hold 30 more registers through the geometry)
+  constexpr bool kEarly = N <= 7;
   T lx[P], ly[P], lz[P], lu[P], lv[P], lw[P];
   pencil_load<N>(gx, p, lx);
   pencil_load<N>(gy, p, ly);
   pencil_load<N>(gz, p, lz);
-  pencil_load<N>(gu, p, lu);
-  pencil_load<N>(gv, p, lv);
-  pencil_load<N>(gw, p, lw);
+  if constexpr (kEarly) {
+    pencil_load<N>(gu, p, lu);
+    pencil_load<N>(gv, p, lv);
+    pencil_load<N>(gw, p, lw);
+  }
   InvJac<T> kk[H0];
   const bool ok = pencil_geometry<N>(lx, ly, lz, d, sm, FX, FY, FZ, h, p, kk);
   T fr[H0], fs[H0], ft[H0];
   T a01[H0], a02[H0], a12[H0];
   // row 0 (u)
+  if constexpr (!kEarly) pencil_load<N>(gu, p, lu);
   pencil_pass<N>(lu, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
@@ -508,6 +520,7 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
     qv[ii] = a00 * a00;
   }
   // row 1 (v)
+  if constexpr (!kEarly) pencil_load<N>(gv, p, lv);
   pencil_pass<N>(lv, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
@@ -520,6 +533,7 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
     om[ii] = w3 * w3;
   }
   // row 2 (w)
+  if constexpr (!kEarly) pencil_load<N>(gw, p, lw);
   pencil_pass<N>(lw, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
@@ -543,8 +557,8 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   using Q = Pen<N>;
   constexpr int P = Q::P, H0 = Q::H0;
   __shared__ PencilTiles<N, T> sm;
-  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int p = t & 63;
+  const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
+  const int p = t % Q::LT;
   const int64_t base = e * (P * P * P);
   T qv[H0], ov[H0];
   int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
@@ -570,7 +584,7 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   bad = __syncthreads_or(bad);
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
   if (qmm) {
-    block_minmax<T, 128>(mn, mx, sm.red);
+    block_minmax<T, Q::TH>(mn, mx, sm.red);
     if (t == 0) {
       qmm[2 * e] = mn;
       qmm[2 * e + 1] = mx;
@@ -579,7 +593,7 @@ __device__ __forceinline__ void qcrit_pencil_elem(
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(Pen<N>::TH)
 qcrit_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
              const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
              const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
@@ -1308,8 +1322,8 @@ qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restr
              double* __restrict__ qmm, int n_iso, IsoList<double> iso,
              const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
              int64_t* __restrict__ active, int32_t* __restrict__ status) {
-  qcount_dma7_elem<COUNT>(blockIdx.x, threadIdx.x, n_elem, eo, x, y, z, u, v, w, q, om, qmm, n_iso, iso,
-                          ntri_tab, cnt, active, status);
+  qcount_dma7_elem<COUNT>(blockIdx.x, threadIdx.x, n_elem, eo, x, y, z, u, v, w, q, om, qmm,
+                          n_iso, iso, ntri_tab, cnt, active, status);
 }
 
 // Emission for N = 7, FP64: elements with triangles stage their field and
@@ -1764,8 +1778,8 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
 // qcount_dma7 on one element per work item.
 template <int N, int FORM>
 constexpr int batch_threads() {
-  return FORM == kBatchPencil ? 128 : FORM == kBatchNodeTile ? Shape<N>::kNodeThreads
-                                                             : kBatchThreads;
+  return FORM == kBatchPencil ? Pen<N>::TH : FORM == kBatchNodeTile ? Shape<N>::kNodeThreads
+                                                                    : kBatchThreads;
 }
 
 template <int N, typename T, int FORM>
@@ -1775,34 +1789,52 @@ qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ s
   const int s0 = hdr->snap_begin[N], s1 = hdr->snap_begin[N + 1];
   const int64_t total = hdr->items[N];
   int bad = 0;
+  // The descriptor of the current snapshot stays in scalar registers; a
+  // workgroup's items increase, so it is looked up again only when an item
+  // passes the next snapshot's first item.
+  int cur = s0 - 1;
+  int64_t begin = 0, next_begin = 0, n_elem = 0;
+  int chunk = 1;
+  const double *dmat = nullptr, *eo = nullptr;
+  const T *f0 = nullptr, *f1 = nullptr, *f2 = nullptr, *f3 = nullptr, *f4 = nullptr,
+          *f5 = nullptr;
+  T *oq = nullptr, *oom = nullptr, *oqmm = nullptr;
   for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-    int lo = s0, hi = s1 - 1;          // last snapshot of this order with item_begin <= item
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (snaps[mid].item_begin <= item) lo = mid;
-      else hi = mid - 1;
+    if (cur < s0 || item >= next_begin) {
+      int lo = cur < s0 ? s0 : cur, hi = s1 - 1;   // last snapshot with item_begin <= item
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (snaps[mid].item_begin <= item) lo = mid;
+        else hi = mid - 1;
+      }
+      cur = __builtin_amdgcn_readfirstlane(lo);
+      const BatchSnap& sn = snaps[cur];
+      begin = uniform_i64(sn.item_begin);
+      next_begin = uniform_i64(cur + 1 < s1 ? snaps[cur + 1].item_begin : total);
+      n_elem = uniform_i64(sn.n_elem);
+      chunk = __builtin_amdgcn_readfirstlane(sn.chunk);
+      dmat = uniform_ptr(static_cast<const double*>(sn.dmat));
+      eo = uniform_ptr(static_cast<const double*>(sn.eo));
+      f0 = uniform_ptr(static_cast<const T*>(sn.f[0]));
+      f1 = uniform_ptr(static_cast<const T*>(sn.f[1]));
+      f2 = uniform_ptr(static_cast<const T*>(sn.f[2]));
+      f3 = uniform_ptr(static_cast<const T*>(sn.f[3]));
+      f4 = uniform_ptr(static_cast<const T*>(sn.f[4]));
+      f5 = uniform_ptr(static_cast<const T*>(sn.f[5]));
+      oq = uniform_ptr(static_cast<T*>(sn.q));
+      oom = uniform_ptr(static_cast<T*>(sn.om));
+      oqmm = uniform_ptr(static_cast<T*>(sn.qmm));
     }
-    const BatchSnap& sn = snaps[lo];
-    const int64_t e0 = uniform_i64((item - sn.item_begin) * sn.chunk);
+    const int64_t e0 = (item - begin) * chunk;
     // the thread index is made opaque per item, so that no index arithmetic
     // of the body is hoisted out of the loop and held in registers across it
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
-    const double* dmat = uniform_ptr(static_cast<const double*>(sn.dmat));
-    const T* f0 = uniform_ptr(static_cast<const T*>(sn.f[0]));
-    const T* f1 = uniform_ptr(static_cast<const T*>(sn.f[1]));
-    const T* f2 = uniform_ptr(static_cast<const T*>(sn.f[2]));
-    const T* f3 = uniform_ptr(static_cast<const T*>(sn.f[3]));
-    const T* f4 = uniform_ptr(static_cast<const T*>(sn.f[4]));
-    const T* f5 = uniform_ptr(static_cast<const T*>(sn.f[5]));
-    T* oq = uniform_ptr(static_cast<T*>(sn.q));
-    T* oom = uniform_ptr(static_cast<T*>(sn.om));
-    T* oqmm = uniform_ptr(static_cast<T*>(sn.qmm));
     if constexpr (FORM == kBatchChunk) {
       __shared__ T tiles[kBatchTile];
       __shared__ double sd[(kMaxOrder + 1) * (kMaxOrder + 1)];
-      const int64_t left = sn.n_elem - e0;
-      const int ne = __builtin_amdgcn_readfirstlane((int)(left < sn.chunk ? left : sn.chunk));
+      const int64_t left = n_elem - e0;
+      const int ne = (int)(left < chunk ? left : chunk);
       const T* fp[6] = {f0, f1, f2, f3, f4, f5};
       bad |= batch_chunk<N, T>(dmat, fp, oq, oom, oqmm, e0, ne, tiles, sd);
     } else if constexpr (FORM == kBatchNodeTile) {
@@ -1811,9 +1843,8 @@ qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ s
       qcrit_pencil_elem<N, T>(e0, t, dmat, f0, f1, f2, f3, f4, f5, oq, oom, oqmm, status);
     } else {
       static_assert(N == 7 && std::is_same<T, double>::value, "direct-to-LDS form: N = 7, FP64");
-      qcount_dma7_elem<false>(e0, t, 0, uniform_ptr(static_cast<const double*>(sn.eo)), f0, f1, f2,
-                              f3, f4, f5, oq, oom, oqmm, 0, IsoList<double>{}, nullptr, nullptr,
-                              nullptr, status);
+      qcount_dma7_elem<false>(e0, t, 0, eo, f0, f1, f2, f3, f4, f5, oq, oom, oqmm, 0,
+                              IsoList<double>{}, nullptr, nullptr, nullptr, status);
     }
     __syncthreads();                   // the next item reuses the LDS
   }
@@ -1876,7 +1907,7 @@ hipError_t derivs_t(int order, const DeviceTables& tab, int64_t n_elem, const vo
   const double* d = dmat_of<T>(tab, order);
   SEM_ORDER_SWITCH(order, {
     if constexpr (N <= 7) {
-      hipLaunchKernelGGL((derivs_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s, d,
+      hipLaunchKernelGGL((derivs_pencil<N, T>), dim3((unsigned)n_elem), dim3(Pen<N>::TH), 0, s, d,
                          (const T*)x, (const T*)y, (const T*)z, (const T*)f, (T*)gx, (T*)gy,
                          (T*)gz, status);
     } else {
@@ -1907,9 +1938,11 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
   }
   if (!done) {
     SEM_ORDER_SWITCH(order, {
-      if constexpr (N <= 7) {
-        hipExtLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
-                              pt.start, pt.stop, 0, d, (const T*)x, (const T*)y, (const T*)z,
+      // pencil form wherever it is the faster one: every order in FP32,
+      // N <= 7 in FP64 (at N = 8, 9 its FP64 registers spill)
+      if constexpr (N <= 7 || !std::is_same<T, double>::value) {
+        hipExtLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)n_elem), dim3(Pen<N>::TH),
+                              0, s, pt.start, pt.stop, 0, d, (const T*)x, (const T*)y, (const T*)z,
                               (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm,
                               status);
       } else {
@@ -2107,7 +2140,7 @@ bool batch_variant_ok(int order, sem_dtype dt, int variant) {
   const int p3 = (order + 1) * (order + 1) * (order + 1);
   switch (batch_variant_form(variant)) {
     case kBatchChunk: return batch_variant_chunk(variant) * p3 <= kBatchTile / 6;
-    case kBatchPencil: return order <= 7;
+    case kBatchPencil: return true;
     case kBatchNodeTile: return true;
     default: return order == 7 && dt == SEM_F64;
   }
@@ -2116,16 +2149,16 @@ bool batch_variant_ok(int order, sem_dtype dt, int variant) {
 // untuned: the form sem_qcrit itself uses for this order and precision
 int batch_default_variant(int order, sem_dtype dt) {
   if (order == 7 && dt == SEM_F64) return 4;
-  return order <= 7 ? 3 : 5;
+  return (order <= 7 || dt == SEM_F32) ? 3 : 5;
 }
 
 template <int N, typename T>
 const void* batch_kernel_nt(int form) {
-  if constexpr (N <= 7) {
-    if (form == kBatchPencil) return reinterpret_cast<const void*>(&qcrit_batch<N, T, kBatchPencil>);
-  }
+  if (form == kBatchPencil)
+    return reinterpret_cast<const void*>(&qcrit_batch<N, T, kBatchPencil>);
   if constexpr (N == 7 && std::is_same<T, double>::value) {
-    if (form == kBatchDma7) return reinterpret_cast<const void*>(&qcrit_batch<7, double, kBatchDma7>);
+    if (form == kBatchDma7)
+      return reinterpret_cast<const void*>(&qcrit_batch<7, double, kBatchDma7>);
   }
   if (form == kBatchNodeTile)
     return reinterpret_cast<const void*>(&qcrit_batch<N, T, kBatchNodeTile>);
@@ -2134,7 +2167,7 @@ const void* batch_kernel_nt(int form) {
 }
 
 int batch_threads_of(int n, int form) {
-  if (form == kBatchPencil) return 128;
+  if (form == kBatchPencil) return 128 * (((n + 1) * (n + 1) + 63) / 64);
   if (form == kBatchNodeTile) return (((n + 1) * (n + 1) * (n + 1) + 63) / 64) * 64;
   return kBatchThreads;
 }

@@ -273,6 +273,7 @@ def test_batch_argument_errors_and_struct_layout():
     assert L.sem_autotune(0, 0, None, None) == _lib.SEM_ERR_ORDER
     assert L.sem_autotune(5, 3, None, None) == _lib.SEM_ERR_DTYPE
     assert L.sem_batch_variant(10, 0) == _lib.SEM_ERR_ORDER
-    assert L.sem_batch_set_variant(9, 0, 3) == _lib.SEM_ERR_ARG     # pencil needs N <= 7
+    assert L.sem_batch_set_variant(9, 1, 4) == _lib.SEM_ERR_ARG     # direct-to-LDS: N = 7 FP64
+    assert L.sem_batch_set_variant(7, 1, 4) == _lib.SEM_ERR_ARG
     assert L.sem_batch_set_variant(9, 0, 1) == _lib.SEM_ERR_ARG     # 2 x 1000 nodes > tile
     assert L.sem_batch_set_variant(5, 1, 7) == _lib.SEM_ERR_ARG

@@ -224,16 +224,17 @@ def batch_spec(seed, orders=(5, 7, 9), e_min=4096, e_max=200000):
     return n, shape, beta
 
 
-def batch_snapshot(seed, device, dtype=None, features=256, chunk=1 << 22):
+def batch_snapshot(seed, device, dtype=None, features=256, chunk=1 << 22, e_min=4096,
+                   e_max=200000):
     """Batch snapshot `seed` on `device` (torch): unit box mesh with the
     spec's order, shape and stretching; velocity = channel-style random
     solenoidal modes (8 shells x 4 directions, seeded); scalar theta = a
     Gaussian random field by random Fourier features (Rahimi & Recht 2007):
     theta = sqrt(2 / F) sum_f cos(k_f . x + b_f), k_f ~ N(0, 1 / l^2),
     l = 0.1 of the domain, b_f ~ U(0, 2 pi).  Returns (spec, (x, y, z, u,
-    v, w, theta))."""
+    v, w, theta)).  e_min, e_max: range of the element count."""
     import torch
-    n, shape, beta = batch_spec(seed)
+    n, shape, beta = batch_spec(seed, e_min=e_min, e_max=e_max)
     lat = [torch.from_numpy(axis_lattice(shape[a], n, 0.0, 1.0, beta[a])).to(device)
            for a in range(3)]
     ex, ey, ez = (torch.from_numpy(c).to(device) for c in element_axes(shape))
