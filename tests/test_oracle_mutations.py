@@ -271,3 +271,104 @@ def test_last_occurrence_weld_is_caught():
         return v[::-1].copy(), (v.shape[0] - 1 - i)      # reversed vertex order
     with patched(c0, "weld", bad):
         _fails(T.test_welded_sphere_is_closed_manifold_across_elements)
+
+
+# --------------------------------------------------------------------------
+# compression network, optimiser, fallback and baseline (oracle/ae.py)
+# --------------------------------------------------------------------------
+
+def test_wrong_tanh_derivative_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+    orig = ae.gradient
+
+    def bad(params, x, quantize=True, tanh_mask=ae.TANH_NONE):
+        # 1 - y instead of 1 - y^2 in the backward pass
+        x = np.asarray(x, dtype=np.float64)
+        acts = ae.forward(params, x, quantize, tanh_mask)
+        layers = ae.unpack(params)
+        g = 2.0 * (acts[-1] - x) / x.size
+        grads = [None] * len(ae.ARCH)
+        for l in range(len(ae.ARCH) - 1, -1, -1):
+            kind = ae.ARCH[l][0]
+            if (tanh_mask >> l) & 1:
+                g = g * (1.0 - acts[l + 1])
+            gx, gw, gb = (ae.conv_grads if kind == "conv" else ae.conv_t_grads)(
+                acts[l], layers[l][0], g)
+            grads[l] = (gw, gb)
+            g = gx
+        return ae.loss(acts[-1], x), ae.pack(grads)
+    assert orig is not bad
+    with patched(ae, "gradient", bad):
+        _fails(lambda: T.test_gradient_matches_central_differences(ae.TANH_HIDDEN))
+
+
+def test_flipped_kernel_offset_in_conv_t_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+
+    def bad(x, w, b):
+        y = np.empty((x.shape[0], w.shape[1]) + tuple(2 * s for s in x.shape[2:]))
+        for dz, dy, dx in ae._delta():
+            # kernel tap (dx, dy, dz) instead of (dz, dy, dx)
+            y[:, :, dz::2, dy::2, dx::2] = np.einsum("io,bizyx->bozyx", w[:, :, dx, dy, dz], x)
+        return y + b[None, :, None, None, None]
+    with patched(ae, "conv_t", bad):
+        _fails(T.test_conv_t_impulse_response)
+        _fails(T.test_conv_t_is_the_adjoint_of_conv)
+
+
+def test_adam_without_bias_correction_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+
+    def bad(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        g = np.asarray(grad, dtype=np.float64)
+        m = beta1 * np.asarray(m) + (1.0 - beta1) * g
+        v = beta2 * np.asarray(v) + (1.0 - beta2) * g * g
+        return np.asarray(params) - lr * m / (np.sqrt(v) + eps), m, v
+    with patched(ae, "adam", bad):
+        _fails(T.test_adam_constant_gradient_closed_form)
+
+
+def test_fallback_without_floor_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+
+    def bad(fields, recon, gmax):
+        f = np.stack([np.asarray(a) for a in fields], axis=1)
+        r = np.stack([np.asarray(a) for a in recon], axis=1)
+        s = np.abs(f).max(axis=(2, 3, 4))
+        err = np.abs(f - r).max(axis=(2, 3, 4))
+        return np.any(err > 1e-3 * s, axis=1)          # no floor
+    with patched(ae, "fallback", bad):
+        _fails(T.test_fallback_rule_at_its_boundary)
+
+
+def test_total_degree_truncation_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+    orig = ae.modal_truncate
+
+    def bad(fields, quantize=True):
+        r, keep = orig(fields, quantize)
+        # total degree <= 1 (4 modes) instead of every degree <= 1 (8 modes)
+        k = keep.copy()
+        k[:, :, 1, 1, :] = 0
+        k[:, :, 1, :, 1] = 0
+        k[:, :, :, 1, 1] = 0
+        v2 = ae.legendre_vandermonde()[:, :2]
+        return np.einsum("ka,lb,mc,xyabc->xyklm", v2, v2, v2, k), k
+    with patched(ae, "modal_truncate", bad):
+        _fails(T.test_modal_truncation_keeps_its_span_and_drops_higher_modes)
+
+
+def test_pca_init_with_trailing_eigenvectors_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+
+    def bad(c, r):
+        lam, u = np.linalg.eigh(c)
+        return lam[:r], u[:, :r]                        # smallest, not largest
+    with patched(ae, "_leading_eigvecs", bad):
+        _fails(T.test_pca_init_is_exact_on_data_of_low_rank)

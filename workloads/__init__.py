@@ -28,6 +28,7 @@ __all__ = [
     "gll_points", "axis_lattice", "box_mesh", "element_axes", "tgv_velocity",
     "channel_modes", "channel_velocity", "warp", "tgv_config", "channel_config",
     "lattice_gid", "batch_spec", "batch_snapshot", "CHANNEL_SHAPE", "TGV_SHAPE",
+    "ae_fields", "ae_training_elements", "AE_SHAPE", "AE_PHASES",
 ]
 
 TGV_SHAPE = (8, 8, 8)          # Taylor-Green box [0, 2 pi]^3, 512 elements
@@ -260,3 +261,63 @@ def batch_snapshot(seed, device, dtype=None, features=256, chunk=1 << 22, e_min=
     if dtype is not None:
         out = tuple(t.to(dtype).contiguous() for t in out)
     return (n, shape, beta), out
+
+
+# --------------------------------------------------------------------------
+# compression snapshots: Taylor-Green velocity and a random scalar, advected
+# --------------------------------------------------------------------------
+
+AE_SHAPE = (64, 64, 64)          # 262,144 order-7 elements on [0, 2 pi]^3
+AE_PHASES = 64
+AE_DRIFT = (1.0, 0.5, 0.25)      # translation direction of the advected fields
+AE_THETA_SEED = 4096
+
+
+def ae_fields(phase, device, shape=AE_SHAPE, elements=None, dtype=None, features=256,
+              chunk=1 << 22):
+    """(u, v, w, theta) of compression snapshot `phase` (0 <= phase < 64) on
+    `device` (torch), order 7, uniform box [0, 2 pi]^3 of `shape` elements
+    (or the subset `elements`, numbered as in element_axes).
+
+    Every field is a fixed pattern translated by t = 2 pi phase / 64 along
+    AE_DRIFT, f(x - t d): the Taylor-Green velocity and a Gaussian random
+    scalar theta by random Fourier features (Rahimi & Recht 2007; 256
+    features, k ~ N(0, 1 / l^2) with l = 0.1 of the domain, seeded).  The
+    phase may be fractional (a held-out time between training phases)."""
+    import torch
+    n, p = 7, 8
+    lat = [torch.from_numpy(axis_lattice(shape[a], n, 0.0, 2 * np.pi)).to(device)
+           for a in range(3)]
+    ex, ey, ez = (torch.from_numpy(np.asarray(c)).to(device)
+                  for c in element_axes(shape, elements))
+    loc = torch.arange(p, device=device)
+    t = 2 * np.pi * float(phase) / AE_PHASES
+    xs = lat[0][ex[:, None] * n + loc[None, :]] - t * AE_DRIFT[0]
+    ys = lat[1][ey[:, None] * n + loc[None, :]] - t * AE_DRIFT[1]
+    zs = lat[2][ez[:, None] * n + loc[None, :]] - t * AE_DRIFT[2]
+    e_cnt = xs.shape[0]
+    x = xs[:, None, None, :].expand(e_cnt, p, p, p)
+    y = ys[:, None, :, None].expand(e_cnt, p, p, p)
+    z = zs[:, :, None, None].expand(e_cnt, p, p, p)
+    u, v, w = tgv_velocity(x, y, z)
+    rng = np.random.default_rng(AE_THETA_SEED)
+    ell = 0.1 * 2 * np.pi
+    kf = torch.from_numpy(rng.normal(0.0, 1.0 / ell, size=(features, 3))).to(device)
+    bf = torch.from_numpy(rng.uniform(0.0, 2.0 * np.pi, size=features)).to(device)
+    pts = torch.stack([x.reshape(-1), y.reshape(-1), z.reshape(-1)], dim=1)
+    theta = torch.empty(pts.shape[0], dtype=pts.dtype, device=device)
+    for c0 in range(0, pts.shape[0], chunk):
+        ph = pts[c0:c0 + chunk] @ kf.T + bf
+        theta[c0:c0 + chunk] = torch.cos(ph).sum(dim=1) * math.sqrt(2.0 / features)
+    out = (u.contiguous(), v.contiguous(), w.contiguous(), theta.reshape(e_cnt, p, p, p))
+    if dtype is not None:
+        out = tuple(f.to(dtype).contiguous() for f in out)
+    return out
+
+
+def ae_training_elements(seed, count, shape=AE_SHAPE, phases=AE_PHASES):
+    """(phase, element) pairs of a training sample: `count` elements drawn
+    uniformly from the integer phases and the mesh, seeded."""
+    rng = np.random.default_rng(30_000 + seed)
+    n_el = shape[0] * shape[1] * shape[2]
+    return rng.integers(0, phases, size=count), rng.integers(0, n_el, size=count)
