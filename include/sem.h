@@ -79,7 +79,8 @@ enum {
   SEM_FLAG_BAD_JACOBIAN = 1,   /* det J <= 0 at some node                         */
   SEM_FLAG_TRI_OVERFLOW = 2,   /* triangles did not fit (counts stay exact)       */
   SEM_FLAG_BAD_ID = 4,         /* a node id or edge key outside its valid range   */
-  SEM_FLAG_VERT_OVERFLOW = 8   /* welded vertices did not fit (count stays exact) */
+  SEM_FLAG_VERT_OVERFLOW = 8,  /* welded vertices did not fit (count stays exact) */
+  SEM_FLAG_RAW_OVERFLOW = 16   /* raw fallback blocks did not fit (count exact)   */
 };
 
 #define SEM_MIN_ORDER 1
@@ -374,6 +375,109 @@ int sem_timing_begin(int max_spans);
  * releases the events, and returns the number of dropped spans (>= 0), or
  * SEM_ERR_ARG when timing was not on, SEM_ERR_HIP on a runtime error. */
 int64_t sem_timing_end(double* ms_total, int64_t* spans, int n_phases);
+
+/* ---------------------------------------------------------------------
+ * Learned in-transit compression (order 7, FP32 fields u, v, w, theta)
+ * ---------------------------------------------------------------------
+ * The in-transit workflow (section 4.2) ships every snapshot from the
+ * simulation nodes to visualisation nodes; this compressor cuts the bytes.
+ * Per element, each channel is divided by its element maximum s_ec and the
+ * 4 x 8^3 block goes through a convolutional autoencoder: three
+ * kernel-2 stride-2 convolutions 4 -> 32 -> 64 -> 32 channels (8^3 -> 4^3
+ * -> 2^3 -> 1: the 32-value latent, stored as IEEE binary16) and three
+ * kernel-2 stride-2 transposed convolutions 32 -> 64 -> 32 -> 4 back.  Layers
+ * are linear; tanh_mask (bits 0, 1, 3, 4 only: SEM_AE_TANH_HIDDEN) adds tanh
+ * after hidden layers.  An element whose reconstruction misses
+ * max |f - f_hat| <= 1e-3 max(s_ec, 1e-3 max_e s_ec) on any channel is
+ * shipped raw instead.
+ *
+ * Parameters (FP32, sem_ae_param_count() values): for each layer, weights
+ * then biases; a convolution's weight (d, i, o) at (d Cin + i) Cout + o, a
+ * transposed one's at (i 8 + d) Cout + o, d = dx + 2 dy + 4 dz.
+ * Blocks (the network's input layout, FP32 [E][512][4]): value (i, j, k) of
+ * channel c at [e][m][c], m the Morton index (bits i0 j0 k0 i1 j1 k1 i2 j2 k2
+ * from the least significant).  Every pointer is DEVICE memory; workspace
+ * sizes come from the matching *_workspace_bytes call. */
+#define SEM_AE_LATENT 32
+#define SEM_AE_TANH_HIDDEN 0x1B
+
+int64_t sem_ae_param_count(void);
+
+/* Workspace of sem_ae_forward / sem_ae_grad for a batch of n elements. */
+size_t sem_ae_workspace_bytes(int64_t n);
+
+/* Normalised blocks [E][512][4] and element maxima scale[E][4] of four
+ * fields [E][8][8][8] (GLL layout). */
+int sem_ae_blocks(int64_t n_elem, const float* u, const float* v, const float* w,
+                  const float* theta, float* blocks, float* scale, void* stream);
+
+/* Network on n blocks: reconstruction [n][512][4] (normalised, may be NULL)
+ * and binary16 latent [n][32] (may be NULL). */
+int sem_ae_forward(int64_t n, const float* blocks, const float* params, int tanh_mask,
+                   float* recon, uint16_t* latent, void* workspace, size_t workspace_bytes,
+                   void* stream);
+
+/* Mean-squared-error loss (*loss, device float, may be NULL) and its
+ * gradient grad[sem_ae_param_count()] on the batch pool[idx[r]], r < n (idx
+ * NULL: the first n blocks of the pool).  The latent is rounded to binary16
+ * in the forward pass and its gradient passed through unchanged.  An index
+ * outside [0, n_pool) sets SEM_FLAG_BAD_ID and contributes a zero block. */
+int sem_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
+                const float* params, int tanh_mask, float* grad, float* loss,
+                void* workspace, size_t workspace_bytes, int32_t* status_word, void* stream);
+
+/* One Adam step (Kingma & Ba 2015) on n values; step counts from 1. */
+int sem_ae_adam(int64_t n, float* params, const float* grad, float* m, float* v, int step,
+                float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Symmetric eigenproblem of the n x n FP64 matrix a (n even, 2 <= n <= 512),
+ * cyclic Jacobi: the r largest eigenvalues in decreasing order into lam[r]
+ * (may be NULL) and their eigenvectors into vec[n][r] (FP32, each signed so
+ * that its largest-magnitude entry is positive); *sweeps (device int, may
+ * be NULL) receives the sweeps used. */
+size_t sem_eig_workspace_bytes(int n);
+int sem_sym_eig(int n, const double* a, int r, double* lam, float* vec, void* workspace,
+                size_t workspace_bytes, int* sweeps, void* stream);
+
+/* Parameters from layer-wise principal components of n_pool blocks
+ * (1 <= n_pool <= 2^24): layer
+ * 0 the identity on each 2^3 patch, layers 1 and 2 the 64 and 32 leading
+ * eigenvectors of the second-moment matrices of their inputs, decoder
+ * layers the transposes, biases zero; lam (may be NULL) receives the 64 +
+ * 32 eigenvalues. */
+size_t sem_ae_pca_workspace_bytes(int64_t n_pool);
+int sem_ae_pca_init(int64_t n_pool, const float* pool, float* params, double* lam,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Compress E elements: binary16 latent [E][32], scale [E][4], flags [E]
+ * (1 = raw), the raw elements' fields packed in element order into
+ * raw[raw_cap][4][512] and their count into *n_raw (device int64; exact even
+ * when raw_cap is too small, which sets SEM_FLAG_RAW_OVERFLOW). */
+size_t sem_ae_compress_workspace_bytes(int64_t n_elem);
+int sem_ae_compress(int64_t n_elem, const float* u, const float* v, const float* w,
+                    const float* theta, const float* params, int tanh_mask, uint16_t* latent,
+                    float* scale, uint8_t* flags, float* raw, int64_t raw_cap, int64_t* n_raw,
+                    void* workspace, size_t workspace_bytes, int32_t* status_word,
+                    void* stream);
+
+/* Fields [E][8][8][8] from a compressed snapshot (workspace: the
+ * compression's size for E).  raw holds raw_count blocks (raw may be NULL
+ * when raw_count is 0); a flagged element past them decodes from its latent
+ * and sets SEM_FLAG_RAW_OVERFLOW. */
+int sem_ae_decompress(int64_t n_elem, const uint16_t* latent, const float* scale,
+                      const uint8_t* flags, const float* raw, int64_t raw_count,
+                      const float* params, int tanh_mask, float* u, float* v, float* w,
+                      float* theta, void* workspace, size_t workspace_bytes,
+                      int32_t* status_word, void* stream);
+
+/* Non-learned baseline at the same bytes: per channel the eight Legendre
+ * coefficients with degrees in {0, 1}^3 of the element's interpolant (GLL
+ * quadrature), stored as binary16 of c / s_ec into coef[E][4][8]; scale,
+ * fallback flags by the same rule, reconstructions (may be NULL). */
+int sem_modal_compress(int64_t n_elem, const float* u, const float* v, const float* w,
+                       const float* theta, uint16_t* coef, float* scale, uint8_t* flags,
+                       float* ru, float* rv, float* rw, float* rtheta, void* workspace,
+                       size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,9 @@ SEM_ERR_HIP, SEM_ERR_WORKSPACE, SEM_ERR_DTYPE = -4, -5, -6
 SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW = 1, 2, 4, 8
 SEM_MIN_ORDER, SEM_MAX_ORDER = 1, 9
 SEM_MAX_ISO = 64
+SEM_FLAG_RAW_OVERFLOW = 16
+SEM_AE_LATENT = 32
+SEM_AE_TANH_HIDDEN = 0x1B
 BATCH_VARIANTS = 6          # variants of the batched kernel (sem_autotune)
 SEM_MC_MAX_TRI = 5
 SEM_PHASE_QCRIT, SEM_PHASE_COUNT, SEM_PHASE_SCAN, SEM_PHASE_EMIT = 0, 1, 2, 3
@@ -39,6 +42,10 @@ EXPORTS = (
     "sem_weld_workspace_bytes", "sem_weld",
     "sem_batch_plan_bytes", "sem_batch_plan", "sem_qcrit_batch", "sem_autotune",
     "sem_batch_variant", "sem_batch_set_variant",
+    "sem_ae_param_count", "sem_ae_workspace_bytes", "sem_ae_blocks", "sem_ae_forward",
+    "sem_ae_grad", "sem_ae_adam", "sem_eig_workspace_bytes", "sem_sym_eig",
+    "sem_ae_pca_workspace_bytes", "sem_ae_pca_init", "sem_ae_compress_workspace_bytes",
+    "sem_ae_compress", "sem_ae_decompress", "sem_modal_compress",
 )
 
 
@@ -124,6 +131,36 @@ def lib():
         L.sem_batch_variant.argtypes = [i32, i32]
         L.sem_batch_set_variant.restype = i32
         L.sem_batch_set_variant.argtypes = [i32, i32, i32]
+        sz, flt = ctypes.c_size_t, ctypes.c_float
+        L.sem_ae_param_count.restype = i64
+        L.sem_ae_param_count.argtypes = []
+        L.sem_ae_workspace_bytes.restype = sz
+        L.sem_ae_workspace_bytes.argtypes = [i64]
+        L.sem_ae_blocks.restype = i32
+        L.sem_ae_blocks.argtypes = [i64] + [vp] * 7
+        L.sem_ae_forward.restype = i32
+        L.sem_ae_forward.argtypes = [i64, vp, vp, i32, vp, vp, vp, sz, vp]
+        L.sem_ae_grad.restype = i32
+        L.sem_ae_grad.argtypes = [i64, vp, i64, vp, vp, i32, vp, vp, vp, sz, vp, vp]
+        L.sem_ae_adam.restype = i32
+        L.sem_ae_adam.argtypes = [i64, vp, vp, vp, vp, i32, flt, flt, flt, flt, vp]
+        L.sem_eig_workspace_bytes.restype = sz
+        L.sem_eig_workspace_bytes.argtypes = [i32]
+        L.sem_sym_eig.restype = i32
+        L.sem_sym_eig.argtypes = [i32, vp, i32, vp, vp, vp, sz, vp, vp]
+        L.sem_ae_pca_workspace_bytes.restype = sz
+        L.sem_ae_pca_workspace_bytes.argtypes = [i64]
+        L.sem_ae_pca_init.restype = i32
+        L.sem_ae_pca_init.argtypes = [i64, vp, vp, vp, vp, sz, vp]
+        L.sem_ae_compress_workspace_bytes.restype = sz
+        L.sem_ae_compress_workspace_bytes.argtypes = [i64]
+        L.sem_ae_compress.restype = i32
+        L.sem_ae_compress.argtypes = [i64] + [vp] * 5 + [i32, vp, vp, vp, vp, i64, vp, vp, sz,
+                                                        vp, vp]
+        L.sem_ae_decompress.restype = i32
+        L.sem_ae_decompress.argtypes = [i64] + [vp] * 4 + [i64, vp, i32] + [vp] * 5 + [sz, vp, vp]
+        L.sem_modal_compress.restype = i32
+        L.sem_modal_compress.argtypes = [i64] + [vp] * 12 + [sz, vp]
         del dbl
         _lib = L
     return _lib
@@ -630,3 +667,201 @@ def batch_set_variant(order, dtype_code, variant, device=None):
     init(device)
     _check(lib().sem_batch_set_variant(int(order), int(dtype_code), int(variant)),
            "sem_batch_set_variant")
+
+
+# ---------------------------------------------------------------------------
+# learned in-transit compression (order 7, FP32 u, v, w, theta)
+# ---------------------------------------------------------------------------
+
+def _ae_fields(fields):
+    torch = _torch()
+    if len(fields) != 4:
+        raise ValueError("four fields (u, v, w, theta)")
+    ref = fields[0]
+    if ref.dtype != torch.float32 or _order_of(ref) != 7:
+        raise TypeError("compression takes float32 order-7 fields")
+    _field_check(ref, *fields)
+    init(ref.device.index)
+    return ref
+
+
+def _ws(nbytes, ref):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=ref.device)
+
+
+def ae_param_count():
+    return int(lib().sem_ae_param_count())
+
+
+def ae_blocks(fields):
+    """(blocks [E, 512, 4] Morton order, scale [E, 4]) of (u, v, w, theta)."""
+    torch = _torch()
+    ref = _ae_fields(fields)
+    e = ref.shape[0]
+    blocks = torch.empty((e, 512, 4), dtype=torch.float32, device=ref.device)
+    scale = torch.empty((e, 4), dtype=torch.float32, device=ref.device)
+    _check(lib().sem_ae_blocks(e, *(f.data_ptr() for f in fields), blocks.data_ptr(),
+                               scale.data_ptr(), _stream(ref)), "sem_ae_blocks")
+    return blocks, scale
+
+
+def ae_forward(blocks, params, tanh_mask=0):
+    """(reconstruction [n, 512, 4], binary16 latent [n, 32]) of n blocks."""
+    torch = _torch()
+    n = blocks.shape[0]
+    recon = torch.empty_like(blocks)
+    latent = torch.empty((n, SEM_AE_LATENT), dtype=torch.float16, device=blocks.device)
+    ws = _ws(lib().sem_ae_workspace_bytes(n), blocks)
+    _check(lib().sem_ae_forward(n, blocks.data_ptr(), params.data_ptr(), int(tanh_mask),
+                                recon.data_ptr(), latent.data_ptr(), ws.data_ptr(), ws.numel(),
+                                _stream(blocks)), "sem_ae_forward")
+    return recon, latent
+
+
+def ae_grad(pool, params, idx=None, n=None, tanh_mask=0, grad=None, workspace=None,
+            status=None):
+    """(loss [1] float32, grad) of the batch pool[idx] (or the first n)."""
+    torch = _torch()
+    if idx is not None:
+        if idx.dtype != torch.int64 or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int64 tensor")
+        n = idx.numel()
+    elif n is None:
+        n = pool.shape[0]
+    if grad is None:
+        grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=pool.device)
+    if workspace is None:
+        workspace = _ws(lib().sem_ae_workspace_bytes(n), pool)
+    _check(lib().sem_ae_grad(n, pool.data_ptr(), pool.shape[0], _ptr(idx), params.data_ptr(),
+                             int(tanh_mask), grad.data_ptr(), loss.data_ptr(),
+                             workspace.data_ptr(), workspace.numel(), _ptr(status),
+                             _stream(pool)), "sem_ae_grad")
+    return loss, grad
+
+
+def ae_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().sem_ae_adam(params.numel(), params.data_ptr(), grad.data_ptr(), m.data_ptr(),
+                             v.data_ptr(), int(step), float(lr), float(beta1), float(beta2),
+                             float(eps), _stream(params)), "sem_ae_adam")
+
+
+def sym_eig(a, r):
+    """(r leading eigenvalues, eigenvectors [n, r] float32, sweeps) of the
+    symmetric float64 matrix a [n, n] (n even, <= 512)."""
+    torch = _torch()
+    n = a.shape[0]
+    init(a.device.index)
+    lam = torch.empty(r, dtype=torch.float64, device=a.device)
+    vec = torch.empty((n, r), dtype=torch.float32, device=a.device)
+    sweeps = torch.zeros(1, dtype=torch.int32, device=a.device)
+    ws = _ws(lib().sem_eig_workspace_bytes(n), a)
+    _check(lib().sem_sym_eig(n, a.contiguous().data_ptr(), int(r), lam.data_ptr(),
+                             vec.data_ptr(), ws.data_ptr(), ws.numel(), sweeps.data_ptr(),
+                             _stream(a)), "sem_sym_eig")
+    return lam, vec, sweeps
+
+
+def ae_pca_init(pool):
+    """(params, eigenvalues [96]) from layer-wise principal components of the
+    blocks pool [n, 512, 4]."""
+    torch = _torch()
+    init(pool.device.index)
+    params = torch.empty(ae_param_count(), dtype=torch.float32, device=pool.device)
+    lam = torch.empty(96, dtype=torch.float64, device=pool.device)
+    ws = _ws(lib().sem_ae_pca_workspace_bytes(pool.shape[0]), pool)
+    _check(lib().sem_ae_pca_init(pool.shape[0], pool.data_ptr(), params.data_ptr(),
+                                 lam.data_ptr(), ws.data_ptr(), ws.numel(), _stream(pool)),
+           "sem_ae_pca_init")
+    return params, lam
+
+
+def ae_train(pool, params, steps, batch=2048, lr=1e-4, seed=0, tanh_mask=0, m=None, v=None,
+             step0=0, loss_every=0):
+    """Adam on the mean-squared error of random batches of the pool (indices
+    drawn on the device from a seeded generator); returns (m, v, losses)."""
+    torch = _torch()
+    if m is None:
+        m = torch.zeros_like(params)
+    if v is None:
+        v = torch.zeros_like(params)
+    gen = torch.Generator(device=pool.device).manual_seed(seed)
+    ws = _ws(lib().sem_ae_workspace_bytes(batch), pool)
+    grad = torch.empty_like(params)
+    losses = []
+    for t in range(1, steps + 1):
+        idx = torch.randint(0, pool.shape[0], (batch,), device=pool.device, generator=gen)
+        loss, _ = ae_grad(pool, params, idx=idx, tanh_mask=tanh_mask, grad=grad, workspace=ws)
+        ae_adam(params, grad, m, v, step0 + t, lr)
+        if loss_every and (t % loss_every == 0 or t == steps):
+            losses.append((t, float(loss.item())))
+    return m, v, losses
+
+
+def ae_compress(fields, params, tanh_mask=0, raw_cap=None, status=None):
+    """Compressed snapshot: dict(latent [E, 32] float16, scale [E, 4],
+    flags [E] uint8, raw [n_raw, 4, 512], n_raw)."""
+    torch = _torch()
+    ref = _ae_fields(fields)
+    e = ref.shape[0]
+    dev = ref.device
+    latent = torch.empty((e, SEM_AE_LATENT), dtype=torch.float16, device=dev)
+    scale = torch.empty((e, 4), dtype=torch.float32, device=dev)
+    flags = torch.empty(e, dtype=torch.uint8, device=dev)
+    n_raw = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = _ws(lib().sem_ae_compress_workspace_bytes(e), ref)
+    cap = e if raw_cap is None else int(raw_cap)
+    raw = torch.empty((max(cap, 1), 4, 512), dtype=torch.float32, device=dev)
+    _check(lib().sem_ae_compress(e, *(f.data_ptr() for f in fields), params.data_ptr(),
+                                 int(tanh_mask), latent.data_ptr(), scale.data_ptr(),
+                                 flags.data_ptr(), raw.data_ptr(), cap, n_raw.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _ptr(status), _stream(ref)),
+           "sem_ae_compress")
+    k = int(n_raw.item())
+    return {"latent": latent, "scale": scale, "flags": flags, "raw": raw[:min(k, cap)],
+            "n_raw": k}
+
+
+def ae_decompress(packet, params, tanh_mask=0, status=None):
+    """(u, v, w, theta) [E, 8, 8, 8] from a compressed snapshot."""
+    torch = _torch()
+    latent = packet["latent"]
+    e = latent.shape[0]
+    dev = latent.device
+    init(dev.index)
+    out = [torch.empty((e, 8, 8, 8), dtype=torch.float32, device=dev) for _ in range(4)]
+    ws = _ws(lib().sem_ae_compress_workspace_bytes(e), latent)
+    raw = packet["raw"]
+    _check(lib().sem_ae_decompress(e, latent.data_ptr(), packet["scale"].data_ptr(),
+                                   packet["flags"].data_ptr(),
+                                   raw.data_ptr() if raw.numel() else None, raw.shape[0],
+                                   params.data_ptr(), int(tanh_mask),
+                                   *(t.data_ptr() for t in out), ws.data_ptr(), ws.numel(),
+                                   _ptr(status), _stream(latent)), "sem_ae_decompress")
+    return tuple(out)
+
+
+def modal_compress(fields, recon=True):
+    """Legendre modal truncation baseline: dict(coef [E, 4, 8] float16,
+    scale, flags, recon (u, v, w, theta) or None)."""
+    torch = _torch()
+    ref = _ae_fields(fields)
+    e = ref.shape[0]
+    dev = ref.device
+    coef = torch.empty((e, 4, 8), dtype=torch.float16, device=dev)
+    scale = torch.empty((e, 4), dtype=torch.float32, device=dev)
+    flags = torch.empty(e, dtype=torch.uint8, device=dev)
+    r = [torch.empty_like(ref) for _ in range(4)] if recon else [None] * 4
+    ws = _ws(lib().sem_ae_compress_workspace_bytes(e), ref)
+    _check(lib().sem_modal_compress(e, *(f.data_ptr() for f in fields), coef.data_ptr(),
+                                    scale.data_ptr(), flags.data_ptr(), *(_ptr(t) for t in r),
+                                    ws.data_ptr(), ws.numel(), _stream(ref)),
+           "sem_modal_compress")
+    return {"coef": coef, "scale": scale, "flags": flags, "recon": tuple(r) if recon else None}
+
+
+def compressed_bytes(n_elem, n_raw):
+    """Bytes shipped for a compressed snapshot: binary16 latent, FP32 scales
+    and a flag byte per element, and the raw elements' 4 x 512 FP32 values."""
+    return n_elem * (SEM_AE_LATENT * 2 + 4 * 4 + 1) + n_raw * 4 * 512 * 4

@@ -1,0 +1,1153 @@
+// Per-element autoencoder compression of order-7 snapshots (u, v, w, theta)
+// for the in-transit hand-off (section 4.2 ships every snapshot to separate
+// visualisation nodes; here its bytes shrink first).
+//
+// Blocks are kept in Morton order: value (i, j, k) of channel c of element e
+// at X[e][m][c] with m the bit interleave (i0 j0 k0 i1 j1 k1 i2 j2 k2, from
+// the least significant bit).  Then node 8 p + d of a grid is position d =
+// dx + 2 dy + 4 dz of the 2^3 patch p of the grid one level coarser, so a
+// kernel-2 stride-2 convolution reads each output position's 8 x Cin inputs
+// as one contiguous row, and a transposed one writes 8 x Cout contiguous
+// outputs: every layer is a plain row-major GEMM
+//   conv:  Y[rows][Cout]   = X[rows][8 Cin] W[8 Cin][Cout] + b
+//   convT: Y[rows][8 Cout] = X[rows][Cin]   W[Cin][8 Cout] + b (b per Cout)
+// with rows = element x output position, and the parameter layouts
+// W[(d Cin + i) Cout + o] (conv) and W[(i 8 + d) Cout + o] (convT).
+//
+// Training: forward (GEMMs with fused bias / tanh / binary16 rounding of the
+// latent), output gradient and loss, backward GEMMs (input gradients with
+// the tanh derivative fused; weight gradients as split reductions summed in
+// a fixed order), Adam.  Initialisation: layer-wise principal components
+// from FP64 Gram matrices and a cyclic Jacobi eigensolver.  Compression:
+// encode, decode, per-element error check, raw blocks compacted by an
+// exclusive scan; decompression reverses it.
+
+#include <cmath>
+#include <cstdint>
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "sem_internal.h"
+
+namespace sem {
+namespace {
+
+constexpr int kT = 256;
+
+__host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+__device__ __forceinline__ int morton8(int i, int j, int k) {
+  int m = 0;
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+    m |= (((i >> l) & 1) << (3 * l)) | (((j >> l) & 1) << (3 * l + 1)) |
+         (((k >> l) & 1) << (3 * l + 2));
+  return m;
+}
+
+__device__ __forceinline__ float half_round(float v) {
+  return __half2float(__float2half_rn(v));
+}
+
+template <typename T>
+__device__ __forceinline__ T block_max_pos(T v, T* red) {
+  // max of non-negative values over a 256-thread block
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const T o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  T r = red[0];
+#pragma unroll
+  for (int i = 1; i < kT / 64; ++i) r = red[i] > r ? red[i] : r;
+  __syncthreads();
+  return r;
+}
+
+__global__ void fill_f32(float* p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// blocks: per-channel element maxima, normalised Morton blocks
+// ---------------------------------------------------------------------------
+
+// s[e][c] = max |f_c| over element e; gmax_bits[c] = bits of max_e s[e][c]
+// (non-negative floats order like their bit patterns).
+__global__ void __launch_bounds__(kT)
+ae_scales(int64_t e_begin, const float* __restrict__ u, const float* __restrict__ v,
+          const float* __restrict__ w, const float* __restrict__ th, float* __restrict__ scale,
+          uint32_t* __restrict__ gmax_bits) {
+  __shared__ float red[kT / 64];
+  const int64_t e = e_begin + blockIdx.x;
+  const float* f[4] = {u, v, w, th};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float* src = f[c] + e * 512;
+    const float a = fabsf(src[threadIdx.x]), b = fabsf(src[threadIdx.x + 256]);
+    const float m = block_max_pos(a > b ? a : b, red);
+    if (threadIdx.x == 0) {
+      scale[e * 4 + c] = m;
+      if (gmax_bits) atomicMax(gmax_bits + c, __float_as_uint(m));
+    }
+  }
+}
+
+// X[r][m][c] = f_c(node of m) / s[e][c] (0 for a vanishing channel), element
+// e = e_begin + r.
+__global__ void __launch_bounds__(kT)
+ae_pack(int64_t e_begin, const float* __restrict__ u, const float* __restrict__ v,
+        const float* __restrict__ w, const float* __restrict__ th,
+        const float* __restrict__ scale, float* __restrict__ x) {
+  const int64_t e = e_begin + blockIdx.x;
+  const float* f[4] = {u, v, w, th};
+  float s[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s[c] = scale[e * 4 + c];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int n = threadIdx.x + 256 * h;
+    const int m = morton8(n & 7, (n >> 3) & 7, n >> 6);
+    float4 o;
+    float* op = reinterpret_cast<float*>(&o);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) op[c] = s[c] > 0.f ? f[c][e * 512 + n] / s[c] : 0.f;
+    reinterpret_cast<float4*>(x + (int64_t)blockIdx.x * 2048)[m] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM with strided operands and fused epilogue (FP32)
+// ---------------------------------------------------------------------------
+//
+// C[z][m][n] = sum_{k in split z} A(m, k) B(k, n), A(m, k) = A[m a_sm + k a_sk],
+// B(k, n) = B[k b_sk + n b_sn].  Epilogue (flags): + bias[n % bias_mod], tanh,
+// binary16 rounding, times (1 - D[m][n]^2).  64 x 64 tiles, 16-deep k steps,
+// 256 threads with 4 x 4 outputs each.
+
+enum : int { kEpiTanh = 1, kEpiHalf = 2, kEpiTanhGrad = 4 };
+constexpr int kBM = 64, kBN = 64, kBK = 16;
+
+struct GemmArgs {
+  int64_t M;
+  int N;
+  int64_t K;
+  const float* A;
+  int64_t a_sm, a_sk;
+  const float* B;
+  int64_t b_sk, b_sn;
+  float* C;
+  int64_t ldc;
+  int64_t k_split;       // reduction length per grid.z slice
+  int64_t c_split;       // stride between the slices' C
+  const float* bias;
+  int bias_mod;
+  int flags;
+  const float* D;        // tanh-derivative source, layout of C
+};
+
+__global__ void __launch_bounds__(kT) gemm_f32(GemmArgs g) {
+  __shared__ float As[kBK][kBM + 4];
+  __shared__ float Bs[kBK][kBN + 4];
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  const int64_t m0 = (int64_t)blockIdx.x * kBM;   // rows on x: up to 2^31 - 1 tiles
+  const int n0 = blockIdx.y * kBN;
+  const int64_t kb = (int64_t)blockIdx.z * g.k_split;
+  const int64_t ke = kb + g.k_split < g.K ? kb + g.k_split : g.K;
+  float acc[4][4] = {};
+  for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
+    // A tile: kBM x kBK; the index order follows the contiguous operand axis
+#pragma unroll
+    for (int q = 0; q < (kBM * kBK) / kT; ++q) {
+      const int idx = t + q * kT;
+      int mm, kk;
+      if (g.a_sk == 1) { kk = idx % kBK; mm = idx / kBK; }
+      else { mm = idx % kBM; kk = idx / kBM; }
+      const int64_t m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < ke) ? g.A[m * g.a_sm + k * g.a_sk] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < (kBN * kBK) / kT; ++q) {
+      const int idx = t + q * kT;
+      int nn, kk;
+      if (g.b_sn == 1) { nn = idx % kBN; kk = idx / kBN; }
+      else { kk = idx % kBK; nn = idx / kBK; }
+      const int n = n0 + nn;
+      const int64_t k = k0 + kk;
+      Bs[kk][nn] = (n < g.N && k < ke) ? g.B[k * g.b_sk + (int64_t)n * g.b_sn] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kBK; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  float* C = g.C + (int64_t)blockIdx.z * g.c_split;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t m = m0 + ty + 16 * i;
+    if (m >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx + 16 * j;
+      if (n >= g.N) continue;
+      float v = acc[i][j];
+      if (g.bias) v += g.bias[n % g.bias_mod];
+      if (g.flags & kEpiTanh) v = tanhf(v);
+      if (g.flags & kEpiHalf) v = half_round(v);
+      if (g.flags & kEpiTanhGrad) {
+        const float d = g.D[m * g.ldc + n];
+        v *= 1.f - d * d;
+      }
+      C[m * g.ldc + n] = v;
+    }
+  }
+}
+
+// out[i] = sum_z part[z][i] in order z = 0, 1, ... (deterministic)
+__global__ void sum_splits(const float* __restrict__ part, int64_t n, int splits,
+                           float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + i];
+  out[i] = s;
+}
+
+// part[z][col] = sum of G[rows of slice z][col]
+__global__ void colsum_splits(const float* __restrict__ G, int64_t rows, int cols,
+                              int64_t rows_per, float* __restrict__ part) {
+  const int col = blockIdx.x * kT + threadIdx.x;
+  if (col >= cols) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+  const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
+  float s = 0.f;
+  for (int64_t r = r0; r < r1; ++r) s += G[r * cols + col];
+  part[(int64_t)blockIdx.y * cols + col] = s;
+}
+
+// db[o] = sum_z sum_d part[z][d * cout + o] (fold = 8 for convT, 1 for conv)
+__global__ void fold_bias(const float* __restrict__ part, int splits, int cols, int cout,
+                          float* __restrict__ db) {
+  const int o = blockIdx.x * kT + threadIdx.x;
+  if (o >= cout) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z)
+    for (int d = 0; d < cols / cout; ++d) s += part[(int64_t)z * cols + d * cout + o];
+  db[o] = s;
+}
+
+// ---------------------------------------------------------------------------
+// loss, gather, Adam, binary16 conversion
+// ---------------------------------------------------------------------------
+
+// g = 2 (y - x) / count; per-block partial sums of (y - x)^2 in FP64
+__global__ void __launch_bounds__(kT)
+out_grad(const float* __restrict__ y, const float* __restrict__ x, int64_t n, float inv2,
+         float* __restrict__ g, double* __restrict__ part) {
+  __shared__ double red[kT / 64];
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  double sq = 0.0;
+  if (i < n) {
+    const float d = y[i] - x[i];
+    g[i] = inv2 * d;
+    sq = (double)d * d;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(1024)
+loss_reduce(const double* __restrict__ part, int64_t nb, double inv_n, float* __restrict__ loss) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nb; i += 1024) s += part[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int i = 0; i < 16; ++i) tot += red[i];
+    *loss = (float)(tot * inv_n);
+  }
+}
+
+__global__ void gather_blocks(const float* __restrict__ pool, const int64_t* __restrict__ idx,
+                              int64_t n, int64_t n_pool, float* __restrict__ out,
+                              int32_t* __restrict__ status) {
+  const int64_t r = blockIdx.x;
+  const int64_t src = idx ? idx[r] : r;
+  if (src < 0 || src >= n_pool) {
+    if (threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_BAD_ID);
+    for (int q = threadIdx.x; q < 2048; q += kT) out[r * 2048 + q] = 0.f;
+    return;
+  }
+  for (int q = threadIdx.x; q < 2048; q += kT) out[r * 2048 + q] = pool[src * 2048 + q];
+}
+
+__global__ void adam_step(int64_t n, float* __restrict__ p, const float* __restrict__ g,
+                          float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                          float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+__global__ void to_half_bits(const float* __restrict__ z, int64_t n, uint16_t* __restrict__ h) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) h[i] = __half_as_ushort(__float2half_rn(z[i]));
+}
+
+__global__ void from_half_bits(const uint16_t* __restrict__ h, int64_t n, float* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) z[i] = __half2float(__ushort_as_half(h[i]));
+}
+
+// W^T: out[c][r] = in[r][c]
+__global__ void transpose_f32(const float* __restrict__ in, int rows, int cols,
+                              float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int r = (int)(i / cols), c = (int)(i % cols);
+  out[(int64_t)c * rows + r] = in[i];
+}
+
+__global__ void identity_f32(float* __restrict__ w, int n) {
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i < n * n) w[i] = (i / n == i % n) ? 1.f : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// principal components: FP64 Gram matrix and cyclic Jacobi
+// ---------------------------------------------------------------------------
+
+// part[z][i][j] = sum over rows of slice z of a[r][i] a[r][j]  (32 x 32 tiles)
+__global__ void __launch_bounds__(kT)
+gram_f64(const float* __restrict__ a, int64_t rows, int k, int64_t rows_per,
+         double* __restrict__ part) {
+  __shared__ double Ai[32][33];
+  __shared__ double Aj[32][33];
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int t = threadIdx.x;
+  const int ti = t & 31, tj4 = (t >> 5) * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.z * rows_per;
+  const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
+  for (int64_t rb = r0; rb < r1; rb += 32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = t + q * kT;            // 32 rows x 32 columns
+      const int rr = idx >> 5, cc = idx & 31;
+      const int64_t r = rb + rr;
+      Ai[rr][cc] = r < r1 ? (double)a[r * k + i0 + cc] : 0.0;
+      Aj[rr][cc] = r < r1 ? (double)a[r * k + j0 + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < 32; ++rr) {
+      const double ai = Ai[rr][ti];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(ai, Aj[rr][tj4 + q], acc[q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    part[(int64_t)blockIdx.z * k * k + (int64_t)(i0 + ti) * k + j0 + tj4 + q] = acc[q];
+}
+
+__global__ void sum_splits_f64(const double* __restrict__ part, int64_t n, int splits,
+                               double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * n + i];
+  out[i] = s;
+}
+
+// Cyclic Jacobi on the symmetric n x n matrix a (n even, in place, one
+// workgroup): each round rotates n/2 disjoint pairs (p, q) of the
+// round-robin tournament ordering at once, a <- J^T a J, v <- v J, with the
+// rotation that zeroes a_pq (t = sign(th) / (|th| + sqrt(th^2 + 1)),
+// th = (a_qq - a_pp) / (2 a_pq); Rutishauser's formulas, e.g. Golub & Van
+// Loan, Matrix Computations, section 8.5).  Sweeps of n - 1 rounds repeat
+// until the off-diagonal mass (sum of squares) is below 1e-28 of the total,
+// or below 1e-20 and no longer falling fourfold per sweep (the rounding
+// floor of a large matrix), or 40 sweeps.
+constexpr int kJacobiThreads = 1024;
+constexpr int kJacobiMaxN = 512;
+
+__global__ void __launch_bounds__(kJacobiThreads)
+jacobi_sym(int n, double* __restrict__ a, double* __restrict__ v, int* __restrict__ sweeps_out) {
+  __shared__ double cs[kJacobiMaxN / 2], sn[kJacobiMaxN / 2];
+  __shared__ int pp[kJacobiMaxN / 2], qq[kJacobiMaxN / 2];
+  __shared__ double red[kJacobiThreads / 64];
+  __shared__ int done;
+  const int t = threadIdx.x;
+  const int half = n / 2;
+  for (int64_t i = t; i < (int64_t)n * n; i += kJacobiThreads)
+    v[i] = (i / n == i % n) ? 1.0 : 0.0;
+  int sweep = 0;
+  double prev_off = 0.0;
+  for (; sweep < 40; ++sweep) {
+    // convergence test on the off-diagonal mass
+    double off = 0.0, tot = 0.0;
+    for (int64_t i = t; i < (int64_t)n * n; i += kJacobiThreads) {
+      const double x = a[i] * a[i];
+      tot += x;
+      if (i / n != i % n) off += x;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
+    if ((t & 63) == 0) red[t >> 6] = off;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int i = 0; i < kJacobiThreads / 64; ++i) s += red[i];
+      off = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if ((t & 63) == 0) red[t >> 6] = tot;
+    __syncthreads();
+    if (t == 0) {
+      double s = 0.0;
+      for (int i = 0; i < kJacobiThreads / 64; ++i) s += red[i];
+      done = !(off > 1e-28 * s) || (sweep > 0 && off >= 0.25 * prev_off && off <= 1e-20 * s);
+      prev_off = off;
+    }
+    __syncthreads();
+    if (done) break;
+    for (int r = 0; r < n - 1; ++r) {
+      // pairs of round r: player 0 fixed, players 1..n-1 rotate
+      for (int i = t; i < half; i += kJacobiThreads) {
+        const int x = i == 0 ? 0 : 1 + (i - 1 + r) % (n - 1);
+        const int y = 1 + (n - 2 - i + r) % (n - 1);
+        const int p = x < y ? x : y, q = x < y ? y : x;
+        const double apq = a[(int64_t)p * n + q];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0) {
+          const double th = (a[(int64_t)q * n + q] - a[(int64_t)p * n + p]) / (2.0 * apq);
+          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+          c = 1.0 / sqrt(tt * tt + 1.0);
+          s = tt * c;
+        }
+        pp[i] = p;
+        qq[i] = q;
+        cs[i] = c;
+        sn[i] = s;
+      }
+      __syncthreads();
+      // columns: a <- a J, v <- v J
+      for (int64_t w = t; w < (int64_t)n * half; w += kJacobiThreads) {
+        const int row = (int)(w / half), i = (int)(w % half);
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], s = sn[i];
+        double* ar = a + (int64_t)row * n;
+        const double ap = ar[p], aq = ar[q];
+        ar[p] = c * ap - s * aq;
+        ar[q] = s * ap + c * aq;
+        double* vr = v + (int64_t)row * n;
+        const double vp = vr[p], vq = vr[q];
+        vr[p] = c * vp - s * vq;
+        vr[q] = s * vp + c * vq;
+      }
+      __syncthreads();
+      // rows: a <- J^T a
+      for (int64_t w = t; w < (int64_t)n * half; w += kJacobiThreads) {
+        const int col = (int)(w % n), i = (int)(w / n);
+        const int p = pp[i], q = qq[i];
+        const double c = cs[i], s = sn[i];
+        const double ap = a[(int64_t)p * n + col], aq = a[(int64_t)q * n + col];
+        a[(int64_t)p * n + col] = c * ap - s * aq;
+        a[(int64_t)q * n + col] = s * ap + c * aq;
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// The r largest eigenvalues (diagonal of a) in decreasing order into lam and
+// their eigenvectors (columns of v) into w[k][rank] (FP32; sign chosen so
+// that the entry of largest magnitude, first on ties, is positive).
+__global__ void __launch_bounds__(kJacobiThreads)
+select_leading(int n, int r, const double* __restrict__ a, const double* __restrict__ v,
+               double* __restrict__ lam, float* __restrict__ w) {
+  for (int i = threadIdx.x; i < n; i += kJacobiThreads) {
+    const double li = a[(int64_t)i * n + i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = a[(int64_t)j * n + j];
+      rank += (lj > li) || (lj == li && j < i);
+    }
+    if (rank >= r) continue;
+    if (lam) lam[rank] = li;
+    int arg = 0;
+    double best = -1.0;
+    for (int k = 0; k < n; ++k) {
+      const double x = fabs(v[(int64_t)k * n + i]);
+      if (x > best) {
+        best = x;
+        arg = k;
+      }
+    }
+    const double sg = v[(int64_t)arg * n + i] < 0.0 ? -1.0 : 1.0;
+    for (int k = 0; k < n; ++k) w[(int64_t)k * r + rank] = (float)(sg * v[(int64_t)k * n + i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// compression: error check, raw packing, decompression, modal baseline
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float fallback_bound(float s, uint32_t gbits) {
+  const float g = __uint_as_float(gbits);
+  const float floor_ = 1e-3f * g;
+  return 1e-3f * (s > floor_ ? s : floor_);
+}
+
+// flag[e] = 1 if any channel's max |f - s xhat| exceeds the bound; element
+// e = e_begin + r, xhat[r] in Morton order.
+__global__ void __launch_bounds__(kT)
+ae_check(int64_t e_begin, const float* __restrict__ u, const float* __restrict__ v,
+         const float* __restrict__ w, const float* __restrict__ th,
+         const float* __restrict__ scale, const uint32_t* __restrict__ gmax_bits,
+         const float* __restrict__ xhat, int32_t* __restrict__ flag) {
+  __shared__ float red[kT / 64];
+  const int64_t e = e_begin + blockIdx.x;
+  const float* f[4] = {u, v, w, th};
+  int bad = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float s = scale[e * 4 + c];
+    float err = 0.f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = threadIdx.x + 256 * h;
+      const int m = morton8(n & 7, (n >> 3) & 7, n >> 6);
+      const float r = s * xhat[(int64_t)blockIdx.x * 2048 + m * 4 + c];
+      const float d = fabsf(f[c][e * 512 + n] - r);
+      err = d > err ? d : err;
+    }
+    err = block_max_pos(err, red);
+    bad |= err > fallback_bound(s, gmax_bits[c]);
+  }
+  if (threadIdx.x == 0) flag[e] = bad;
+}
+
+// raw[offs[e]] = the element's four channels (GLL layout) for flagged e
+__global__ void __launch_bounds__(kT)
+pack_raw(const float* __restrict__ u, const float* __restrict__ v, const float* __restrict__ w,
+         const float* __restrict__ th, const int32_t* __restrict__ flag,
+         const int64_t* __restrict__ offs, int64_t cap, float* __restrict__ raw,
+         uint8_t* __restrict__ flag_out, int32_t* __restrict__ status) {
+  const int64_t e = blockIdx.x;
+  const int fl = flag[e];
+  if (threadIdx.x == 0 && flag_out) flag_out[e] = (uint8_t)fl;
+  if (!fl) return;
+  const int64_t o = offs[e];
+  if (o >= cap) {
+    if (threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_RAW_OVERFLOW);
+    return;
+  }
+  const float* f[4] = {u, v, w, th};
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = threadIdx.x + 256 * h;
+      raw[(o * 4 + c) * 512 + n] = f[c][e * 512 + n];
+    }
+}
+
+__global__ void flags_u8_to_i32(const uint8_t* __restrict__ f8, int64_t n,
+                                int32_t* __restrict__ f32) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) f32[i] = f8[i] ? 1 : 0;
+}
+
+__global__ void flags_i32_to_u8_k(const int32_t* __restrict__ f32, int64_t n,
+                                  uint8_t* __restrict__ f8) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < n) f8[i] = f32[i] ? 1 : 0;
+}
+
+// fields of elements e_begin + r: raw copy if flagged, else s * xhat
+__global__ void __launch_bounds__(kT)
+ae_unpack(int64_t e_begin, const float* __restrict__ xhat, const float* __restrict__ scale,
+          const int32_t* __restrict__ flag, const int64_t* __restrict__ offs,
+          const float* __restrict__ raw, int64_t raw_count, float* __restrict__ u,
+          float* __restrict__ v, float* __restrict__ w, float* __restrict__ th,
+          int32_t* __restrict__ status) {
+  const int64_t e = e_begin + blockIdx.x;
+  float* f[4] = {u, v, w, th};
+  const bool flagged = flag && flag[e];
+  const int64_t o = flagged ? offs[e] : 0;
+  // a flagged element beyond the raw blocks given decodes from its latent
+  const bool is_raw = flagged && raw && o < raw_count;
+  if (flagged && !is_raw && threadIdx.x == 0 && status)
+    atomicOr(status, SEM_FLAG_RAW_OVERFLOW);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float s = scale[e * 4 + c];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = threadIdx.x + 256 * h;
+      const int m = morton8(n & 7, (n >> 3) & 7, n >> 6);
+      f[c][e * 512 + n] = is_raw ? raw[(o * 4 + c) * 512 + n]
+                                 : s * xhat[(int64_t)blockIdx.x * 2048 + m * 4 + c];
+    }
+  }
+}
+
+struct Gll7 {
+  float xi[8];
+  float l0[8];   // w_n / 2: row 0 of the inverse Legendre Vandermonde matrix
+  float l1[8];   // 3 w_n xi_n / 2: row 1
+};
+
+// Legendre modal truncation to degrees {0, 1}^3 per channel, coefficients
+// stored as binary16 of c / s; reconstruction, fallback flag.
+__global__ void __launch_bounds__(kT)
+modal_k(const float* __restrict__ u, const float* __restrict__ v, const float* __restrict__ w,
+        const float* __restrict__ th, Gll7 g, const uint32_t* __restrict__ gmax_bits,
+        const float* __restrict__ scale, uint16_t* __restrict__ coef,
+        int32_t* __restrict__ flag, float* __restrict__ ru, float* __restrict__ rv,
+        float* __restrict__ rw, float* __restrict__ rth) {
+  __shared__ float red[kT / 64];
+  __shared__ float part[kT / 64][8];
+  __shared__ float cq[8];
+  const int64_t e = blockIdx.x;
+  const float* f[4] = {u, v, w, th};
+  float* r[4] = {ru, rv, rw, rth};
+  int bad = 0;
+  for (int c = 0; c < 4; ++c) {
+    const float s = scale[e * 4 + c];
+    float acc[8] = {};
+    float val[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = threadIdx.x + 256 * h;
+      const int i = n & 7, j = (n >> 3) & 7, k = n >> 6;
+      val[h] = f[c][e * 512 + n];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const float li = (d & 1) ? g.l1[i] : g.l0[i];
+        const float lj = (d & 2) ? g.l1[j] : g.l0[j];
+        const float lk = (d & 4) ? g.l1[k] : g.l0[k];
+        acc[d] = fmaf(li * lj * lk, val[h], acc[d]);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      float x = acc[d];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+      if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6][d] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      const int d = threadIdx.x;
+      const float cd = part[0][d] + part[1][d] + part[2][d] + part[3][d];
+      const __half hq = __float2half_rn(s > 0.f ? cd / s : 0.f);
+      if (coef) coef[(e * 4 + c) * 8 + d] = __half_as_ushort(hq);
+      cq[d] = s * __half2float(hq);
+    }
+    __syncthreads();
+    float err = 0.f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = threadIdx.x + 256 * h;
+      const int i = n & 7, j = (n >> 3) & 7, k = n >> 6;
+      float rec = 0.f;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const float pi = (d & 1) ? g.xi[i] : 1.f;
+        const float pj = (d & 2) ? g.xi[j] : 1.f;
+        const float pk = (d & 4) ? g.xi[k] : 1.f;
+        rec = fmaf(cq[d], pi * pj * pk, rec);
+      }
+      if (r[c]) r[c][e * 512 + n] = rec;
+      const float dd = fabsf(val[h] - rec);
+      err = dd > err ? dd : err;
+    }
+    err = block_max_pos(err, red);
+    bad |= err > fallback_bound(s, gmax_bits[c]);
+  }
+  if (threadIdx.x == 0) flag[e] = bad;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct Layer {
+  bool conv;
+  int cin, cout;
+  int64_t w_off, b_off;
+};
+
+constexpr int kLayers = 6;
+const Layer* layers() {
+  static Layer L[kLayers];
+  static bool init = false;
+  if (!init) {
+    const int spec[kLayers][3] = {{1, 4, 32}, {1, 32, 64}, {1, 64, 32},
+                                  {0, 32, 64}, {0, 64, 32}, {0, 32, 4}};
+    int64_t off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+      L[l].conv = spec[l][0] != 0;
+      L[l].cin = spec[l][1];
+      L[l].cout = spec[l][2];
+      L[l].w_off = off;
+      off += (int64_t)8 * L[l].cin * L[l].cout;
+      L[l].b_off = off;
+      off += L[l].cout;
+    }
+    init = true;
+  }
+  return L;
+}
+
+// GEMM rows of layer l for n elements: output positions of a convolution,
+// input positions of a transposed one
+int64_t out_rows(int l, int64_t n) {
+  static const int pos[kLayers] = {64, 8, 1, 1, 8, 64};
+  return n * pos[l];
+}
+int out_width(int l) {
+  const Layer& L = layers()[l];
+  return L.conv ? L.cout : 8 * L.cout;
+}
+int in_width(int l) {
+  const Layer& L = layers()[l];
+  return L.conv ? 8 * L.cin : L.cin;
+}
+
+hipError_t gemm(const GemmArgs& g0, int splits, hipStream_t s) {
+  GemmArgs g = g0;
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), (unsigned)splits);
+  hipLaunchKernelGGL(gemm_f32, grid, dim3(kT), 0, s, g);
+  return hipGetLastError();
+}
+
+// Y = act(X W + b) for layer l on n elements
+hipError_t layer_forward(int l, int64_t n, const float* params, const float* x, float* y,
+                         int flags, hipStream_t s) {
+  const Layer& L = layers()[l];
+  GemmArgs g{};
+  g.M = out_rows(l, n);
+  g.K = in_width(l);
+  g.N = out_width(l);
+  g.A = x;
+  g.a_sm = g.K;
+  g.a_sk = 1;
+  g.B = params + L.w_off;
+  g.b_sk = g.N;
+  g.b_sn = 1;
+  g.C = y;
+  g.ldc = g.N;
+  g.k_split = g.K;
+  g.c_split = 0;
+  g.bias = params + L.b_off;
+  g.bias_mod = L.cout;
+  g.flags = flags;
+  return gemm(g, 1, s);
+}
+
+constexpr int64_t kSplitRows = 4096;
+
+struct AeWs {
+  float* act[kLayers + 1];   // act[0] = input blocks, act[l + 1] = layer l output
+  float* g0;                 // gradient ping-pong
+  float* g1;
+  float* part;               // weight-gradient split partials
+  double* lpart;
+  int64_t n;
+  size_t bytes;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int64_t max_splits(int64_t n) { return cdiv(n * 64, kSplitRows); }
+
+AeWs ae_layout(void* base, int64_t n) {
+  AeWs w{};
+  char* p = static_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* q = p ? p + off : nullptr;
+    off += align256(b);
+    return q;
+  };
+  w.act[0] = reinterpret_cast<float*>(take((size_t)n * 2048 * 4));
+  for (int l = 0; l < kLayers; ++l)
+    w.act[l + 1] = reinterpret_cast<float*>(take((size_t)out_rows(l, n) * out_width(l) * 4));
+  w.g0 = reinterpret_cast<float*>(take((size_t)n * 2048 * 4));
+  w.g1 = reinterpret_cast<float*>(take((size_t)n * 2048 * 4));
+  // largest weight-gradient partial: splits x (8 Cin x Cout) = splits x 16384
+  w.part = reinterpret_cast<float*>(take((size_t)max_splits(n) * 16384 * 4));
+  w.lpart = reinterpret_cast<double*>(take((size_t)cdiv(n * 2048, kT) * 8));
+  w.n = n;
+  w.bytes = off;
+  return w;
+}
+
+int act_flags(int l, int tanh_mask) {
+  int f = ((tanh_mask >> l) & 1) ? kEpiTanh : 0;
+  if (l == 2) f |= kEpiHalf;   // the latent is binary16
+  return f;
+}
+
+hipError_t forward_all(int64_t n, const float* params, int tanh_mask, const AeWs& w,
+                       hipStream_t s) {
+  for (int l = 0; l < kLayers; ++l) {
+    const hipError_t e = layer_forward(l, n, params, w.act[l], w.act[l + 1],
+                                       act_flags(l, tanh_mask), s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+int64_t ae_param_count() {
+  const Layer& L = layers()[kLayers - 1];
+  return L.b_off + L.cout;
+}
+
+size_t ae_workspace_bytes(int64_t n) { return ae_layout(nullptr, n).bytes; }
+
+hipError_t launch_ae_scales(int64_t n_elem, const float* const* f, float* scale,
+                            uint32_t* gmax_bits, hipStream_t s) {
+  if (gmax_bits) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(kT), 0, s, gmax_bits, 4, 0u);
+  if (n_elem > 0)
+    hipLaunchKernelGGL(ae_scales, dim3((unsigned)n_elem), dim3(kT), 0, s, (int64_t)0, f[0], f[1],
+                       f[2], f[3], scale, gmax_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_ae_pack(int64_t e_begin, int64_t n, const float* const* f, const float* scale,
+                          float* x, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(ae_pack, dim3((unsigned)n), dim3(kT), 0, s, e_begin, f[0], f[1], f[2],
+                       f[3], scale, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_ae_forward(int64_t n, const float* blocks, const float* params, int tanh_mask,
+                             float* recon, uint16_t* latent, void* ws, hipStream_t s) {
+  AeWs w = ae_layout(ws, n);
+  if (n <= 0) return hipSuccess;
+  hipMemcpyAsync(w.act[0], blocks, (size_t)n * 2048 * 4, hipMemcpyDeviceToDevice, s);
+  hipError_t e = forward_all(n, params, tanh_mask, w, s);
+  if (e != hipSuccess) return e;
+  if (latent)
+    hipLaunchKernelGGL(to_half_bits, dim3((unsigned)cdiv(n * 32, kT)), dim3(kT), 0, s, w.act[3],
+                       n * 32, latent);
+  if (recon)
+    hipMemcpyAsync(recon, w.act[kLayers], (size_t)n * 2048 * 4, hipMemcpyDeviceToDevice, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
+                          const float* params, int tanh_mask, float* grad, float* loss,
+                          void* ws, int32_t* status, hipStream_t s) {
+  AeWs w = ae_layout(ws, n);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_blocks, dim3((unsigned)n), dim3(kT), 0, s, pool, idx, n, n_pool,
+                     w.act[0], status);
+  hipError_t e = forward_all(n, params, tanh_mask, w, s);
+  if (e != hipSuccess) return e;
+  const int64_t cnt = n * 2048;
+  const int64_t nb = cdiv(cnt, kT);
+  hipLaunchKernelGGL(out_grad, dim3((unsigned)nb), dim3(kT), 0, s, w.act[kLayers], w.act[0], cnt,
+                     (float)(2.0 / (double)cnt), w.g0, w.lpart);
+  if (loss)
+    hipLaunchKernelGGL(loss_reduce, dim3(1), dim3(1024), 0, s, w.lpart, nb, 1.0 / (double)cnt,
+                       loss);
+  float* g = w.g0;      // dL/d(output of layer l), tanh factor not yet applied
+  float* gn = w.g1;
+  for (int l = kLayers - 1; l >= 0; --l) {
+    const Layer& L = layers()[l];
+    const int64_t rows = out_rows(l, n);
+    const int kin = in_width(l), nout = out_width(l);
+    // the tanh derivative of layer l itself is applied by the previous step's
+    // epilogue (or here for the output layer, which is linear)
+    // weight gradient: dW[kin][nout] = A^T G, split over rows
+    const int splits = (int)cdiv(rows, kSplitRows);
+    GemmArgs gw{};
+    gw.M = kin;
+    gw.N = nout;
+    gw.K = rows;
+    gw.A = w.act[l];
+    gw.a_sm = 1;
+    gw.a_sk = kin;
+    gw.B = g;
+    gw.b_sk = nout;
+    gw.b_sn = 1;
+    gw.C = w.part;
+    gw.ldc = nout;
+    gw.k_split = kSplitRows;
+    gw.c_split = (int64_t)kin * nout;
+    e = gemm(gw, splits, s);
+    if (e != hipSuccess) return e;
+    const int64_t wn = (int64_t)kin * nout;
+    hipLaunchKernelGGL(sum_splits, dim3((unsigned)cdiv(wn, kT)), dim3(kT), 0, s, w.part, wn,
+                       splits, grad + L.w_off);
+    // bias gradient
+    hipLaunchKernelGGL(colsum_splits, dim3((unsigned)cdiv(nout, kT), (unsigned)splits), dim3(kT),
+                       0, s, g, rows, nout, kSplitRows, w.part);
+    hipLaunchKernelGGL(fold_bias, dim3((unsigned)cdiv(L.cout, kT)), dim3(kT), 0, s, w.part,
+                       splits, nout, L.cout, grad + L.b_off);
+    if (l == 0) break;
+    // input gradient: dX[rows][kin] = G W^T, times tanh' of layer l - 1
+    GemmArgs gx{};
+    gx.M = rows;
+    gx.N = kin;
+    gx.K = nout;
+    gx.A = g;
+    gx.a_sm = nout;
+    gx.a_sk = 1;
+    gx.B = params + L.w_off;
+    gx.b_sk = 1;
+    gx.b_sn = nout;
+    gx.C = gn;
+    gx.ldc = kin;
+    gx.k_split = nout;
+    gx.c_split = 0;
+    gx.flags = ((tanh_mask >> (l - 1)) & 1) ? kEpiTanhGrad : 0;
+    gx.D = w.act[l];
+    e = gemm(gx, 1, s);
+    if (e != hipSuccess) return e;
+    float* tmp = g;
+    g = gn;
+    gn = tmp;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ae_adam(int64_t n, float* p, const float* g, float* m, float* v, int step,
+                          float lr, float b1, float b2, float eps, hipStream_t s) {
+  const double c1 = 1.0 / (1.0 - std::pow((double)b1, step));
+  const double c2 = 1.0 / (1.0 - std::pow((double)b2, step));
+  if (n > 0)
+    hipLaunchKernelGGL(adam_step, dim3((unsigned)cdiv(n, kT)), dim3(kT), 0, s, n, p, g, m, v, lr,
+                       b1, b2, eps, (float)c1, (float)c2);
+  return hipGetLastError();
+}
+
+size_t eig_workspace_bytes(int n) { return align256((size_t)n * n * 8) * 2 + 256; }
+
+hipError_t launch_sym_eig(int n, const double* a_in, int r, double* lam, float* w, void* ws,
+                          int* sweeps, hipStream_t s) {
+  char* p = static_cast<char*>(ws);
+  double* a = reinterpret_cast<double*>(p);
+  double* v = reinterpret_cast<double*>(p + align256((size_t)n * n * 8));
+  hipMemcpyAsync(a, a_in, (size_t)n * n * 8, hipMemcpyDeviceToDevice, s);
+  hipLaunchKernelGGL(jacobi_sym, dim3(1), dim3(kJacobiThreads), 0, s, n, a, v, sweeps);
+  hipLaunchKernelGGL(select_leading, dim3(1), dim3(kJacobiThreads), 0, s, n, r, a, v, lam, w);
+  return hipGetLastError();
+}
+
+// Gram matrices: at most 64 row slices (each at least kSplitRows rows)
+int64_t gram_splits(int64_t rows) {
+  const int64_t s = cdiv(rows, kSplitRows);
+  return s < 64 ? s : 64;
+}
+
+size_t pca_workspace_bytes(int64_t n_pool) {
+  const int64_t splits = gram_splits(n_pool * 8);
+  return align256((size_t)n_pool * 512 * 4) +                 // layer-1 outputs
+         align256((size_t)splits * 512 * 512 * 8) +          // Gram partials
+         align256((size_t)512 * 512 * 8) + eig_workspace_bytes(512);
+}
+
+hipError_t launch_ae_pca_init(int64_t n_pool, const float* pool, float* params, double* lams,
+                              void* ws, hipStream_t s) {
+  const Layer* L = layers();
+  char* p = static_cast<char*>(ws);
+  float* a2 = reinterpret_cast<float*>(p);
+  size_t off = align256((size_t)n_pool * 512 * 4);
+  double* part = reinterpret_cast<double*>(p + off);
+  off += align256((size_t)gram_splits(n_pool * 8) * 512 * 512 * 8);
+  double* gram = reinterpret_cast<double*>(p + off);
+  off += align256((size_t)512 * 512 * 8);
+  void* eig_ws = p + off;
+  hipLaunchKernelGGL(fill_f32, dim3((unsigned)cdiv(ae_param_count(), kT)), dim3(kT), 0, s, params,
+                     ae_param_count(), 0.f);
+  // layer 0: identity on each patch (its input and output rows coincide)
+  hipLaunchKernelGGL(identity_f32, dim3((unsigned)cdiv(32 * 32, kT)), dim3(kT), 0, s,
+                     params + L[0].w_off, 32);
+  // layers 1 and 2: leading eigenvectors of the second moments of their inputs
+  const float* in = pool;                    // layer-1 inputs: [n_pool * 8][256]
+  for (int l = 1; l <= 2; ++l) {
+    const int k = in_width(l), r = L[l].cout;
+    const int64_t rows = l == 1 ? n_pool * 8 : n_pool;
+    const int splits = (int)gram_splits(rows);
+    hipLaunchKernelGGL(gram_f64, dim3(k / 32, k / 32, splits), dim3(kT), 0, s, in, rows, k,
+                       cdiv(rows, splits), part);
+    hipLaunchKernelGGL(sum_splits_f64, dim3((unsigned)cdiv((int64_t)k * k, kT)), dim3(kT), 0, s,
+                       part, (int64_t)k * k, splits, gram);
+    hipError_t e = launch_sym_eig(k, gram, r, lams ? lams + (l == 1 ? 0 : 64) : nullptr,
+                                  params + L[l].w_off, eig_ws, nullptr, s);
+    if (e != hipSuccess) return e;
+    if (l == 1) {
+      e = layer_forward(1, n_pool, params, pool, a2, 0, s);   // [n_pool * 8][64]
+      if (e != hipSuccess) return e;
+      in = a2;                               // layer-2 inputs: [n_pool][512]
+    }
+  }
+  // decoder layers: transposes of the encoder layers
+  hipLaunchKernelGGL(transpose_f32, dim3((unsigned)cdiv(512 * 32, kT)), dim3(kT), 0, s,
+                     params + L[2].w_off, 512, 32, params + L[3].w_off);
+  hipLaunchKernelGGL(transpose_f32, dim3((unsigned)cdiv(256 * 64, kT)), dim3(kT), 0, s,
+                     params + L[1].w_off, 256, 64, params + L[4].w_off);
+  hipLaunchKernelGGL(identity_f32, dim3((unsigned)cdiv(32 * 32, kT)), dim3(kT), 0, s,
+                     params + L[5].w_off, 32);
+  return hipGetLastError();
+}
+
+// Compression in chunks of kChunk elements.
+constexpr int64_t kChunk = 16384;
+
+struct CompressWs {
+  AeWs ae;
+  int32_t* flag;
+  int64_t* offs;
+  int64_t* partial;
+  uint32_t* gmax;
+  size_t bytes;
+};
+
+CompressWs compress_layout(void* base, int64_t n_elem) {
+  CompressWs c{};
+  const int64_t chunk = n_elem < kChunk ? n_elem : kChunk;
+  c.ae = ae_layout(base, chunk > 0 ? chunk : 1);
+  char* p = static_cast<char*>(base);
+  size_t off = c.ae.bytes;
+  auto take = [&](size_t b) {
+    char* q = p ? p + off : nullptr;
+    off += align256(b);
+    return q;
+  };
+  c.flag = reinterpret_cast<int32_t*>(take((size_t)(n_elem + 1) * 4));
+  c.offs = reinterpret_cast<int64_t*>(take((size_t)(n_elem + 1) * 8));
+  c.partial = reinterpret_cast<int64_t*>(take((size_t)(scan_blocks(n_elem + 1) + 1) * 8));
+  c.gmax = reinterpret_cast<uint32_t*>(take(16));
+  c.bytes = off;
+  return c;
+}
+
+size_t compress_workspace_bytes(int64_t n_elem) { return compress_layout(nullptr, n_elem).bytes; }
+
+hipError_t launch_ae_compress(int64_t n_elem, const float* const* f, const float* params,
+                              int tanh_mask, uint16_t* latent, float* scale, uint8_t* flags,
+                              float* raw, int64_t raw_cap, int64_t* n_raw, void* ws,
+                              int32_t* status, hipStream_t s) {
+  CompressWs c = compress_layout(ws, n_elem);
+  hipError_t e = launch_ae_scales(n_elem, f, scale, c.gmax, s);
+  if (e != hipSuccess) return e;
+  for (int64_t b = 0; b < n_elem; b += kChunk) {
+    const int64_t n = n_elem - b < kChunk ? n_elem - b : kChunk;
+    e = launch_ae_pack(b, n, f, scale, c.ae.act[0], s);
+    if (e != hipSuccess) return e;
+    e = forward_all(n, params, tanh_mask, c.ae, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(to_half_bits, dim3((unsigned)cdiv(n * 32, kT)), dim3(kT), 0, s,
+                       c.ae.act[3], n * 32, latent + b * 32);
+    hipLaunchKernelGGL(ae_check, dim3((unsigned)n), dim3(kT), 0, s, b, f[0], f[1], f[2], f[3],
+                       scale, c.gmax, c.ae.act[kLayers], c.flag);
+  }
+  e = launch_exclusive_scan(c.flag, n_elem, c.partial, c.offs, s);
+  if (e != hipSuccess) return e;
+  if (n_raw) hipMemcpyAsync(n_raw, c.offs + n_elem, 8, hipMemcpyDeviceToDevice, s);
+  if (n_elem > 0)
+    hipLaunchKernelGGL(pack_raw, dim3((unsigned)n_elem), dim3(kT), 0, s, f[0], f[1], f[2], f[3],
+                       c.flag, c.offs, raw_cap, raw, flags, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_ae_decompress(int64_t n_elem, const uint16_t* latent, const float* scale,
+                                const uint8_t* flags, const float* raw, int64_t raw_count,
+                                const float* params, int tanh_mask, float* const* f, void* ws,
+                                int32_t* status, hipStream_t s) {
+  CompressWs c = compress_layout(ws, n_elem);
+  if (n_elem <= 0) return hipSuccess;
+  hipLaunchKernelGGL(flags_u8_to_i32, dim3((unsigned)cdiv(n_elem, kT)), dim3(kT), 0, s, flags,
+                     n_elem, c.flag);
+  hipError_t e = launch_exclusive_scan(c.flag, n_elem, c.partial, c.offs, s);
+  if (e != hipSuccess) return e;
+  for (int64_t b = 0; b < n_elem; b += kChunk) {
+    const int64_t n = n_elem - b < kChunk ? n_elem - b : kChunk;
+    hipLaunchKernelGGL(from_half_bits, dim3((unsigned)cdiv(n * 32, kT)), dim3(kT), 0, s,
+                       latent + b * 32, n * 32, c.ae.act[3]);
+    for (int l = 3; l < kLayers; ++l) {
+      e = layer_forward(l, n, params, c.ae.act[l], c.ae.act[l + 1], act_flags(l, tanh_mask), s);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(ae_unpack, dim3((unsigned)n), dim3(kT), 0, s, b, c.ae.act[kLayers], scale,
+                       c.flag, c.offs, raw, raw_count, f[0], f[1], f[2], f[3], status);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_modal(int64_t n_elem, const float* const* f, const double* xi,
+                        const double* wq, float* scale, uint16_t* coef, uint8_t* flags,
+                        float* const* recon, void* ws, hipStream_t s) {
+  CompressWs c = compress_layout(ws, n_elem);
+  hipError_t e = launch_ae_scales(n_elem, f, scale, c.gmax, s);
+  if (e != hipSuccess || n_elem <= 0) return e;
+  Gll7 g{};
+  for (int i = 0; i < 8; ++i) {
+    g.xi[i] = (float)xi[i];
+    g.l0[i] = (float)(0.5 * wq[i]);
+    g.l1[i] = (float)(1.5 * wq[i] * xi[i]);
+  }
+  float* r[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (recon)
+    for (int k = 0; k < 4; ++k) r[k] = recon[k];
+  hipLaunchKernelGGL(modal_k, dim3((unsigned)n_elem), dim3(kT), 0, s, f[0], f[1], f[2], f[3], g,
+                     c.gmax, scale, coef, c.flag, r[0], r[1], r[2], r[3]);
+  hipLaunchKernelGGL(flags_i32_to_u8_k, dim3((unsigned)cdiv(n_elem, kT)), dim3(kT), 0, s, c.flag,
+                     n_elem, flags);
+  return hipGetLastError();
+}
+
+}  // namespace sem

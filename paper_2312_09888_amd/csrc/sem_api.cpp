@@ -648,4 +648,156 @@ int64_t sem_timing_end(double* ms_total, int64_t* spans, int n_phases) {
   return rc;
 }
 
+// ---------------------------------------------------------------------------
+// learned in-transit compression
+// ---------------------------------------------------------------------------
+
+int64_t sem_ae_param_count(void) { return ae_param_count(); }
+
+size_t sem_ae_workspace_bytes(int64_t n) { return n < 1 ? 0 : ae_workspace_bytes(n); }
+
+static bool ae_mask_ok(int m) { return (m & ~SEM_AE_TANH_HIDDEN) == 0; }
+
+int sem_ae_blocks(int64_t n_elem, const float* u, const float* v, const float* w,
+                  const float* theta, float* blocks, float* scale, void* stream) {
+  if (n_elem < 0 || n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
+  if (n_elem == 0) return SEM_OK;
+  if (!u || !v || !w || !theta || !blocks || !scale) return SEM_ERR_ARG;
+  const float* f[4] = {u, v, w, theta};
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_ae_scales(n_elem, f, scale, nullptr, s);
+  if (e == hipSuccess) e = launch_ae_pack(0, n_elem, f, scale, blocks, s);
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+int sem_ae_forward(int64_t n, const float* blocks, const float* params, int tanh_mask,
+                   float* recon, uint16_t* latent, void* workspace, size_t workspace_bytes,
+                   void* stream) {
+  if (n < 0 || n > (int64_t)0x7fffffff || !ae_mask_ok(tanh_mask)) return SEM_ERR_ARG;
+  if (n == 0) return SEM_OK;
+  if (!blocks || !params || (!recon && !latent)) return SEM_ERR_ARG;
+  if (!workspace || workspace_bytes < ae_workspace_bytes(n)) return SEM_ERR_WORKSPACE;
+  return launch_ae_forward(n, blocks, params, tanh_mask, recon, latent, workspace,
+                           static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+int sem_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
+                const float* params, int tanh_mask, float* grad, float* loss,
+                void* workspace, size_t workspace_bytes, int32_t* status_word, void* stream) {
+  if (n < 1 || n > (int64_t)0x7fffffff || n_pool < 1 || !ae_mask_ok(tanh_mask))
+    return SEM_ERR_ARG;
+  if (!idx && n > n_pool) return SEM_ERR_ARG;
+  if (!pool || !params || !grad) return SEM_ERR_ARG;
+  if (!workspace || workspace_bytes < ae_workspace_bytes(n)) return SEM_ERR_WORKSPACE;
+  return launch_ae_grad(n, pool, n_pool, idx, params, tanh_mask, grad, loss, workspace,
+                        status_word, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+int sem_ae_adam(int64_t n, float* params, const float* grad, float* m, float* v, int step,
+                float lr, float beta1, float beta2, float eps, void* stream) {
+  if (n < 0 || step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f))
+    return SEM_ERR_ARG;
+  if (n == 0) return SEM_OK;
+  if (!params || !grad || !m || !v) return SEM_ERR_ARG;
+  return launch_ae_adam(n, params, grad, m, v, step, lr, beta1, beta2, eps,
+                        static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+size_t sem_eig_workspace_bytes(int n) {
+  return (n < 2 || n > 512 || (n & 1)) ? 0 : eig_workspace_bytes(n);
+}
+
+int sem_sym_eig(int n, const double* a, int r, double* lam, float* vec, void* workspace,
+                size_t workspace_bytes, int* sweeps, void* stream) {
+  if (n < 2 || n > 512 || (n & 1) || r < 1 || r > n || !a || !vec) return SEM_ERR_ARG;
+  if (!workspace || workspace_bytes < eig_workspace_bytes(n)) return SEM_ERR_WORKSPACE;
+  return launch_sym_eig(n, a, r, lam, vec, workspace, sweeps,
+                        static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+size_t sem_ae_pca_workspace_bytes(int64_t n_pool) {
+  return n_pool < 1 ? 0 : pca_workspace_bytes(n_pool);
+}
+
+int sem_ae_pca_init(int64_t n_pool, const float* pool, float* params, double* lam,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (n_pool < 1 || n_pool > ((int64_t)1 << 24) || !pool || !params) return SEM_ERR_ARG;
+  if (!workspace || workspace_bytes < pca_workspace_bytes(n_pool)) return SEM_ERR_WORKSPACE;
+  return launch_ae_pca_init(n_pool, pool, params, lam, workspace,
+                            static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+size_t sem_ae_compress_workspace_bytes(int64_t n_elem) {
+  return (n_elem < 0 || n_elem > (int64_t)0x7fffffff) ? 0 : compress_workspace_bytes(n_elem);
+}
+
+int sem_ae_compress(int64_t n_elem, const float* u, const float* v, const float* w,
+                    const float* theta, const float* params, int tanh_mask, uint16_t* latent,
+                    float* scale, uint8_t* flags, float* raw, int64_t raw_cap, int64_t* n_raw,
+                    void* workspace, size_t workspace_bytes, int32_t* status_word,
+                    void* stream) {
+  if (n_elem < 0 || n_elem > (int64_t)0x7fffffff || raw_cap < 0 || !ae_mask_ok(tanh_mask))
+    return SEM_ERR_ARG;
+  if (n_elem == 0) return SEM_OK;
+  if (!u || !v || !w || !theta || !params || !latent || !scale || !flags || !n_raw)
+    return SEM_ERR_ARG;
+  if (raw_cap > 0 && !raw) return SEM_ERR_ARG;
+  if (!workspace || workspace_bytes < compress_workspace_bytes(n_elem)) return SEM_ERR_WORKSPACE;
+  const float* f[4] = {u, v, w, theta};
+  return launch_ae_compress(n_elem, f, params, tanh_mask, latent, scale, flags, raw, raw_cap,
+                            n_raw, workspace, status_word,
+                            static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+int sem_ae_decompress(int64_t n_elem, const uint16_t* latent, const float* scale,
+                      const uint8_t* flags, const float* raw, int64_t raw_count,
+                      const float* params, int tanh_mask, float* u, float* v, float* w,
+                      float* theta, void* workspace, size_t workspace_bytes,
+                      int32_t* status_word, void* stream) {
+  if (n_elem < 0 || n_elem > (int64_t)0x7fffffff || raw_count < 0 || !ae_mask_ok(tanh_mask))
+    return SEM_ERR_ARG;
+  if (raw_count > 0 && !raw) return SEM_ERR_ARG;
+  if (n_elem == 0) return SEM_OK;
+  if (!latent || !scale || !flags || !params || !u || !v || !w || !theta) return SEM_ERR_ARG;
+  if (!workspace || workspace_bytes < compress_workspace_bytes(n_elem)) return SEM_ERR_WORKSPACE;
+  float* f[4] = {u, v, w, theta};
+  return launch_ae_decompress(n_elem, latent, scale, flags, raw, raw_count, params, tanh_mask,
+                              f, workspace, status_word,
+                              static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+int sem_modal_compress(int64_t n_elem, const float* u, const float* v, const float* w,
+                       const float* theta, uint16_t* coef, float* scale, uint8_t* flags,
+                       float* ru, float* rv, float* rw, float* rtheta, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+  if (n_elem < 0 || n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
+  if (n_elem == 0) return SEM_OK;
+  if (!u || !v || !w || !theta || !scale || !flags) return SEM_ERR_ARG;
+  const bool any_r = ru || rv || rw || rtheta;
+  if (any_r && !(ru && rv && rw && rtheta)) return SEM_ERR_ARG;
+  if (!workspace || workspace_bytes < compress_workspace_bytes(n_elem)) return SEM_ERR_WORKSPACE;
+  double xi[8], wq[8], dm[64];
+  if (!gll_basis(7, xi, wq, dm)) return SEM_ERR_ARG;
+  const float* f[4] = {u, v, w, theta};
+  float* r[4] = {ru, rv, rw, rtheta};
+  return launch_modal(n_elem, f, xi, wq, scale, coef, flags, any_r ? r : nullptr, workspace,
+                      static_cast<hipStream_t>(stream)) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
 }  // extern "C"

@@ -179,4 +179,37 @@ hipError_t launch_isosurface(int order, sem_dtype dt, const DeviceTables& tab,
                              uint8_t* case_idx, const IsoWorkspace& ws,
                              int32_t* status, hipStream_t s);
 
+// Learned compression (sem_ae.hip)
+int64_t ae_param_count();
+size_t ae_workspace_bytes(int64_t n);
+size_t eig_workspace_bytes(int n);
+size_t pca_workspace_bytes(int64_t n_pool);
+size_t compress_workspace_bytes(int64_t n_elem);
+hipError_t launch_ae_scales(int64_t n_elem, const float* const* f, float* scale,
+                            uint32_t* gmax_bits, hipStream_t s);
+hipError_t launch_ae_pack(int64_t e_begin, int64_t n, const float* const* f, const float* scale,
+                          float* x, hipStream_t s);
+hipError_t launch_ae_forward(int64_t n, const float* blocks, const float* params, int tanh_mask,
+                             float* recon, uint16_t* latent, void* ws, hipStream_t s);
+hipError_t launch_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
+                          const float* params, int tanh_mask, float* grad, float* loss,
+                          void* ws, int32_t* status, hipStream_t s);
+hipError_t launch_ae_adam(int64_t n, float* p, const float* g, float* m, float* v, int step,
+                          float lr, float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_sym_eig(int n, const double* a_in, int r, double* lam, float* w, void* ws,
+                          int* sweeps, hipStream_t s);
+hipError_t launch_ae_pca_init(int64_t n_pool, const float* pool, float* params, double* lams,
+                              void* ws, hipStream_t s);
+hipError_t launch_ae_compress(int64_t n_elem, const float* const* f, const float* params,
+                              int tanh_mask, uint16_t* latent, float* scale, uint8_t* flags,
+                              float* raw, int64_t raw_cap, int64_t* n_raw, void* ws,
+                              int32_t* status, hipStream_t s);
+hipError_t launch_ae_decompress(int64_t n_elem, const uint16_t* latent, const float* scale,
+                                const uint8_t* flags, const float* raw, int64_t raw_count,
+                                const float* params, int tanh_mask, float* const* f, void* ws,
+                                int32_t* status, hipStream_t s);
+hipError_t launch_modal(int64_t n_elem, const float* const* f, const double* xi,
+                        const double* wq, float* scale, uint16_t* coef, uint8_t* flags,
+                        float* const* recon, void* ws, hipStream_t s);
+
 }  // namespace sem

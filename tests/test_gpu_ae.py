@@ -1,0 +1,309 @@
+"""GPU parity of the learned compressor against the oracle (oracle/ae.py).
+
+Blocks and scales are exact (maxima and correctly rounded divisions).  The
+network runs in FP32 against the FP64 oracle: layer outputs within 1e-5
+normwise, the binary16 latent within one binary16 step (a value near a
+rounding boundary may round either way), gradients within 2e-4 normwise
+(the straight-through gradient depends on the rounded latent).  Integer
+decisions -- fallback flags -- are compared exactly with the oracle's rule
+applied in FP32 to the kernel's own reconstruction.  Raw blocks are copies
+and compared bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ae
+
+torch = pytest.importorskip("torch")
+import paper_2312_09888_amd as sem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _morton():
+    m = np.zeros((8, 8, 8), dtype=np.int64)              # [k][j][i]
+    for k in range(8):
+        for j in range(8):
+            for i in range(8):
+                v = 0
+                for l in range(3):
+                    v |= (((i >> l) & 1) << (3 * l)) | (((j >> l) & 1) << (3 * l + 1)) \
+                        | (((k >> l) & 1) << (3 * l + 2))
+                m[k, j, i] = v
+    return m
+
+
+MORTON = _morton()
+
+
+def to_natural(blocks):
+    """[E, 512, 4] Morton -> [E, 4, 8, 8, 8] (oracle layout)."""
+    b = np.asarray(blocks)
+    return b[:, MORTON, :].transpose(0, 4, 1, 2, 3)
+
+
+def to_morton(x):
+    x = np.asarray(x)
+    out = np.empty((x.shape[0], 512, 4), dtype=x.dtype)
+    out[:, MORTON.ravel(), :] = x.reshape(x.shape[0], 4, 512).transpose(0, 2, 1)
+    return out
+
+
+def normwise(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _fields(e, seed):
+    r = np.random.default_rng(seed)
+    f = [r.normal(size=(e, 8, 8, 8)).astype(np.float32) * s for s in (1.0, 3.0, 0.0, 0.01)]
+    f[3][0] = 0.0                                       # a vanishing channel on one element
+    return f
+
+
+def test_blocks_and_scales_exact():
+    f = _fields(9, 1)
+    blocks, scale = sem.ae_blocks([dev(a) for a in f])
+    ox, os_ = ae.blocks(f)
+    np.testing.assert_array_equal(scale.cpu().numpy(), os_)
+    np.testing.assert_array_equal(to_natural(blocks.cpu().numpy()), ox)
+
+
+def _layers_from(params, x, z, mask):
+    """Oracle encoder output (unrounded) and decoder output from latent z."""
+    layers = ae.unpack(params)
+    a = np.asarray(x, dtype=np.float64)
+    for l in range(3):
+        kind = ae.ARCH[l][0]
+        a = (ae.conv if kind == "conv" else ae.conv_t)(a, *layers[l])
+        if (mask >> l) & 1:
+            a = np.tanh(a)
+    enc = a
+    a = np.asarray(z, dtype=np.float64)
+    for l in range(3, 6):
+        a = ae.conv_t(a, *layers[l])
+        if (mask >> l) & 1:
+            a = np.tanh(a)
+    return enc, a
+
+
+@pytest.mark.parametrize("mask", [0, sem.SEM_AE_TANH_HIDDEN])
+def test_forward_matches_oracle(mask):
+    params = ae.init_params(3)
+    x = np.random.default_rng(4).uniform(-1, 1, size=(6, 4, 8, 8, 8)).astype(np.float32)
+    recon, latent = sem.ae_forward(dev(to_morton(x)), dev(params), tanh_mask=mask)
+    z = latent.float().cpu().numpy().astype(np.float64)          # [n, 32]
+    enc, dec = _layers_from(params, x, z.reshape(-1, 32, 1, 1, 1), mask)
+    enc = enc.reshape(-1, 32)
+    # binary16: within one step of the exact encoder output
+    step = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(enc), 2.0 ** -14))) - 10)
+    assert np.all(np.abs(z - enc) <= step * 1.0001)
+    assert normwise(to_natural(recon.cpu().numpy()), dec) <= 1e-5
+
+
+@pytest.mark.parametrize("mask", [0, sem.SEM_AE_TANH_HIDDEN])
+def test_gradient_matches_oracle(mask):
+    params = ae.init_params(5).astype(np.float64)
+    r = np.random.default_rng(6)
+    params += r.normal(scale=0.02, size=params.size)        # non-zero biases too
+    params = params.astype(np.float32)
+    pool = r.uniform(-1, 1, size=(7, 4, 8, 8, 8)).astype(np.float32)
+    idx = np.array([3, 0, 6, 3, 1], dtype=np.int64)
+    loss, grad = sem.ae_grad(dev(to_morton(pool)), dev(params), idx=dev(idx), tanh_mask=mask)
+    ol, og = ae.gradient(params, pool[idx], quantize=True, tanh_mask=mask)
+    assert abs(float(loss.item()) - ol) <= 1e-5 * ol
+    g = grad.cpu().numpy().astype(np.float64)
+    off = 0
+    for (w, b) in ae.layer_sizes():
+        for n in (w, b):
+            assert normwise(g[off:off + n], og[off:off + n]) <= 2e-4, off
+            off += n
+
+
+def test_gradient_flags_bad_indices():
+    pool = dev(np.zeros((3, 512, 4), dtype=np.float32))
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    sem.ae_grad(pool, dev(ae.init_params(1)), idx=dev(np.array([0, 3], dtype=np.int64)),
+                status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) & sem.SEM_FLAG_BAD_ID
+
+
+def test_adam_matches_oracle():
+    r = np.random.default_rng(7)
+    p, g, m, v = (r.normal(size=1000).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    tp, tg, tm, tv = dev(p), dev(g), dev(m), dev(v)
+    sem.ae_adam(tp, tg, tm, tv, 3, 1e-3)
+    op, om, ov = ae.adam(p, g, m, v, 3, 1e-3)
+    assert normwise(tm.cpu().numpy(), om) <= 1e-6
+    assert normwise(tv.cpu().numpy(), ov) <= 1e-6
+    assert normwise(tp.cpu().numpy() - p, op - p) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [8, 64, 256])
+def test_symmetric_eigensolver_matches_numpy(n):
+    r = np.random.default_rng(n)
+    q, _ = np.linalg.qr(r.normal(size=(n, n)))
+    lam = np.geomspace(1.0, 1e-9, n) * (1 + 0.1 * r.uniform(size=n))
+    a = (q * lam) @ q.T
+    a = (a + a.T) / 2
+    k = min(n, 32)
+    glam, gvec, sweeps = sem.sym_eig(dev(a), k)
+    wl, wv = np.linalg.eigh(a)
+    wl, wv = wl[::-1][:k], wv[:, ::-1][:, :k]
+    np.testing.assert_allclose(glam.cpu().numpy(), wl, rtol=0, atol=1e-12 * wl[0])
+    gv = gvec.cpu().numpy().astype(np.float64)
+    # the leading eigenvectors are well separated: each matches up to sign
+    dots = np.abs(np.sum(gv * wv, axis=0))
+    assert np.all(dots[:min(k, 16)] >= 1 - 1e-6)
+    # sign convention: largest-magnitude entry positive
+    top = gv[np.argmax(np.abs(gv), axis=0), np.arange(k)]
+    assert np.all(top > 0)
+    assert 1 <= int(sweeps.item()) < 40
+
+
+def _octant_low_rank(b, seed):
+    import test_oracle_ae as T
+    return T._low_rank_blocks(b, 24, seed, noise=1e-4).astype(np.float32)
+
+
+def test_pca_init_matches_oracle():
+    x_all = _octant_low_rank(272, 21)
+    x, test = x_all[:256], x_all[256:]
+    params, lam = sem.ae_pca_init(dev(to_morton(x)))
+    op, olams = ae.pca_init(x.astype(np.float64))
+    gl = lam.cpu().numpy()
+    np.testing.assert_allclose(gl[:64], olams[0], rtol=1e-9, atol=1e-12 * olams[0][0])
+    # layer-2 inputs are the FP32 outputs of layer 1 (FP32 weights): 1e-6
+    np.testing.assert_allclose(gl[64:], olams[1], rtol=1e-6, atol=1e-12 * olams[1][0])
+    # eigenvector signs may differ: compare the networks' maps on held-out
+    # blocks of the same distribution, not weights.  Beyond the data's rank
+    # the kept eigenvectors span noise (1e-4) and are nearly degenerate, so
+    # the maps agree to the noise level there.
+    gout = ae.forward(params.cpu().numpy(), test, quantize=False)[-1]
+    oout = ae.forward(op, test, quantize=False)[-1]
+    assert normwise(gout, oout) <= 1e-4
+
+
+def _ae_setup(n_pool=4096, seed=0):
+    ph, el = W.ae_training_elements(seed, n_pool)
+    pools = []
+    for p in np.unique(ph):
+        f = W.ae_fields(int(p), DEV, elements=el[ph == p], dtype=torch.float32)
+        pools.append(sem.ae_blocks(list(f))[0])
+    pool = torch.cat(pools)
+    params, _ = sem.ae_pca_init(pool)
+    return pool, params
+
+
+def test_compress_roundtrip_flags_and_raw():
+    _, params = _ae_setup(2048)
+    f = W.ae_fields(40.5, DEV, elements=np.arange(0, 262144, 877), dtype=torch.float32)
+    fields = list(f)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    pk = sem.ae_compress(fields, params, status=st)
+    out = sem.ae_decompress(pk, params)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    hf = [t.cpu().numpy() for t in fields]
+    ho = [t.cpu().numpy() for t in out]
+    flags = pk["flags"].cpu().numpy().astype(bool)
+    assert pk["n_raw"] == int(flags.sum())
+    # raw elements come back bit for bit, in element order in the raw buffer
+    raw = pk["raw"].cpu().numpy()
+    for c in range(4):
+        np.testing.assert_array_equal(ho[c][flags], hf[c][flags])
+        np.testing.assert_array_equal(raw[:, c].reshape(-1, 8, 8, 8), hf[c][flags])
+    # the flags are the rule applied (in FP32) to the network's reconstruction
+    pure = dict(pk, flags=torch.zeros_like(pk["flags"]), raw=pk["raw"][:0])
+    rec = [t.cpu().numpy() for t in sem.ae_decompress(pure, params)]
+    gmax = pk["scale"].cpu().numpy().max(axis=0)
+    np.testing.assert_array_equal(ae.fallback(hf, rec, gmax), flags)
+    assert not ae.fallback(hf, ho, gmax).any()
+    # the reconstruction is the oracle's network on the kernel's own latent
+    x, s = ae.blocks(hf)
+    z = pk["latent"].float().cpu().numpy().reshape(-1, 32, 1, 1, 1)
+    _, dec = _layers_from(params.cpu().numpy(), x, z, 0)
+    want = dec * s[:, :, None, None, None]
+    got = np.stack(rec, 1)
+    assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max()
+
+
+def test_compress_raw_overflow_keeps_count():
+    _, params = _ae_setup(1024)
+    f = list(W.ae_fields(7, DEV, elements=np.arange(0, 262144, 4001), dtype=torch.float32))
+    f[0] = f[0] + 0.3 * torch.randn_like(f[0])          # noise: many raw elements
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    full = sem.ae_compress(f, params)
+    k = full["n_raw"]
+    assert k >= 4
+    part = sem.ae_compress(f, params, raw_cap=k // 2, status=st)
+    torch.cuda.synchronize()
+    assert part["n_raw"] == k and int(st.item()) & sem.SEM_FLAG_RAW_OVERFLOW
+    assert torch.equal(part["raw"], full["raw"][:k // 2])
+
+
+def test_modal_baseline_matches_oracle():
+    f = W.ae_fields(12, DEV, elements=np.arange(0, 262144, 1999), dtype=torch.float32)
+    fields = list(f)
+    r = sem.modal_compress(fields)
+    hf = [t.cpu().numpy() for t in fields]
+    rec = [t.cpu().numpy() for t in r["recon"]]
+    orec, okeep = ae.modal_truncate(hf, quantize=True)
+    s = r["scale"].cpu().numpy()
+    gq = r["coef"].float().cpu().numpy().reshape(-1, 4, 2, 2, 2)
+    safe = np.where(s > 0, s, 1.0)[:, :, None, None, None]
+    oq = okeep / safe
+    step = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(oq), 2.0 ** -14))) - 10)
+    assert np.all(np.abs(gq - oq) <= step * 1.0001)
+    tol = 8 * 2.0 ** -11 * s[:, :, None, None, None] + 1e-6 * np.abs(orec).max()
+    assert np.all(np.abs(np.stack(rec, 1) - orec) <= tol)
+    gmax = s.max(axis=0)
+    np.testing.assert_array_equal(ae.fallback(hf, rec, gmax),
+                                  r["flags"].cpu().numpy().astype(bool))
+
+
+def test_training_on_gpu_lowers_the_loss():
+    pool, _ = _ae_setup(2048, seed=3)
+    params = dev(ae.init_params(9))
+    eval_idx = torch.arange(512, device=DEV)
+    l0 = float(sem.ae_grad(pool, params, idx=eval_idx)[0].item())
+    sem.ae_train(pool, params, steps=300, batch=256, lr=1e-3, seed=1)
+    l1 = float(sem.ae_grad(pool, params, idx=eval_idx)[0].item())
+    print(f"\nloss from random init: {l0:.3e} -> {l1:.3e} after 300 Adam steps")
+    assert l1 < 0.05 * l0
+
+
+def test_trained_network_beats_the_modal_baseline():
+    """The gain of the learned part: on a held-out time (a phase between
+    training phases) the network ships far fewer raw elements than the
+    Legendre truncation with the same bytes per element, so the snapshot
+    shrinks far more."""
+    pool, params = _ae_setup(8192, seed=4)
+    eval_idx = torch.arange(1024, device=DEV)
+    l0 = float(sem.ae_grad(pool, params, idx=eval_idx)[0].item())
+    sem.ae_train(pool, params, steps=200, batch=1024, lr=1e-6, seed=2)
+    l1 = float(sem.ae_grad(pool, params, idx=eval_idx)[0].item())
+    f = list(W.ae_fields(31.5, DEV, elements=np.arange(0, 262144, 97), dtype=torch.float32))
+    e = f[0].shape[0]
+    pk = sem.ae_compress(f, params)
+    mod = sem.modal_compress(f, recon=False)
+    frac_ae = pk["n_raw"] / e
+    frac_mod = float(mod["flags"].float().mean().item())
+    raw_bytes = e * 4 * 512 * 4
+    ratio_ae = raw_bytes / sem.compressed_bytes(e, pk["n_raw"])
+    ratio_mod = raw_bytes / sem.compressed_bytes(e, int(mod["flags"].sum().item()))
+    print(f"\nPCA-init loss {l0:.3e} -> fine-tuned {l1:.3e}; raw fallback: network "
+          f"{frac_ae:.3f}, modal {frac_mod:.3f}; ratio network {ratio_ae:.1f}x, "
+          f"modal {ratio_mod:.1f}x")
+    assert l1 <= 1.05 * l0
+    assert frac_ae <= 0.25 and frac_mod >= 0.9
+    assert ratio_ae >= 3 * ratio_mod

@@ -277,3 +277,43 @@ def test_batch_argument_errors_and_struct_layout():
     assert L.sem_batch_set_variant(7, 1, 4) == _lib.SEM_ERR_ARG
     assert L.sem_batch_set_variant(9, 0, 1) == _lib.SEM_ERR_ARG     # 2 x 1000 nodes > tile
     assert L.sem_batch_set_variant(5, 1, 7) == _lib.SEM_ERR_ARG
+
+
+def test_compression_entry_points_reject_bad_arguments():
+    L = _lib.lib()
+    FAKE = ctypes.c_void_p(16)
+    assert L.sem_ae_param_count() == 67812
+    assert L.sem_ae_workspace_bytes(0) == 0 and L.sem_ae_workspace_bytes(8) > 8 * 2048 * 4
+    assert L.sem_eig_workspace_bytes(3) == 0 and L.sem_eig_workspace_bytes(514) == 0
+    assert L.sem_eig_workspace_bytes(512) >= 2 * 512 * 512 * 8
+    assert L.sem_ae_pca_workspace_bytes(0) == 0
+    assert L.sem_ae_compress_workspace_bytes(-1) == 0
+    # tanh only after hidden layers
+    assert L.sem_ae_forward(4, FAKE, FAKE, 0x04, FAKE, None, FAKE, 1 << 30, None) == \
+        _lib.SEM_ERR_ARG
+    assert L.sem_ae_forward(4, FAKE, FAKE, 0x20, FAKE, None, FAKE, 1 << 30, None) == \
+        _lib.SEM_ERR_ARG
+    assert L.sem_ae_forward(4, FAKE, FAKE, 0, None, None, FAKE, 1 << 30, None) == \
+        _lib.SEM_ERR_ARG
+    assert L.sem_ae_forward(4, FAKE, FAKE, 0, FAKE, None, FAKE, 16, None) == \
+        _lib.SEM_ERR_WORKSPACE
+    assert L.sem_ae_forward(0, None, None, 0, None, None, None, 0, None) == _lib.SEM_OK
+    assert L.sem_ae_grad(0, FAKE, 1, None, FAKE, 0, FAKE, None, FAKE, 1 << 30, None,
+                         None) == _lib.SEM_ERR_ARG
+    assert L.sem_ae_grad(5, FAKE, 4, None, FAKE, 0, FAKE, None, FAKE, 1 << 30, None,
+                         None) == _lib.SEM_ERR_ARG          # first n > pool without indices
+    assert L.sem_ae_adam(10, FAKE, FAKE, FAKE, FAKE, 0, 1e-3, 0.9, 0.999, 1e-8, None) == \
+        _lib.SEM_ERR_ARG                                     # steps count from 1
+    assert L.sem_ae_adam(10, FAKE, FAKE, FAKE, FAKE, 1, 1e-3, 1.0, 0.999, 1e-8, None) == \
+        _lib.SEM_ERR_ARG
+    assert L.sem_sym_eig(5, FAKE, 2, None, FAKE, FAKE, 1 << 30, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_sym_eig(8, FAKE, 9, None, FAKE, FAKE, 1 << 30, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_sym_eig(8, FAKE, 2, None, FAKE, FAKE, 8, None, None) == _lib.SEM_ERR_WORKSPACE
+    assert L.sem_ae_compress(4, FAKE, FAKE, FAKE, FAKE, FAKE, 0, FAKE, FAKE, FAKE, FAKE, -1,
+                             FAKE, FAKE, 1 << 30, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_ae_compress(4, FAKE, FAKE, FAKE, FAKE, FAKE, 0, FAKE, FAKE, FAKE, None, 4,
+                             FAKE, FAKE, 1 << 30, None, None) == _lib.SEM_ERR_ARG
+    assert L.sem_ae_compress(4, FAKE, FAKE, FAKE, FAKE, FAKE, 0, FAKE, FAKE, FAKE, FAKE, 4,
+                             FAKE, FAKE, 8, None, None) == _lib.SEM_ERR_WORKSPACE
+    assert L.sem_modal_compress(4, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None, None,
+                                None, FAKE, 1 << 30, None) == _lib.SEM_ERR_ARG   # some recon
