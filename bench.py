@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--batched", choices=("on", "off"), default="on",
                     help="also time 16 uneven snapshots (orders 5/7/9) in one persistent "
                          "launch, and the whole batched step replayed as a HIP graph")
+    ap.add_argument("--compression", choices=("on", "off"), default="on",
+                    help="also train the per-element autoencoder and time compression of "
+                         "a 262,144-element FP32 snapshot against the modal baseline")
     ap.add_argument("--cpu-elements", type=int, default=16384,
                     help="elements of the snapshot the CPU oracle is timed on")
     ap.add_argument("--quiet", action="store_true")
@@ -300,9 +303,123 @@ def main():
         result["c0"] = c0_timing(args, sem, fields, q, isos, n)
     if args.precision_modes == "on" and args.dtype == "f64":
         result["precision_modes"] = precision_modes(args, sem, fields, isos, n_elem, points)
+    if args.compression == "on" and args.dtype == "f64":
+        result["compression"] = compression_timing(args, sem)
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(args, fields, isos, n, n_elem)
     print(json.dumps(result), flush=True)
+
+
+def compression_timing(args, sem):
+    """Learned in-transit compression of a 262,144-element order-7 FP32
+    snapshot (u, v, w of the Taylor-Green vortex and a Gaussian random
+    scalar theta, advected; 134 M points).  Training on the GPU: a pool of
+    16,384 elements drawn from the 64 training phases, layer-wise PCA
+    initialisation, then Adam.  The snapshot is a held-out time (phase
+    63.5): compressed and decompressed, against the Legendre modal baseline
+    with the same bytes per element; agreement of the Q isosurface (90th
+    percentile) of the decompressed velocity with the original's."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    dev = "cuda:0"
+    t0 = time.time()
+    ph, el = W.ae_training_elements(0, 16384)
+    pools = []
+    for p in np.unique(ph):
+        f = W.ae_fields(int(p), dev, elements=el[ph == p], dtype=torch.float32)
+        pools.append(sem.ae_blocks(list(f))[0])
+    pool = torch.cat(pools)
+    del pools
+    torch.cuda.synchronize()
+    t_pool = time.time() - t0
+
+    def clock(fn):
+        torch.cuda.synchronize()
+        a = time.time()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.time() - a
+
+    (params, _), t_pca = clock(lambda: sem.ae_pca_init(pool))
+    eval_idx = torch.arange(4096, device=dev)
+    loss_pca = float(sem.ae_grad(pool, params, idx=eval_idx)[0].item())
+    _, t_train = clock(lambda: sem.ae_train(pool, params, steps=200, batch=2048, lr=1e-7,
+                                            seed=0))
+    loss_ft = float(sem.ae_grad(pool, params, idx=eval_idx)[0].item())
+    del pool
+    fields = list(W.ae_fields(63.5, dev, dtype=torch.float32))
+    e = fields[0].shape[0]
+    points = e * 512
+    raw_bytes = e * 4 * 512 * 4
+    reps = max(3, args.steps // 8)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        out = fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return out, e0.elapsed_time(e1) / reps
+
+    pk, comp_ms = timed(lambda: sem.ae_compress(fields, params))
+    dec, decomp_ms = timed(lambda: sem.ae_decompress(pk, params))
+    mod, modal_ms = timed(lambda: sem.modal_compress(fields, recon=True))
+    n_raw = pk["n_raw"]
+    n_raw_mod = int(mod["flags"].sum().item())
+    ratio = raw_bytes / sem.compressed_bytes(e, n_raw)
+    ratio_mod = raw_bytes / sem.compressed_bytes(e, n_raw_mod)
+    # relative L-inf error per channel of the decompressed fields
+    err = []
+    for a, b in zip(fields, dec):
+        gm = float(a.abs().max().item())
+        err.append(float((a - b).abs().max().item()) / gm if gm > 0 else 0.0)
+    # Q isosurface of the decompressed velocity against the original's
+    x, y, z = W.ae_mesh(dev, dtype=torch.float32)
+    q0, _, mm0 = sem.qcrit(x, y, z, *fields[:3])
+    flat = q0.reshape(-1)
+    gen = torch.Generator(device=dev).manual_seed(0)
+    idx = torch.randint(0, flat.numel(), (1 << 20,), device=dev, generator=gen)
+    iso = float(torch.quantile(flat[idx].double(), 0.9).item())
+    r0 = sem.isosurface(x, y, z, q0, [iso], minmax=mm0, cases=True)
+    agree = {}
+    for name, vel in (("network", dec[:3]), ("modal", mod["recon"][:3])):
+        q1, _, mm1 = sem.qcrit(x, y, z, *vel)
+        r1 = sem.isosurface(x, y, z, q1, [iso], minmax=mm1, cases=True)
+        t0_, t1_ = int(r0["tri_count"][0].item()), int(r1["tri_count"][0].item())
+        mism = float((r0["cases"] != r1["cases"]).float().mean().item())
+        agree[name] = {"triangles": t1_, "triangle_rel_diff": abs(t1_ - t0_) / max(t0_, 1),
+                       "case_mismatch_frac": mism,
+                       "q_rel_linf": float((q1 - q0).abs().max().item())
+                       / float(q0.abs().max().item())}
+        del q1, r1
+    tri0 = int(r0["tri_count"][0].item())
+    log(args, f"compression: pool {t_pool:.1f} s, PCA init {t_pca * 1e3:.0f} ms, 200 Adam steps "
+              f"{t_train * 1e3:.0f} ms (loss {loss_pca:.3e} -> {loss_ft:.3e}); compress "
+              f"{comp_ms:.2f} ms ({points / (comp_ms * 1e-3) / 1e9:.1f} G points/s), "
+              f"decompress {decomp_ms:.2f} ms; raw fallback {n_raw / e:.4f} (modal "
+              f"{n_raw_mod / e:.4f}); ratio {ratio:.1f}x (modal {ratio_mod:.2f}x); Q "
+              f"triangles {tri0} vs network {agree['network']['triangles']}, modal "
+              f"{agree['modal']['triangles']}")
+    out = {"elements": e, "points": points, "raw_bytes": raw_bytes,
+           "pool_elements": 16384, "pca_init_ms": round(t_pca * 1e3, 2),
+           "train_steps": 200, "train_batch": 2048, "train_ms": round(t_train * 1e3, 2),
+           "loss_pca": loss_pca, "loss_finetuned": loss_ft,
+           "compress_ms": round(comp_ms, 4), "decompress_ms": round(decomp_ms, 4),
+           "compress_points_per_s": points / (comp_ms * 1e-3),
+           "modal_ms": round(modal_ms, 4),
+           "fallback_frac": n_raw / e, "ratio": ratio,
+           "modal_fallback_frac": n_raw_mod / e, "modal_ratio": ratio_mod,
+           "rel_linf_per_channel": err, "q_isovalue": iso, "q_triangles": tri0,
+           "isosurface_agreement": agree}
+    del fields, dec, mod, pk, x, y, z, q0, r0
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_timing(args, sem):

@@ -28,7 +28,7 @@ __all__ = [
     "gll_points", "axis_lattice", "box_mesh", "element_axes", "tgv_velocity",
     "channel_modes", "channel_velocity", "warp", "tgv_config", "channel_config",
     "lattice_gid", "batch_spec", "batch_snapshot", "CHANNEL_SHAPE", "TGV_SHAPE",
-    "ae_fields", "ae_training_elements", "AE_SHAPE", "AE_PHASES",
+    "ae_fields", "ae_mesh", "ae_training_elements", "AE_SHAPE", "AE_PHASES",
 ]
 
 TGV_SHAPE = (8, 8, 8)          # Taylor-Green box [0, 2 pi]^3, 512 elements
@@ -313,6 +313,25 @@ def ae_fields(phase, device, shape=AE_SHAPE, elements=None, dtype=None, features
     if dtype is not None:
         out = tuple(f.to(dtype).contiguous() for f in out)
     return out
+
+
+def ae_mesh(device, shape=AE_SHAPE, elements=None, dtype=None):
+    """(x, y, z) of the compression snapshots' uniform [0, 2 pi]^3 mesh on
+    `device` (torch), order 7 (the fields of ae_fields sit at these nodes)."""
+    import torch
+    n, p = 7, 8
+    lat = [torch.from_numpy(axis_lattice(shape[a], n, 0.0, 2 * np.pi)).to(device)
+           for a in range(3)]
+    ex, ey, ez = (torch.from_numpy(np.asarray(c)).to(device)
+                  for c in element_axes(shape, elements))
+    loc = torch.arange(p, device=device)
+    e_cnt = ex.shape[0]
+    xs = lat[0][ex[:, None] * n + loc[None, :]]
+    ys = lat[1][ey[:, None] * n + loc[None, :]]
+    zs = lat[2][ez[:, None] * n + loc[None, :]]
+    out = (xs[:, None, None, :].expand(e_cnt, p, p, p), ys[:, None, :, None].expand(e_cnt, p, p, p),
+           zs[:, :, None, None].expand(e_cnt, p, p, p))
+    return tuple((c.to(dtype) if dtype is not None else c).contiguous() for c in out)
 
 
 def ae_training_elements(seed, count, shape=AE_SHAPE, phases=AE_PHASES):
