@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--compression", choices=("on", "off"), default="on",
                     help="also train the per-element autoencoder and time compression of "
                          "a 262,144-element FP32 snapshot against the modal baseline")
-    ap.add_argument("--cpu-elements", type=int, default=16384,
+    ap.add_argument("--cpu-elements", type=int, default=65536,
                     help="elements of the snapshot the CPU oracle is timed on")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -82,12 +82,10 @@ __global__ void fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 // blocks: per-channel element maxima, normalised Morton blocks
 // ---------------------------------------------------------------------------
 
-// s[e][c] = max |f_c| over element e; gmax_bits[c] = bits of max_e s[e][c]
-// (non-negative floats order like their bit patterns).
+// s[e][c] = max |f_c| over element e
 __global__ void __launch_bounds__(kT)
 ae_scales(int64_t e_begin, const float* __restrict__ u, const float* __restrict__ v,
-          const float* __restrict__ w, const float* __restrict__ th, float* __restrict__ scale,
-          uint32_t* __restrict__ gmax_bits) {
+          const float* __restrict__ w, const float* __restrict__ th, float* __restrict__ scale) {
   __shared__ float red[kT / 64];
   const int64_t e = e_begin + blockIdx.x;
   const float* f[4] = {u, v, w, th};
@@ -96,10 +94,24 @@ ae_scales(int64_t e_begin, const float* __restrict__ u, const float* __restrict_
     const float* src = f[c] + e * 512;
     const float a = fabsf(src[threadIdx.x]), b = fabsf(src[threadIdx.x + 256]);
     const float m = block_max_pos(a > b ? a : b, red);
-    if (threadIdx.x == 0) {
-      scale[e * 4 + c] = m;
-      if (gmax_bits) atomicMax(gmax_bits + c, __float_as_uint(m));
+    if (threadIdx.x == 0) scale[e * 4 + c] = m;
+  }
+}
+
+// gmax_bits[c] = bits of max_e s[e][c] (non-negative floats order like their
+// bit patterns): one atomic per block and channel
+__global__ void __launch_bounds__(kT)
+gmax_k(const float* __restrict__ scale, int64_t n, uint32_t* __restrict__ gmax_bits) {
+  __shared__ float red[kT / 64];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float m = 0.f;
+    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT) {
+      const float x = scale[e * 4 + c];
+      m = x > m ? x : m;
     }
+    m = block_max_pos(m, red);
+    if (threadIdx.x == 0) atomicMax(gmax_bits + c, __float_as_uint(m));
   }
 }
 
@@ -234,16 +246,30 @@ __global__ void sum_splits(const float* __restrict__ part, int64_t n, int splits
   out[i] = s;
 }
 
-// part[z][col] = sum of G[rows of slice z][col]
-__global__ void colsum_splits(const float* __restrict__ G, int64_t rows, int cols,
-                              int64_t rows_per, float* __restrict__ part) {
-  const int col = blockIdx.x * kT + threadIdx.x;
-  if (col >= cols) return;
+// part[z][col] = sum of G[rows of slice z][col]: the block's threads split
+// into column lanes and row groups (coalesced rows), then the row groups'
+// sums are added in a fixed order.
+__global__ void __launch_bounds__(kT)
+colsum_splits(const float* __restrict__ G, int64_t rows, int cols, int64_t rows_per,
+              float* __restrict__ part) {
+  __shared__ float red[kT];
   const int64_t r0 = (int64_t)blockIdx.y * rows_per;
   const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
-  float s = 0.f;
-  for (int64_t r = r0; r < r1; ++r) s += G[r * cols + col];
-  part[(int64_t)blockIdx.y * cols + col] = s;
+  const int lanes = cols < kT ? cols : kT;       // cols is 32, 64, 256 or 512
+  const int groups = kT / lanes;
+  const int lane = threadIdx.x % lanes, grp = threadIdx.x / lanes;
+  for (int c0 = 0; c0 < cols; c0 += lanes) {
+    float s = 0.f;
+    for (int64_t r = r0 + grp; r < r1; r += groups) s += G[r * cols + c0 + lane];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (grp == 0) {
+      float t = 0.f;
+      for (int q = 0; q < groups; ++q) t += red[q * lanes + lane];
+      part[(int64_t)blockIdx.y * cols + c0 + lane] = t;
+    }
+    __syncthreads();
+  }
 }
 
 // db[o] = sum_z sum_d part[z][d * cout + o] (fold = 8 for convT, 1 for conv)
@@ -791,7 +817,7 @@ hipError_t layer_forward(int l, int64_t n, const float* params, const float* x, 
   return gemm(g, 1, s);
 }
 
-constexpr int64_t kSplitRows = 4096;
+constexpr int64_t kSplitRows = 512;   // rows per weight-gradient slice
 
 struct AeWs {
   float* act[kLayers + 1];   // act[0] = input blocks, act[l + 1] = layer l output
@@ -857,9 +883,15 @@ size_t ae_workspace_bytes(int64_t n) { return ae_layout(nullptr, n).bytes; }
 hipError_t launch_ae_scales(int64_t n_elem, const float* const* f, float* scale,
                             uint32_t* gmax_bits, hipStream_t s) {
   if (gmax_bits) hipLaunchKernelGGL(fill_u32, dim3(1), dim3(kT), 0, s, gmax_bits, 4, 0u);
-  if (n_elem > 0)
+  if (n_elem > 0) {
     hipLaunchKernelGGL(ae_scales, dim3((unsigned)n_elem), dim3(kT), 0, s, (int64_t)0, f[0], f[1],
-                       f[2], f[3], scale, gmax_bits);
+                       f[2], f[3], scale);
+    if (gmax_bits) {
+      const int64_t nb = cdiv(n_elem, kT);
+      hipLaunchKernelGGL(gmax_k, dim3((unsigned)(nb < 1024 ? nb : 1024)), dim3(kT), 0, s, scale,
+                         n_elem, gmax_bits);
+    }
+  }
   return hipGetLastError();
 }
 
@@ -932,8 +964,8 @@ hipError_t launch_ae_grad(int64_t n, const float* pool, int64_t n_pool, const in
     hipLaunchKernelGGL(sum_splits, dim3((unsigned)cdiv(wn, kT)), dim3(kT), 0, s, w.part, wn,
                        splits, grad + L.w_off);
     // bias gradient
-    hipLaunchKernelGGL(colsum_splits, dim3((unsigned)cdiv(nout, kT), (unsigned)splits), dim3(kT),
-                       0, s, g, rows, nout, kSplitRows, w.part);
+    hipLaunchKernelGGL(colsum_splits, dim3(1, (unsigned)splits), dim3(kT), 0, s, g, rows, nout,
+                       kSplitRows, w.part);
     hipLaunchKernelGGL(fold_bias, dim3((unsigned)cdiv(L.cout, kT)), dim3(kT), 0, s, w.part,
                        splits, nout, L.cout, grad + L.b_off);
     if (l == 0) break;

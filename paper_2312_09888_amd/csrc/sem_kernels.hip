@@ -548,18 +548,36 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
   return ok;
 }
 
-template <int N, typename T>
+// Where a Q kernel also counts each isovalue's triangles and active cells per
+// element (the count pass of the isosurface, fused).
+template <typename T>
+struct CountSink {
+  int n_iso;
+  IsoList<T> iso;
+  const uint8_t* ntri;     // [256] triangles per case
+  int32_t* cnt;            // [n_iso][n_elem]
+  int64_t* active;         // [n_iso] active-cell totals (may be NULL)
+  int64_t n_elem;
+};
+
+template <int N, typename T, bool COUNT = false>
 __device__ __forceinline__ void qcrit_pencil_elem(
     int64_t e, int t, const double* __restrict__ dmat, const T* __restrict__ x,
     const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
     const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
-    T* __restrict__ qmm, int32_t* __restrict__ status) {
+    T* __restrict__ qmm, int32_t* __restrict__ status, const CountSink<T>* sink = nullptr) {
   using Q = Pen<N>;
   constexpr int P = Q::P, H0 = Q::H0;
   __shared__ PencilTiles<N, T> sm;
+  __shared__ uint32_t s_ntri[COUNT ? 64 : 1];
+  __shared__ int32_t s_sum[Q::TH / 64];
   const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
   const int p = t % Q::LT;
   const int64_t base = e * (P * P * P);
+  if constexpr (COUNT) {
+    // case table, published by the barriers of the passes
+    if (t < 64) s_ntri[t] = reinterpret_cast<const uint32_t*>(sink->ntri)[t];
+  }
   T qv[H0], ov[H0];
   int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
                              sm, sm.F, sm.F, sm.F, h, p, qv, ov);
@@ -575,19 +593,62 @@ __device__ __forceinline__ void qcrit_pencil_elem(
         const int64_t o = base + (k * P + j) * P + i;
         if (q) q[o] = qv[ii];
         if (om) om[o] = ov[ii];
+        if constexpr (COUNT) sm.F[Q::at(i, j, k)] = qv[ii];   // F is free after the last pass
         const T c = qv[ii] != qv[ii] ? neg_inf<T>() : qv[ii];
         mn = c < mn ? c : mn;
         mx = c > mx ? c : mx;
       }
     }
   }
-  bad = __syncthreads_or(bad);
+  bad = __syncthreads_or(bad);   // also publishes the Q tile
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
-  if (qmm) {
+  if (qmm || COUNT) {
     block_minmax<T, Q::TH>(mn, mx, sm.red);
-    if (t == 0) {
+    if (qmm && t == 0) {
       qmm[2 * e] = mn;
       qmm[2 * e + 1] = mx;
+    }
+  }
+  if constexpr (COUNT) {
+    // cells t, t + TH, ...: corner values loaded once for every isovalue
+    constexpr int NC = N * N * N, R = (NC + Q::TH - 1) / Q::TH;
+    T cv[R][8];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int cc = t + r * Q::TH < NC ? t + r * Q::TH : 0;
+      const int n0 = Q::at(cc % N, (cc / N) % N, cc / (N * N));
+#pragma unroll
+      for (int vtx = 0; vtx < 8; ++vtx)
+        cv[r][vtx] = sm.F[n0 + (vtx & 1) + Q::RS * ((vtx >> 1) & 1) + Q::SS * (vtx >> 2)];
+    }
+    const uint8_t* ntri = reinterpret_cast<const uint8_t*>(s_ntri);
+    for (int s = 0; s < sink->n_iso; ++s) {
+      const T c = sink->iso.v[s];
+      int packed = 0;   // triangles in the low 16 bits, active cells above
+      if ((mx > c) && !(mn > c)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (t + r * Q::TH >= NC) continue;
+          int cs = 0;
+#pragma unroll
+          for (int vtx = 7; vtx >= 0; --vtx) cs = cs + cs + (cv[r][vtx] > c);
+          packed += ntri[cs] + ((cs != 0 && cs != 255) << 16);
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
+      if ((t & 63) == 0) s_sum[t >> 6] = packed;
+      __syncthreads();
+      if (t == 0) {
+        int sum = 0;
+#pragma unroll
+        for (int q2 = 0; q2 < Q::TH / 64; ++q2) sum += s_sum[q2];
+        sink->cnt[(int64_t)s * sink->n_elem + e] = sum & 0xffff;
+        const int a = sum >> 16;
+        if (sink->active && a)
+          atomicAdd((unsigned long long*)&sink->active[s], (unsigned long long)a);
+      }
+      __syncthreads();
     }
   }
 }
@@ -600,6 +661,18 @@ qcrit_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* 
              T* __restrict__ qmm, int32_t* __restrict__ status) {
   qcrit_pencil_elem<N, T>(blockIdx.x, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm,
                           status);
+}
+
+// Q, |omega|, range and the per-(isovalue, element) counts in one pass.
+template <int N, typename T>
+__global__ void __launch_bounds__(Pen<N>::TH)
+qcount_pencil(const double* __restrict__ dmat, const T* __restrict__ x,
+              const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
+              const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q,
+              T* __restrict__ om, T* __restrict__ qmm, int32_t* __restrict__ status,
+              CountSink<T> sink) {
+  qcrit_pencil_elem<N, T, true>(blockIdx.x, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm,
+                                status, &sink);
 }
 
 // ---------------------------------------------------------------------------
@@ -1550,18 +1623,27 @@ __device__ __forceinline__ void mix_read(const float* __restrict__ dt, int i, in
 
 // QC: Q, |omega| and the element range of Q from (x, y, z, u, v, w);
 // otherwise the physical gradient of f = u into (o0, o1, o2).
-template <int M, bool QC>
+// COUNT (with QC): also the per-(isovalue, element) triangle and active-cell
+// counts from the element's Q tile.
+template <int M, bool QC, bool COUNT = false>
 __global__ void __launch_bounds__(256)
 mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
        const float* __restrict__ y, const float* __restrict__ z, const float* __restrict__ u,
        const float* __restrict__ v, const float* __restrict__ w, float* __restrict__ o0,
        float* __restrict__ o1, float* __restrict__ o2, float* __restrict__ qmm,
-       int32_t* __restrict__ status) {
+       int32_t* __restrict__ status, CountSink<float> sink) {
+  static_assert(QC || !COUNT, "counting needs Q");
   constexpr int NF = QC ? 6 : 4;
   __shared__ float s_in[NF][512];
   __shared__ float s_d[2][3 * kMixDT];
   __shared__ float s_red[8];
+  __shared__ uint32_t s_ntri[COUNT ? 64 : 1];
+  __shared__ int32_t s_sum[4];
   const int t = threadIdx.x, lane = t & 63;
+  (void)s_sum;
+  if constexpr (COUNT) {
+    if (t < 64) s_ntri[t] = reinterpret_cast<const uint32_t*>(sink.ntri)[t];
+  }
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int64_t base = (int64_t)blockIdx.x * 512;
   const float* src[6] = {x, y, z, u, v, w};
@@ -1643,15 +1725,57 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
       const int64_t o = base + t + 256 * h;
       if (o0) o0[o] = qv;
       if (o1) o1[o] = sqrtf(w1 * w1 + w2 * w2 + w3 * w3);
+      if constexpr (COUNT) s_in[0][t + 256 * h] = qv;   // x was read in the first pass only
       const float c = qv != qv ? neg_inf<float>() : qv;
       mn = c < mn ? c : mn;
       mx = c > mx ? c : mx;
     }
-    if (qmm) {
-      block_minmax<float, 256>(mn, mx, s_red);
-      if (t == 0) {
+    if (qmm || COUNT) {
+      block_minmax<float, 256>(mn, mx, s_red);   // its barriers publish the Q tile
+      if (qmm && t == 0) {
         qmm[2 * (int64_t)blockIdx.x] = mn;
         qmm[2 * (int64_t)blockIdx.x + 1] = mx;
+      }
+    }
+    if constexpr (COUNT) {
+      // cells t and t + 256 (t < 87); corners loaded once
+      constexpr int NC = 343;
+      float cv[2][8];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int cc = t + 256 * r < NC ? t + 256 * r : t;
+        const int n0 = cc % 7 + 8 * ((cc / 7) % 7) + 64 * (cc / 49);
+#pragma unroll
+        for (int vtx = 0; vtx < 8; ++vtx)
+          cv[r][vtx] = s_in[0][n0 + (vtx & 1) + 8 * ((vtx >> 1) & 1) + 64 * (vtx >> 2)];
+      }
+      const uint8_t* ntri = reinterpret_cast<const uint8_t*>(s_ntri);
+      const int64_t e = blockIdx.x;
+      for (int s = 0; s < sink.n_iso; ++s) {
+        const float c = sink.iso.v[s];
+        int packed = 0;   // triangles in the low 16 bits, active cells above
+        if ((mx > c) && !(mn > c)) {
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            if (t + 256 * r >= NC) continue;
+            int cs = 0;
+#pragma unroll
+            for (int vtx = 7; vtx >= 0; --vtx) cs = cs + cs + (cv[r][vtx] > c);
+            packed += ntri[cs] + ((cs != 0 && cs != 255) << 16);
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
+        if (lane == 0) s_sum[wv] = packed;
+        __syncthreads();
+        if (t == 0) {
+          const int sum = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+          sink.cnt[(int64_t)s * sink.n_elem + e] = sum & 0xffff;
+          const int a = sum >> 16;
+          if (sink.active && a)
+            atomicAdd((unsigned long long*)&sink.active[s], (unsigned long long)a);
+        }
+        __syncthreads();
       }
     }
   }
@@ -1968,18 +2092,29 @@ template <bool QC>
 hipError_t mixed_t(sem_dtype dt, const DeviceTables& tab, int64_t n_elem, const void* x,
                    const void* y, const void* z, const void* u, const void* v, const void* w,
                    void* o0, void* o1, void* o2, void* qmm, int32_t* status, hipStream_t s,
-                   const PhaseTimer& pt) {
+                   const PhaseTimer& pt, const CountSink<float>* sink = nullptr) {
+  const CountSink<float> none{};
+  const CountSink<float>& sk = sink ? *sink : none;
   auto go = [&](auto kern) {
     hipExtLaunchKernelGGL(kern, dim3((unsigned)n_elem), dim3(256), 0, s, pt.start, pt.stop, 0,
                           tab.d64[7], (const float*)x, (const float*)y, (const float*)z,
                           (const float*)u, (const float*)v, (const float*)w, (float*)o0,
-                          (float*)o1, (float*)o2, (float*)qmm, status);
+                          (float*)o1, (float*)o2, (float*)qmm, status, sk);
   };
+  constexpr bool kC = QC;   // counting variants exist with Q only
   switch (dt) {
-    case SEM_MIXED_BF16: go(mixed7<kMixBF16, QC>); break;
-    case SEM_MIXED_FP16: go(mixed7<kMixFP16, QC>); break;
-    case SEM_MIXED_BF16X3: go(mixed7<kMixBF16x3, QC>); break;
-    case SEM_MIXED_FP16X3: go(mixed7<kMixFP16x3, QC>); break;
+    case SEM_MIXED_BF16:
+      sink ? go(mixed7<kMixBF16, QC, kC>) : go(mixed7<kMixBF16, QC>);
+      break;
+    case SEM_MIXED_FP16:
+      sink ? go(mixed7<kMixFP16, QC, kC>) : go(mixed7<kMixFP16, QC>);
+      break;
+    case SEM_MIXED_BF16X3:
+      sink ? go(mixed7<kMixBF16x3, QC, kC>) : go(mixed7<kMixBF16x3, QC>);
+      break;
+    case SEM_MIXED_FP16X3:
+      sink ? go(mixed7<kMixFP16x3, QC, kC>) : go(mixed7<kMixFP16x3, QC>);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2106,7 +2241,56 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
     }
   }
   hipError_t err;
+  bool fused = false;
+  if (!is_mixed(dt)) {
+    // pencil forms (sem_qcrit's choice: every order in FP32, N <= 6 in FP64
+    // here) count in the Q kernel
+    CountSink<T> sink;
+    sink.n_iso = n_iso;
+    sink.iso = iso;
+    sink.ntri = tab.ntri;
+    sink.cnt = ws.cnt;
+    sink.active = active;
+    sink.n_elem = n_elem;
+    SEM_ORDER_SWITCH(order, {
+      if constexpr (N <= 7 || !std::is_same<T, double>::value) {
+        if (active)
+          hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
+        const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
+        hipExtLaunchKernelGGL((qcount_pencil<N, T>), dim3((unsigned)n_elem), dim3(Pen<N>::TH),
+                              0, s, pt.start, pt.stop, 0, d, (const T*)x, (const T*)y,
+                              (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q,
+                              (T*)om, (T*)qmm, status, sink);
+        phase_done(pt);
+        fused = true;
+      }
+    });
+  }
+  if (fused) {
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return iso_scan_emit<T>(order, tab, n_elem, x, y, z, q, n_iso, iso, out, nullptr,
+                            tri_count, ws, status, s);
+  }
   if (is_mixed(dt)) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (active)
+        hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
+      CountSink<float> sink;
+      sink.n_iso = n_iso;
+      sink.iso = iso;
+      sink.ntri = tab.ntri;
+      sink.cnt = ws.cnt;
+      sink.active = active;
+      sink.n_elem = n_elem;
+      const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
+      err = mixed_t<true>(dt, tab, n_elem, x, y, z, u, v, w, q, om, nullptr, qmm, status, s, pt,
+                          &sink);
+      phase_done(pt);
+      if (err != hipSuccess) return err;
+      return iso_scan_emit<T>(order, tab, n_elem, x, y, z, q, n_iso, iso, out, nullptr,
+                              tri_count, ws, status, s);
+    }
     const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
     err = mixed_t<true>(dt, tab, n_elem, x, y, z, u, v, w, q, om, nullptr, qmm, status, s, pt);
     phase_done(pt);
