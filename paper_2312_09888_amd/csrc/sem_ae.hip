@@ -144,11 +144,10 @@ ae_pack(int64_t e_begin, const float* __restrict__ u, const float* __restrict__ 
 //
 // C[z][m][n] = sum_{k in split z} A(m, k) B(k, n), A(m, k) = A[m a_sm + k a_sk],
 // B(k, n) = B[k b_sk + n b_sn].  Epilogue (flags): + bias[n % bias_mod], tanh,
-// binary16 rounding, times (1 - D[m][n]^2).  64 x 64 tiles, 16-deep k steps,
-// 256 threads with 4 x 4 outputs each.
+// binary16 rounding, times (1 - D[m][n]^2).  16-deep k steps.
 
 enum : int { kEpiTanh = 1, kEpiHalf = 2, kEpiTanhGrad = 4 };
-constexpr int kBM = 64, kBN = 64, kBK = 16;
+constexpr int kBK = 16;
 
 struct GemmArgs {
   int64_t M;
@@ -168,32 +167,37 @@ struct GemmArgs {
   const float* D;        // tanh-derivative source, layout of C
 };
 
+// BM x BN tile; 256 threads as 16 x 16, each with (BM / 16) x (BN / 16)
+// outputs.  Narrow layers (N = 32) use 128 x 32 tiles so that no thread
+// computes padding columns.
+template <int BM, int BN>
 __global__ void __launch_bounds__(kT) gemm_f32(GemmArgs g) {
-  __shared__ float As[kBK][kBM + 4];
-  __shared__ float Bs[kBK][kBN + 4];
+  constexpr int TM = BM / 16, TN = BN / 16;
+  __shared__ float As[kBK][BM + 4];
+  __shared__ float Bs[kBK][BN + 4];
   const int t = threadIdx.x;
   const int tx = t & 15, ty = t >> 4;
-  const int64_t m0 = (int64_t)blockIdx.x * kBM;   // rows on x: up to 2^31 - 1 tiles
-  const int n0 = blockIdx.y * kBN;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;   // rows on x: up to 2^31 - 1 tiles
+  const int n0 = blockIdx.y * BN;
   const int64_t kb = (int64_t)blockIdx.z * g.k_split;
   const int64_t ke = kb + g.k_split < g.K ? kb + g.k_split : g.K;
-  float acc[4][4] = {};
+  float acc[TM][TN] = {};
   for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
-    // A tile: kBM x kBK; the index order follows the contiguous operand axis
+    // A tile: BM x kBK; the index order follows the contiguous operand axis
 #pragma unroll
-    for (int q = 0; q < (kBM * kBK) / kT; ++q) {
+    for (int q = 0; q < (BM * kBK) / kT; ++q) {
       const int idx = t + q * kT;
       int mm, kk;
       if (g.a_sk == 1) { kk = idx % kBK; mm = idx / kBK; }
-      else { mm = idx % kBM; kk = idx / kBM; }
+      else { mm = idx % BM; kk = idx / BM; }
       const int64_t m = m0 + mm, k = k0 + kk;
       As[kk][mm] = (m < g.M && k < ke) ? g.A[m * g.a_sm + k * g.a_sk] : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < (kBN * kBK) / kT; ++q) {
+    for (int q = 0; q < (BN * kBK) / kT; ++q) {
       const int idx = t + q * kT;
       int nn, kk;
-      if (g.b_sn == 1) { nn = idx % kBN; kk = idx / kBN; }
+      if (g.b_sn == 1) { nn = idx % BN; kk = idx / BN; }
       else { kk = idx % kBK; nn = idx / kBK; }
       const int n = n0 + nn;
       const int64_t k = k0 + kk;
@@ -202,25 +206,25 @@ __global__ void __launch_bounds__(kT) gemm_f32(GemmArgs g) {
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < kBK; ++kk) {
-      float a[4], b[4];
+      float a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty + 16 * i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx + 16 * j];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < TN; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
   float* C = g.C + (int64_t)blockIdx.z * g.c_split;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < TM; ++i) {
     const int64_t m = m0 + ty + 16 * i;
     if (m >= g.M) continue;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < TN; ++j) {
       const int n = n0 + tx + 16 * j;
       if (n >= g.N) continue;
       float v = acc[i][j];
@@ -788,8 +792,13 @@ int in_width(int l) {
 hipError_t gemm(const GemmArgs& g0, int splits, hipStream_t s) {
   GemmArgs g = g0;
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((unsigned)cdiv(g.M, kBM), (unsigned)cdiv(g.N, kBN), (unsigned)splits);
-  hipLaunchKernelGGL(gemm_f32, grid, dim3(kT), 0, s, g);
+  if (g.N <= 32) {
+    dim3 grid((unsigned)cdiv(g.M, 128), (unsigned)cdiv(g.N, 32), (unsigned)splits);
+    hipLaunchKernelGGL((gemm_f32<128, 32>), grid, dim3(kT), 0, s, g);
+  } else {
+    dim3 grid((unsigned)cdiv(g.M, 64), (unsigned)cdiv(g.N, 64), (unsigned)splits);
+    hipLaunchKernelGGL((gemm_f32<64, 64>), grid, dim3(kT), 0, s, g);
+  }
   return hipGetLastError();
 }
 
@@ -907,15 +916,15 @@ hipError_t launch_ae_forward(int64_t n, const float* blocks, const float* params
                              float* recon, uint16_t* latent, void* ws, hipStream_t s) {
   AeWs w = ae_layout(ws, n);
   if (n <= 0) return hipSuccess;
-  hipMemcpyAsync(w.act[0], blocks, (size_t)n * 2048 * 4, hipMemcpyDeviceToDevice, s);
-  hipError_t e = forward_all(n, params, tanh_mask, w, s);
+  hipError_t e = hipMemcpyAsync(w.act[0], blocks, (size_t)n * 2048 * 4, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = forward_all(n, params, tanh_mask, w, s);
   if (e != hipSuccess) return e;
   if (latent)
     hipLaunchKernelGGL(to_half_bits, dim3((unsigned)cdiv(n * 32, kT)), dim3(kT), 0, s, w.act[3],
                        n * 32, latent);
   if (recon)
-    hipMemcpyAsync(recon, w.act[kLayers], (size_t)n * 2048 * 4, hipMemcpyDeviceToDevice, s);
-  return hipGetLastError();
+    e = hipMemcpyAsync(recon, w.act[kLayers], (size_t)n * 2048 * 4, hipMemcpyDeviceToDevice, s);
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,

@@ -736,11 +736,9 @@ __device__ __forceinline__ void dma_tile(const double* __restrict__ src, double*
   }
 }
 
-// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt and lgkmcnt
-// left at their maxima): wait until at most n vector-memory operations of
-// this wave are outstanding.
-constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70 | 0xF00; }
-// ... and additionally all LDS operations of this wave (lgkmcnt(0)).
+// s_waitcnt immediate (vmcnt in bits 3:0 and 15:14, expcnt at its maximum,
+// lgkmcnt 0): wait until at most n vector-memory operations and no LDS
+// operation of this wave are outstanding.
 constexpr int waitcnt_vm_lds(int n) { return (n & 15) | ((n >> 4) << 14) | 0x70; }
 
 // Barrier after an explicit wait: a plain s_barrier (the compiler-level
