@@ -1309,20 +1309,15 @@ __device__ __forceinline__ void qcount_dma7_elem(
     ov[ii] = sqrt(ov[ii] + w1 * w1 + w2 * w2);
   }
   const int j = p & 7, k = p >> 3;
-  const int64_t o = base + (k * 8 + j) * 8;
-  if (q) {
-    q[o + h] = qv[0];
-    q[o + 7 - h] = qv[1];
-  }
-  if (om) {
-    om[o + h] = ov[0];
-    om[o + 7 - h] = ov[1];
-  }
-  double* QT = s_uvw[0];   // free after the u pass
+  // Q and |omega| go out through LDS tiles (free after the u and v passes):
+  // each lane then stores 16 contiguous bytes, a wave 1 KiB
+  double* QT = s_uvw[0];
+  double* OT = s_uvw[1];
   double mn = pos_inf<double>(), mx = neg_inf<double>();
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii) {
-    if (COUNT) QT[dma7::at(ii ? 7 - h : h, j, k)] = qv[ii];
+    QT[dma7::at(ii ? 7 - h : h, j, k)] = qv[ii];
+    OT[dma7::at(ii ? 7 - h : h, j, k)] = ov[ii];
     const double c = qv[ii] != qv[ii] ? neg_inf<double>() : qv[ii];
     mn = c < mn ? c : mn;
     mx = c > mx ? c : mx;
@@ -1333,8 +1328,16 @@ __device__ __forceinline__ void qcount_dma7_elem(
     s_red[h] = mn;
     s_red[4 + h] = mx;
   }
-  bad = __syncthreads_or(bad);   // also publishes the Q tile and s_red
+  bad = __syncthreads_or(bad);   // also publishes the Q and |omega| tiles and s_red
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  {
+    // node pair (2t, 2t + 1) of the natural layout sits in one 16-byte slot
+    const int n = 2 * t;
+    const int sl = 2 * dma7::slot(n >> 6, (n >> 3) & 7, (n & 7) >> 1);
+    if (q) *reinterpret_cast<double2*>(q + base + n) = *reinterpret_cast<const double2*>(QT + sl);
+    if (om)
+      *reinterpret_cast<double2*>(om + base + n) = *reinterpret_cast<const double2*>(OT + sl);
+  }
   mn = fmin(fmin(s_red[0], s_red[1]), fmin(s_red[2], s_red[3]));
   mx = fmax(fmax(s_red[4], s_red[5]), fmax(s_red[6], s_red[7]));
   if (qmm && t == 0) {
