@@ -1402,17 +1402,27 @@ qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restr
 
 // Emission for N = 7, FP64: elements with triangles stage their field and
 // coordinate tiles with direct loads and emit through emit_element.
+// FP32 tiles (2 KiB) arrive in natural node order: lane l of wave h loads
+// bytes [16 l, 16 l + 16) of half h straight to the same LDS offsets.
+__device__ __forceinline__ void dma_tile_f32(const float* __restrict__ src, float* raw, int h,
+                                             int lane) {
+  lds_load16(reinterpret_cast<const double*>(src) + 128 * h + 2 * lane,
+             reinterpret_cast<double*>(raw) + 128 * h);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(128)
-emit_dma7(int64_t n_elem, const double* __restrict__ x, const double* __restrict__ y,
-          const double* __restrict__ z, const double* __restrict__ field, int n_iso,
-          IsoList<double> iso, IsoOut<double> out, const uint8_t* __restrict__ ntri_tab,
+emit_dma7(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
+          const T* __restrict__ z, const T* __restrict__ field, int n_iso,
+          IsoList<T> iso, IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
           const int8_t* __restrict__ tri_tab, const int32_t* __restrict__ cnt,
           const int64_t* __restrict__ offs, uint64_t* __restrict__ keys) {
   constexpr int NC = 343;
-  __shared__ double s_f[512];
-  __shared__ double s_x[512];
-  __shared__ double s_y[512];
-  __shared__ double s_z[512];
+  constexpr bool F64 = std::is_same<T, double>::value;
+  __shared__ T s_f[512];
+  __shared__ T s_x[512];
+  __shared__ T s_y[512];
+  __shared__ T s_z[512];
   static_assert(256 + 256 * kMcMaxTri * 3 == 4096, "tables fill one 4 KiB block");
   __shared__ uint4 s_tab[256];     // triangle counts (256 B), then the case table
   __shared__ uint8_t s_case[NC];
@@ -1434,25 +1444,37 @@ emit_dma7(int64_t n_elem, const double* __restrict__ x, const double* __restrict
              reinterpret_cast<double*>(s_tab) + 128 * h);
   lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * (64 * (h + 2) + p),
              reinterpret_cast<double*>(s_tab) + 128 * (h + 2));
-  dma_tile(field + base, s_f, h, p);
-  dma_tile(x + base, s_x, h, p);
-  dma_tile(y + base, s_y, h, p);
-  dma_tile(z + base, s_z, h, p);
+  if constexpr (F64) {
+    dma_tile(field + base, s_f, h, p);
+    dma_tile(x + base, s_x, h, p);
+    dma_tile(y + base, s_y, h, p);
+    dma_tile(z + base, s_z, h, p);
+  } else {
+    dma_tile_f32(field + base, s_f, h, p);
+    dma_tile_f32(x + base, s_x, h, p);
+    dma_tile_f32(y + base, s_y, h, p);
+    dma_tile_f32(z + base, s_z, h, p);
+  }
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
   barrier_after_wait();
   for (int s = 0; s < n_iso; ++s) {
     const int64_t flat = (int64_t)s * n_elem + e;
     if (cnt[flat] == 0) continue;
     int64_t g = offs[flat];
-    double* dst = out.ptr[0];
+    T* dst = out.ptr[0];
     int64_t cap = out.cap[0];
     if (out.per_iso) {
       g -= offs[(int64_t)s * n_elem];
       dst = out.ptr[s];
       cap = out.cap[s];
     }
-    emit_element<7, 128>(iso.v[s], DmaNode{}, s_f, s_x, s_y, s_z, s_ntri, s_tri, s_case, s_desc,
-                         s_wave, dst, g, cap, out.per_iso ? nullptr : keys, base);
+    if constexpr (F64)
+      emit_element<7, 128>(iso.v[s], DmaNode{}, s_f, s_x, s_y, s_z, s_ntri, s_tri, s_case,
+                           s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys, base);
+    else
+      emit_element<7, 128>(iso.v[s], StridedNode<8, 64>{}, s_f, s_x, s_y, s_z, s_ntri, s_tri,
+                           s_case, s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys,
+                           base);
   }
 }
 
@@ -2151,14 +2173,12 @@ hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, con
   if (!any_cap) return hipGetLastError();
   const PhaseTimer pe = phase_timer(SEM_PHASE_EMIT);
   bool done = false;
-  if constexpr (std::is_same<T, double>::value) {
-    if (order == 7) {
-      hipExtLaunchKernelGGL(emit_dma7, dim3((unsigned)n_elem), dim3(128), 0, s, pe.start,
-                            pe.stop, 0, n_elem, (const T*)x, (const T*)y, (const T*)z,
-                            (const T*)field, n_iso, iso, out, tab.ntri, tab.tri,
-                            (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys);
-      done = true;
-    }
+  if (order == 7) {
+    hipExtLaunchKernelGGL(emit_dma7<T>, dim3((unsigned)n_elem), dim3(128), 0, s, pe.start,
+                          pe.stop, 0, n_elem, (const T*)x, (const T*)y, (const T*)z,
+                          (const T*)field, n_iso, iso, out, tab.ntri, tab.tri,
+                          (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys);
+    done = true;
   }
   if (!done) {
     SEM_ORDER_SWITCH(order, {
