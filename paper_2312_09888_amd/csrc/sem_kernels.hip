@@ -901,13 +901,14 @@ iso_count(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ mm,
   using S = Shape<N>;
   constexpr int TH = S::kCellThreads;
   __shared__ T sf[S::NP];
-  __shared__ uint8_t s_ntri[256];
+  __shared__ uint32_t s_ntri4[64];
   __shared__ T red[2 * (TH / 64)];
-  __shared__ int64_t sred[TH / 64];
+  __shared__ int32_t sred[TH / 64];
   const int t = threadIdx.x;
   const int64_t e = blockIdx.x;
   const int64_t base = e * S::NP;
-  for (int q = t; q < 256; q += TH) s_ntri[q] = ntri_tab[q];
+  const uint8_t* s_ntri = reinterpret_cast<const uint8_t*>(s_ntri4);
+  if (t < 64) s_ntri4[t] = reinterpret_cast<const uint32_t*>(ntri_tab)[t];
   T mn, mx;
   bool need = true;
   if (mm) {
@@ -942,20 +943,27 @@ iso_count(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ mm,
       if (cdump && t < S::NC) cdump[t] = (mx > c) ? 255 : 0;
       continue;
     }
-    int64_t nt = 0, act = 0;
+    // triangles in the low 16 bits, active cells above: one block sum
+    int packed = 0;
     if (t < S::NC) {
       const int cs = cell_case<N>(sf, n0, c);
-      nt = s_ntri[cs];
-      act = (cs != 0 && cs != 255);
+      packed = s_ntri[cs] + ((cs != 0 && cs != 255) << 16);
       if (cdump) cdump[t] = (uint8_t)cs;
     }
-    nt = block_sum<TH>(nt, sred);
-    act = block_sum<TH>(act, sred);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
+    if ((t & 63) == 0) sred[t >> 6] = packed;
+    __syncthreads();
     if (t == 0) {
-      cnt[(int64_t)s * n_elem + e] = (int32_t)nt;
+      int sum = 0;
+#pragma unroll
+      for (int q = 0; q < TH / 64; ++q) sum += sred[q];
+      cnt[(int64_t)s * n_elem + e] = sum & 0xffff;
+      const int act = sum >> 16;
       if (active_total && act) atomicAdd((unsigned long long*)&active_total[s],
                                          (unsigned long long)act);
     }
+    __syncthreads();
   }
 }
 
