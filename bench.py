@@ -22,6 +22,8 @@ Two helper modes turn rocprofv3 CSV output into the committed summaries:
                               FETCH_SIZE / WRITE_SIZE runs of
                               `bench.py --copy-calibration`, scaled by what the
                               counters read for the 1 GiB calibration copy.
+  --summarize-mfma DIR OUT    matrix-core counters (SQ_INSTS_VALU_MFMA_MOPS_*)
+                              of the mixed-precision Q kernels per mode.
 """
 
 import argparse
@@ -73,6 +75,7 @@ def parse():
                          "known HBM traffic for scaling profiler byte counters)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DIR", "OUT"))
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT"))
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("DIR", "OUT"))
     ap.add_argument("--command", default="",
                     help="command line recorded in a summary (with --summarize-*)")
     return ap.parse_args()
@@ -103,6 +106,24 @@ def measured_traffic(kernel, dtype, n_launch_points):
     return rec.get("hbm_bytes_per_launch")
 
 
+MFMA_FILE = os.path.join(ROOT, "profiles", "mixed7_channel65536_mfma.json")
+MIX_MODES = {"0": "bf16", "1": "fp16", "2": "bf16x3", "3": "fp16x3"}
+MFMA_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 / FP16 matrix peak
+
+
+def measured_mfma():
+    """Matrix-core FLOPs per launch of each mixed mode's Q kernel from the
+    committed counter summary, or {} when the kernel source changed."""
+    try:
+        with open(MFMA_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return {}
+    if rec.get("kernel_src_sha256") != kernel_sha():
+        return {}
+    return {m: v["mfma_flops_per_launch"] for m, v in rec.get("modes", {}).items()}
+
+
 def load_isovalues():
     with open(os.path.join(ROOT, "tests", "golden", "channel_isovalues.json")) as fh:
         rec = json.load(fh)
@@ -116,6 +137,9 @@ def main():
         return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.command)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(*args.summarize_mfma, args.command)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -412,6 +436,9 @@ def compression_timing(args, sem):
            "loss_pca": loss_pca, "loss_finetuned": loss_ft,
            "compress_ms": round(comp_ms, 4), "decompress_ms": round(decomp_ms, 4),
            "compress_points_per_s": points / (comp_ms * 1e-3),
+           # one read of the four FP32 fields; latent, scales, flags and raw
+           # elements written
+           "compress_hbm": _hbm(raw_bytes + e * 81 + n_raw * 8192, comp_ms),
            "modal_ms": round(modal_ms, 4),
            "fallback_frac": n_raw / e, "ratio": ratio,
            "modal_fallback_frac": n_raw_mod / e, "modal_ratio": ratio_mod,
@@ -530,6 +557,9 @@ def batched_timing(args, sem):
            "qcrit_batch_default_ms": round(default_ms, 4),
            "qcrit_batch_ms": round(batch_ms, 4),
            "qcrit_batch_points_per_s": points / (batch_ms * 1e-3),
+           # six FP32 inputs, Q and |omega| out, two range values per element
+           "qcrit_batch_hbm": _hbm(32 * points + 8 * sum(
+               sp[1][0] * sp[1][1] * sp[1][2] for sp in specs), batch_ms),
            "step_eager_ms": round(eager_ms, 4), "step_graph_ms": round(graph_ms, 4),
            "step_graph_points_per_s": points / (graph_ms * 1e-3),
            "triangles": total_tri}
@@ -629,10 +659,21 @@ def c0_timing(args, sem, fields, q, isos, n):
               f"global keys + weld {weld_ms:.4f} ms: {n_tri} triangles -> "
               f"{int(verts.shape[0])} vertices")
     n_global = gs.n_global
+    n_nodes = int(q.numel())
     del gid, gs, qa
+    # dsavg: row pointers, column list, field in and out (FP64)
+    dbytes = 8 * (n_global + 1) + 24 * n_nodes
     return {"gs_setup_ms": round(setup_ms, 4), "dsavg_ms": round(avg_ms, 5),
             "keys_weld_ms": round(weld_ms, 5), "triangles": n_tri,
-            "welded_vertices": int(verts.shape[0]), "n_global": n_global}
+            "welded_vertices": int(verts.shape[0]), "n_global": n_global,
+            "dsavg_hbm": _hbm(dbytes, avg_ms)}
+
+
+def _hbm(nbytes, ms):
+    """Algorithmic bytes of one call against the 8 TB/s HBM peak."""
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"bytes": int(nbytes), "achieved_gbps": round(gbps, 1), "peak_gbps": 8000.0,
+            "frac": round(gbps / 8000.0, 4)}
 
 
 def precision_modes(args, sem, fields, isos, n_elem, points):
@@ -642,6 +683,7 @@ def precision_modes(args, sem, fields, isos, n_elem, points):
     import torch
     f32 = [f.float().contiguous() for f in fields]
     k = len(isos)
+    mfma = measured_mfma()
     dev = f32[0].device
     out = {}
     for mode in ("f32", "bf16", "fp16", "bf16x3", "fp16x3"):
@@ -681,6 +723,12 @@ def precision_modes(args, sem, fields, isos, n_elem, points):
         qms = ph["qcrit"][0] / max(ph["qcrit"][1], 1)
         out[mode] = {"ms_per_step": round(ms, 5), "points_per_s": points / (ms * 1e-3),
                      "q_phase_ms": round(qms, 5), "triangles": counts}
+        flops = mfma.get(mode)
+        if flops:
+            ach = flops / (qms * 1e-3) / 1e12
+            out[mode]["mfma"] = {"flops_per_launch": flops, "achieved_tflops": round(ach, 2),
+                                 "peak_tflops": MFMA_PEAK_TFLOPS,
+                                 "frac": round(ach / MFMA_PEAK_TFLOPS, 5)}
         log(args, f"{mode:7s}: {ms:.4f} ms/step ({points / (ms * 1e-3) / 1e9:.1f} G points/s), "
                   f"Q phase {qms:.4f} ms, triangles {counts}")
         del ws, tris, q, om, mm
@@ -754,6 +802,36 @@ def summarize_trace(directory, out, command):
         fh.write(f"# rocprofv3 kernel trace, MI355X\n# command: {command}\n"
                  f"# kernel source sha256: {kernel_sha()}\n\n" + "\n".join(lines) + "\n")
     print(open(out).read())
+
+
+def summarize_mfma(directory, out, command):
+    """Matrix-core work per launch of the mixed-precision Q kernels
+    (mixed7<mode, true, true>, sem_extract): SQ_INSTS_VALU_MFMA_MOPS_BF16 /
+    _F16 count matrix operations in units of 512 FLOPs."""
+    per = {}
+    for r in _csv(directory, "counter_collection.csv"):
+        name = _short(r["Kernel_Name"])
+        if not name.startswith("mixed7<") or not name.endswith("true, true>"):
+            continue
+        mode = MIX_MODES.get(name[len("mixed7<"):].split(",")[0].strip())
+        if mode is None:
+            continue
+        per.setdefault(mode, {}).setdefault(r["Counter_Name"], []).append(
+            float(r["Counter_Value"]))
+    modes = {}
+    for mode, ctr in per.items():
+        avg = {k: sum(v) / len(v) for k, v in ctr.items()}
+        mops = avg.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) + avg.get(
+            "SQ_INSTS_VALU_MFMA_MOPS_F16", 0.0)
+        modes[mode] = {"dispatches": len(next(iter(ctr.values()))),
+                       "counters_per_dispatch": avg,
+                       "mfma_flops_per_launch": mops * 512.0}
+    rec = {"kernel": "mixed7<mode, true, true>",
+           "workload": "channel 65,536 order-7 elements, 3 Q isovalues, FP32 storage",
+           "kernel_src_sha256": kernel_sha(), "command": command, "modes": modes}
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def summarize_pmc(fetch_dir, write_dir, out, command):
