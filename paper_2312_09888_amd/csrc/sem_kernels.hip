@@ -1100,7 +1100,7 @@ __global__ void fill_i64(int64_t* __restrict__ p, int n, int64_t value) {
 //
 // qcount_dma7 computes Q and |omega| from the six staged tiles, keeps Q in
 // LDS and counts every isovalue's triangles and active cells per element.
-// The counts then go through the device-wide exclusive scan, and emit_dma7
+// The counts then go through the device-wide exclusive scan, and emit_direct
 // re-stages the Q and coordinate tiles of the elements that have triangles
 // and writes them at their offsets.  (A single pass with a decoupled
 // look-back saves that re-read, but on MI355X its chain of device-scope
@@ -1410,27 +1410,39 @@ qcount_dma7(int64_t n_elem, const double* __restrict__ eo, const double* __restr
 
 // Emission for N = 7, FP64: elements with triangles stage their field and
 // coordinate tiles with direct loads and emit through emit_element.
-// FP32 tiles (2 KiB) arrive in natural node order: lane l of wave h loads
-// bytes [16 l, 16 l + 16) of half h straight to the same LDS offsets.
-__device__ __forceinline__ void dma_tile_f32(const float* __restrict__ src, float* raw, int h,
-                                             int lane) {
-  lds_load16(reinterpret_cast<const double*>(src) + 128 * h + 2 * lane,
-             reinterpret_cast<double*>(raw) + 128 * h);
+
+// Odd N (an even number of nodes per edge: every tile is a whole number of
+// 16-byte chunks and starts 16-byte aligned): a tile arrives in natural
+// node order, wave h issuing the 1 KiB instructions h, h + 2, ... (lanes
+// past the tile's end load nothing).
+template <int N, typename T>
+__device__ __forceinline__ void dma_tile_natural(const T* __restrict__ src, T* raw, int h,
+                                                 int lane) {
+  constexpr int CH = (N + 1) * (N + 1) * (N + 1) * (int)sizeof(T) / 16;   // 16-byte chunks
+  static_assert((N + 1) * (N + 1) * (N + 1) * sizeof(T) % 16 == 0, "whole chunks");
+#pragma unroll
+  for (int q = h; q * 64 < CH; q += 2) {
+    if (q * 64 + lane < CH)
+      lds_load16(reinterpret_cast<const double*>(src) + 2 * (q * 64 + lane),
+                 reinterpret_cast<double*>(raw) + 128 * q);
+  }
 }
 
-template <typename T>
+// emit_direct<N, T>: the element's tiles and the case tables by direct loads,
+// two waves per element (odd N; N = 7 FP64 uses the swizzled tile).
+template <int N, typename T>
 __global__ void __launch_bounds__(128)
-emit_dma7(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
-          const T* __restrict__ z, const T* __restrict__ field, int n_iso,
-          IsoList<T> iso, IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
-          const int8_t* __restrict__ tri_tab, const int32_t* __restrict__ cnt,
-          const int64_t* __restrict__ offs, uint64_t* __restrict__ keys) {
-  constexpr int NC = 343;
-  constexpr bool F64 = std::is_same<T, double>::value;
-  __shared__ T s_f[512];
-  __shared__ T s_x[512];
-  __shared__ T s_y[512];
-  __shared__ T s_z[512];
+emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
+            const T* __restrict__ z, const T* __restrict__ field, int n_iso,
+            IsoList<T> iso, IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
+            const int8_t* __restrict__ tri_tab, const int32_t* __restrict__ cnt,
+            const int64_t* __restrict__ offs, uint64_t* __restrict__ keys) {
+  constexpr int P = N + 1, NP = P * P * P, NC = N * N * N;
+  constexpr bool SWZ = N == 7 && std::is_same<T, double>::value;
+  __shared__ __attribute__((aligned(16))) T s_f[NP];
+  __shared__ __attribute__((aligned(16))) T s_x[NP];
+  __shared__ __attribute__((aligned(16))) T s_y[NP];
+  __shared__ __attribute__((aligned(16))) T s_z[NP];
   static_assert(256 + 256 * kMcMaxTri * 3 == 4096, "tables fill one 4 KiB block");
   __shared__ uint4 s_tab[256];     // triangle counts (256 B), then the case table
   __shared__ uint8_t s_case[NC];
@@ -1445,23 +1457,23 @@ emit_dma7(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
   bool any = false;
   for (int s = 0; s < n_iso; ++s) any = any || cnt[(int64_t)s * n_elem + e] > 0;
   if (!any) return;
-  const int64_t base = e * 512;
+  const int64_t base = e * NP;
   // the two tables (one 4 KiB block: counts, then the case table) and the
   // four tiles all arrive by direct loads before the one wait below
   lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * (64 * h + p),
              reinterpret_cast<double*>(s_tab) + 128 * h);
   lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * (64 * (h + 2) + p),
              reinterpret_cast<double*>(s_tab) + 128 * (h + 2));
-  if constexpr (F64) {
+  if constexpr (SWZ) {
     dma_tile(field + base, s_f, h, p);
     dma_tile(x + base, s_x, h, p);
     dma_tile(y + base, s_y, h, p);
     dma_tile(z + base, s_z, h, p);
   } else {
-    dma_tile_f32(field + base, s_f, h, p);
-    dma_tile_f32(x + base, s_x, h, p);
-    dma_tile_f32(y + base, s_y, h, p);
-    dma_tile_f32(z + base, s_z, h, p);
+    dma_tile_natural<N>(field + base, s_f, h, p);
+    dma_tile_natural<N>(x + base, s_x, h, p);
+    dma_tile_natural<N>(y + base, s_y, h, p);
+    dma_tile_natural<N>(z + base, s_z, h, p);
   }
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
   barrier_after_wait();
@@ -1476,13 +1488,13 @@ emit_dma7(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
       dst = out.ptr[s];
       cap = out.cap[s];
     }
-    if constexpr (F64)
+    if constexpr (SWZ)
       emit_element<7, 128>(iso.v[s], DmaNode{}, s_f, s_x, s_y, s_z, s_ntri, s_tri, s_case,
                            s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys, base);
     else
-      emit_element<7, 128>(iso.v[s], StridedNode<8, 64>{}, s_f, s_x, s_y, s_z, s_ntri, s_tri,
-                           s_case, s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys,
-                           base);
+      emit_element<N, 128>(iso.v[s], StridedNode<P, P * P>{}, s_f, s_x, s_y, s_z, s_ntri,
+                           s_tri, s_case, s_desc, s_wave, dst, g, cap,
+                           out.per_iso ? nullptr : keys, base);
   }
 }
 
@@ -2180,23 +2192,20 @@ hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, con
   for (int q = 0; q < (out.per_iso ? n_iso : 1); ++q) any_cap = any_cap || out.cap[q] > 0;
   if (!any_cap) return hipGetLastError();
   const PhaseTimer pe = phase_timer(SEM_PHASE_EMIT);
-  bool done = false;
-  if (order == 7) {
-    hipExtLaunchKernelGGL(emit_dma7<T>, dim3((unsigned)n_elem), dim3(128), 0, s, pe.start,
-                          pe.stop, 0, n_elem, (const T*)x, (const T*)y, (const T*)z,
-                          (const T*)field, n_iso, iso, out, tab.ntri, tab.tri,
-                          (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys);
-    done = true;
-  }
-  if (!done) {
-    SEM_ORDER_SWITCH(order, {
+  SEM_ORDER_SWITCH(order, {
+    if constexpr (N % 2 == 1) {
+      hipExtLaunchKernelGGL((emit_direct<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
+                            pe.start, pe.stop, 0, n_elem, (const T*)x, (const T*)y,
+                            (const T*)z, (const T*)field, n_iso, iso, out, tab.ntri, tab.tri,
+                            (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys);
+    } else {
       hipExtLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem),
                             dim3(Shape<N>::kCellThreads), 0, s, pe.start, pe.stop, 0, n_elem,
                             (const T*)x, (const T*)y, (const T*)z, (const T*)field, n_iso, iso,
                             tab.ntri, tab.tri, (const int32_t*)ws.cnt, (const int64_t*)ws.offs,
                             out, keys);
-    });
-  }
+    }
+  });
   phase_done(pe);
   return hipGetLastError();
 }
