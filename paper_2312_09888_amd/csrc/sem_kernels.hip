@@ -1498,6 +1498,111 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
   }
 }
 
+// count_direct<N, T>: the count pass of the two-pass isosurface for odd N:
+// the field tile (and the triangle-count table) by direct loads, two waves
+// per element, one packed block sum (triangles | active cells << 16) per
+// isovalue; elements the range excludes write zero counts without loading.
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+count_direct(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ mm,
+             int n_iso, IsoList<T> iso, const uint8_t* __restrict__ ntri_tab,
+             int32_t* __restrict__ cnt, int64_t* __restrict__ active_total,
+             uint8_t* __restrict__ case_idx) {
+  constexpr int P = N + 1, NP = P * P * P, NC = N * N * N, R = (NC + 127) / 128;
+  __shared__ __attribute__((aligned(16))) T sf[NP];
+  __shared__ __attribute__((aligned(16))) uint8_t s_ntri[256];
+  __shared__ T red[4];
+  __shared__ int32_t s_sum[2];
+  const int t = threadIdx.x;
+  const int h = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int lane = t & 63;
+  const int64_t e = blockIdx.x;
+  T mn = pos_inf<T>(), mx = neg_inf<T>();
+  bool need = true;
+  if (mm) {
+    mn = mm[2 * e];
+    mx = mm[2 * e + 1];
+    need = false;
+    for (int s = 0; s < n_iso; ++s) need = need || ((mx > iso.v[s]) && !(mn > iso.v[s]));
+  }
+  if (!need) {
+    // no isovalue inside the element's range: zero counts, uniform cases
+    for (int s = 0; s < n_iso; ++s) {
+      if (t == 0) cnt[(int64_t)s * n_elem + e] = 0;
+      if (case_idx) {
+        uint8_t* cd = case_idx + ((int64_t)s * n_elem + e) * NC;
+        const uint8_t v = (mx > iso.v[s]) ? 255 : 0;
+        for (int q = t; q < NC; q += 128) cd[q] = v;
+      }
+    }
+    return;
+  }
+  if (h == 0 && lane < 16)
+    lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * lane,
+               reinterpret_cast<double*>(s_ntri));
+  dma_tile_natural<N>(field + e * NP, sf, h, lane);
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
+  barrier_after_wait();
+  if (!mm) {
+    T a = pos_inf<T>(), b = neg_inf<T>();
+    for (int q = t; q < NP; q += 128) {
+      T val = sf[q];
+      if (val != val) val = neg_inf<T>();
+      a = val < a ? val : a;
+      b = val > b ? val : b;
+    }
+    block_minmax<T, 128>(a, b, red);
+    mn = a;
+    mx = b;
+  }
+  // corners of this thread's cells, loaded once
+  T cv[R][8];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int cc = t + 128 * r < NC ? t + 128 * r : 0;
+    const int n0 = cc % N + P * ((cc / N) % N) + P * P * (cc / (N * N));
+#pragma unroll
+    for (int vtx = 0; vtx < 8; ++vtx)
+      cv[r][vtx] = sf[n0 + (vtx & 1) + P * ((vtx >> 1) & 1) + P * P * (vtx >> 2)];
+  }
+  for (int s = 0; s < n_iso; ++s) {
+    const T c = iso.v[s];
+    const bool straddle = (mx > c) && !(mn > c);
+    uint8_t* cd = case_idx ? case_idx + ((int64_t)s * n_elem + e) * NC : nullptr;
+    int packed = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int cell = t + 128 * r;
+      if (cell >= NC) continue;
+      int cs = 0;
+      if (straddle) {
+#pragma unroll
+        for (int vtx = 7; vtx >= 0; --vtx) cs = cs + cs + (cv[r][vtx] > c);
+        packed += s_ntri[cs] + ((cs != 0 && cs != 255) << 16);
+      } else {
+        cs = (mx > c) ? 255 : 0;
+      }
+      if (cd) cd[cell] = (uint8_t)cs;
+    }
+    if (!straddle) {
+      if (t == 0) cnt[(int64_t)s * n_elem + e] = 0;
+      continue;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
+    if (lane == 0) s_sum[h] = packed;
+    __syncthreads();
+    if (t == 0) {
+      const int sum = s_sum[0] + s_sum[1];
+      cnt[(int64_t)s * n_elem + e] = sum & 0xffff;
+      const int act = sum >> 16;
+      if (active_total && act)
+        atomicAdd((unsigned long long*)&active_total[s], (unsigned long long)act);
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // mixed precision, N = 7, FP32 storage: derivative contractions on MFMA
 // ---------------------------------------------------------------------------
@@ -2222,10 +2327,16 @@ hipError_t iso_pipeline(int order, const DeviceTables& tab, int64_t n_elem, cons
   if (active) hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
   const PhaseTimer pt = phase_timer(SEM_PHASE_COUNT);
   SEM_ORDER_SWITCH(order, {
-    hipExtLaunchKernelGGL((iso_count<N, T>), dim3((unsigned)n_elem),
-                          dim3(Shape<N>::kCellThreads), 0, s, pt.start, pt.stop, 0, n_elem,
-                          (const T*)field, (const T*)mm, n_iso, iso, tab.ntri, ws.cnt, active,
-                          case_idx);
+    if constexpr (N % 2 == 1) {
+      hipExtLaunchKernelGGL((count_direct<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
+                            pt.start, pt.stop, 0, n_elem, (const T*)field, (const T*)mm, n_iso,
+                            iso, tab.ntri, ws.cnt, active, case_idx);
+    } else {
+      hipExtLaunchKernelGGL((iso_count<N, T>), dim3((unsigned)n_elem),
+                            dim3(Shape<N>::kCellThreads), 0, s, pt.start, pt.stop, 0, n_elem,
+                            (const T*)field, (const T*)mm, n_iso, iso, tab.ntri, ws.cnt, active,
+                            case_idx);
+    }
   });
   phase_done(pt);
   return iso_scan_emit<T>(order, tab, n_elem, x, y, z, field, n_iso, iso, out, keys, tri_count,
