@@ -1230,6 +1230,17 @@ __device__ __forceinline__ int wave_sum_i32(const WaveXor& w, int v) {
   return v;
 }
 
+// Bits (q > c_s) of the isovalues g .. g + 3 (those below n) at bits 0, 8,
+// 16, 24; a NaN compares below every isovalue.
+__device__ __forceinline__ uint32_t iso_bits4(double q, const IsoList<double>& iso, int g,
+                                              int n) {
+  uint32_t b = 0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if (g + s < n) b |= (uint32_t)(q > iso.v[g + s]) << (8 * s);
+  return b;
+}
+
 // COUNT: also count every isovalue's triangles and active cells per element
 // from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
 template <bool COUNT>
@@ -1248,8 +1259,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
   __shared__ double s_S[Pen<7>::SZ];
   __shared__ double s_T[Pen<7>::SZ];
   __shared__ double s_red[8];
-  __shared__ uint8_t s_ntri[256];
-  __shared__ int32_t s_wave[8];
+  __shared__ int32_t s_wave[16];
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int p = t & 63;
   const int64_t base = e * 512;
@@ -1280,7 +1290,6 @@ __device__ __forceinline__ void qcount_dma7_elem(
     pin(kk[ii].sz); pin(kk[ii].tx); pin(kk[ii].ty); pin(kk[ii].tz);
   }
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
-  if (COUNT) s_ntri[t] = nt_own;   // read only after later barriers
   barrier_after_wait();
   double fr[2], fs[2], ft[2], a01[2], a02[2], a12[2], qv[2], ov[2];
   dma_pass4(s_uvw[0], eo, s_S, s_T, h, p, fr, fs, ft);
@@ -1336,7 +1345,20 @@ __device__ __forceinline__ void qcount_dma7_elem(
     s_red[h] = mn;
     s_red[4 + h] = mx;
   }
-  bad = __syncthreads_or(bad);   // also publishes the Q and |omega| tiles and s_red
+  // Counting works on isovalues four at a time: a node's word holds bit
+  // (Q > c_s) at bit 8s, so the eight corner words of a cell, each shifted
+  // by its vertex number and summed, give the four cell cases as bytes. The
+  // derivative tiles are free now: S holds the node words, T the case table
+  // as triangles + (1 << 16) per non-trivial case.
+  uint32_t* s_bits = reinterpret_cast<uint32_t*>(s_S);
+  int32_t* s_tab = reinterpret_cast<int32_t*>(s_T);
+  const int node0 = h + 8 * j + 64 * k, node1 = 7 - h + 8 * j + 64 * k;
+  if constexpr (COUNT) {
+    s_tab[t] = (int)nt_own + ((t != 0 && t != 255) << 16);
+    s_bits[node0] = iso_bits4(qv[0], iso, 0, n_iso);
+    s_bits[node1] = iso_bits4(qv[1], iso, 0, n_iso);
+  }
+  bad = __syncthreads_or(bad);   // also publishes the tiles, s_red and the node words
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
   {
     // node pair (2t, 2t + 1) of the natural layout sits in one 16-byte slot
@@ -1353,44 +1375,55 @@ __device__ __forceinline__ void qcount_dma7_elem(
     qmm[2 * e + 1] = mx;
   }
   if constexpr (COUNT) {
-    // the eight corner values of this thread's cells, loaded once: cell t,
-    // and cell t + 256 for the threads t < 87 (waves 0 and 1 only)
+    // cell t, and cell t + 256 for the threads t < 87 (waves 0 and 1 only);
+    // corner 0 of a cell at its natural node index, the others at fixed
+    // offsets from it
     constexpr int NC2 = NC - 256;
     const bool two = t < NC2;
-    double cv[2][8];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      if (r == 1 && h >= 2) break;
-      const int cc = r == 0 ? t : (two ? t + 256 : t);
-      const int ci = cc % 7, cj = (cc / 7) % 7, ck = cc / 49;
-#pragma unroll
-      for (int vtx = 0; vtx < 8; ++vtx)
-        cv[r][vtx] = QT[dma7::at(ci + (vtx & 1), cj + ((vtx >> 1) & 1), ck + (vtx >> 2))];
-    }
-    for (int s = 0; s < n_iso; ++s) {
-      const double c = iso.v[s];
-      // triangles in the low 16 bits, active cells above (one wave sum)
-      int packed = 0;
-      if ((mx > c) && !(mn > c)) {
+    const int c1 = two ? t + 256 : t;
+    const int cb[2] = {t % 7 + 8 * ((t / 7) % 7) + 64 * (t / 49),
+                       c1 % 7 + 8 * ((c1 / 7) % 7) + 64 * (c1 / 49)};
+    for (int g = 0; g < n_iso; g += 4) {
+      const int m = n_iso - g < 4 ? n_iso - g : 4;
+      if (g > 0) {   // every read of the previous words is behind the last barrier
+        s_bits[node0] = iso_bits4(qv[0], iso, g, n_iso);
+        s_bits[node1] = iso_bits4(qv[1], iso, g, n_iso);
+        __syncthreads();
+      }
+      // an element outside every isovalue's range of the group has only
+      // trivial cases (NaN nodes count as below; mn is -inf then)
+      bool live = false;
+      for (int s = 0; s < m; ++s) live |= (mx > iso.v[g + s]) && !(mn > iso.v[g + s]);
+      int packed[4] = {0, 0, 0, 0};
+      if (live) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
           if (r == 1 && h >= 2) break;
-          int cs = 0;
+          uint32_t word = 0;
 #pragma unroll
-          for (int vtx = 7; vtx >= 0; --vtx) cs = cs + cs + (cv[r][vtx] > c);
-          if (r == 0 || two) packed += s_ntri[cs] + ((cs != 0 && cs != 255) << 16);
+          for (int vtx = 0; vtx < 8; ++vtx)
+            word += s_bits[cb[r] + (vtx & 1) + 8 * ((vtx >> 1) & 1) + 64 * (vtx >> 2)] << vtx;
+          if (r == 0 || two) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              if (s < m) packed[s] += s_tab[(word >> (8 * s)) & 255];
+          }
         }
       }
-      packed = wave_sum_i32(wx, packed);
-      if (p == 0) s_wave[h] = packed;
-      __syncthreads();
-      if (t == 0) {
-        const int sum = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-        cnt[(int64_t)s * n_elem + e] = sum & 0xffff;
-        const int a = sum >> 16;
-        if (active && a) atomicAdd((unsigned long long*)&active[s], (unsigned long long)a);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if (s < m) {
+          const int sum = wave_sum_i32(wx, packed[s]);
+          if (p == 0) s_wave[4 * s + h] = sum;
+        }
       }
       __syncthreads();
+      if (t < m) {
+        const int sum = s_wave[4 * t] + s_wave[4 * t + 1] + s_wave[4 * t + 2] + s_wave[4 * t + 3];
+        cnt[(int64_t)(g + t) * n_elem + e] = sum & 0xffff;
+        const int a = sum >> 16;
+        if (active && a) atomicAdd((unsigned long long*)&active[g + t], (unsigned long long)a);
+      }
     }
   }
 }
