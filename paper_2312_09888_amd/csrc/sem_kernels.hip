@@ -548,6 +548,58 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
   return ok;
 }
 
+// Counting four isovalues at a time. A node's word holds bit (q > c_s) at
+// bit 8s for the isovalues g .. g + 3 below n (a NaN compares below every
+// isovalue); the eight corner words of a cell, each shifted by its vertex
+// number (vertex bits x, y, z = 1, 2, 4) and summed, hold the cell's four
+// cases as bytes. A case maps to triangles + (1 << 16) when non-trivial, so
+// one sum per isovalue gives both the triangle and the active-cell count.
+template <typename T>
+__device__ __forceinline__ uint32_t iso_bits4(T q, const IsoList<T>& iso, int g, int n) {
+  uint32_t b = 0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if (g + s < n) b |= (uint32_t)(q > iso.v[g + s]) << (8 * s);
+  return b;
+}
+template <int RS, int SS>
+__device__ __forceinline__ uint32_t cell_word(const uint32_t* bits, int n0) {
+  uint32_t w = 0;
+#pragma unroll
+  for (int vtx = 0; vtx < 8; ++vtx)
+    w += bits[n0 + (vtx & 1) + RS * ((vtx >> 1) & 1) + SS * (vtx >> 2)] << vtx;
+  return w;
+}
+__device__ __forceinline__ int case_count_entry(int cs, uint8_t nt) {
+  return (int)nt + ((cs != 0 && cs != 255) << 16);
+}
+// Element totals of the isovalues g .. g + m - 1 from per-thread packed
+// sums: wave sums into red[4 * NW], one barrier, threads t < m write.
+// red must not be read again before a later barrier.
+template <int NW>
+__device__ __forceinline__ void publish_counts(const int (&packed)[4], int m, int g, int t,
+                                               int32_t* red, int32_t* cnt, int64_t n_elem,
+                                               int64_t e, int64_t* active) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (s < m) {
+      int v = packed[s];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if ((t & 63) == 0) red[NW * s + (t >> 6)] = v;
+    }
+  }
+  __syncthreads();
+  if (t < m) {
+    int sum = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += red[NW * t + w];
+    cnt[(int64_t)(g + t) * n_elem + e] = sum & 0xffff;
+    const int a = sum >> 16;
+    if (active && a) atomicAdd((unsigned long long*)&active[g + t], (unsigned long long)a);
+  }
+}
+
 // Where a Q kernel also counts each isovalue's triangles and active cells per
 // element (the count pass of the isosurface, fused).
 template <typename T>
@@ -569,14 +621,14 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   using Q = Pen<N>;
   constexpr int P = Q::P, H0 = Q::H0;
   __shared__ PencilTiles<N, T> sm;
-  __shared__ uint32_t s_ntri[COUNT ? 64 : 1];
-  __shared__ int32_t s_sum[Q::TH / 64];
+  __shared__ int32_t s_tab[COUNT ? 256 : 1];
+  __shared__ int32_t s_sum[COUNT ? 4 * Q::TH / 64 : 1];
   const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
   const int p = t % Q::LT;
   const int64_t base = e * (P * P * P);
   if constexpr (COUNT) {
     // case table, published by the barriers of the passes
-    if (t < 64) s_ntri[t] = reinterpret_cast<const uint32_t*>(sink->ntri)[t];
+    for (int c = t; c < 256; c += Q::TH) s_tab[c] = case_count_entry(c, sink->ntri[c]);
   }
   T qv[H0], ov[H0];
   int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
@@ -593,7 +645,9 @@ __device__ __forceinline__ void qcrit_pencil_elem(
         const int64_t o = base + (k * P + j) * P + i;
         if (q) q[o] = qv[ii];
         if (om) om[o] = ov[ii];
-        if constexpr (COUNT) sm.F[Q::at(i, j, k)] = qv[ii];   // F is free after the last pass
+        if constexpr (COUNT)   // F is free after the last pass
+          reinterpret_cast<uint32_t*>(sm.F)[Q::at(i, j, k)] =
+              iso_bits4<T>(qv[ii], sink->iso, 0, sink->n_iso);
         const T c = qv[ii] != qv[ii] ? neg_inf<T>() : qv[ii];
         mn = c < mn ? c : mn;
         mx = c > mx ? c : mx;
@@ -610,45 +664,46 @@ __device__ __forceinline__ void qcrit_pencil_elem(
     }
   }
   if constexpr (COUNT) {
-    // cells t, t + TH, ...: corner values loaded once for every isovalue
-    constexpr int NC = N * N * N, R = (NC + Q::TH - 1) / Q::TH;
-    T cv[R][8];
+    // cells t, t + TH, ...; node words in F
+    constexpr int NC = N * N * N, R = (NC + Q::TH - 1) / Q::TH, NW = Q::TH / 64;
+    uint32_t* bits = reinterpret_cast<uint32_t*>(sm.F);
+    int n0[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int cc = t + r * Q::TH < NC ? t + r * Q::TH : 0;
-      const int n0 = Q::at(cc % N, (cc / N) % N, cc / (N * N));
-#pragma unroll
-      for (int vtx = 0; vtx < 8; ++vtx)
-        cv[r][vtx] = sm.F[n0 + (vtx & 1) + Q::RS * ((vtx >> 1) & 1) + Q::SS * (vtx >> 2)];
+      n0[r] = Q::at(cc % N, (cc / N) % N, cc / (N * N));
     }
-    const uint8_t* ntri = reinterpret_cast<const uint8_t*>(s_ntri);
-    for (int s = 0; s < sink->n_iso; ++s) {
-      const T c = sink->iso.v[s];
-      int packed = 0;   // triangles in the low 16 bits, active cells above
-      if ((mx > c) && !(mn > c)) {
+    const int n_iso = sink->n_iso;
+    for (int g = 0; g < n_iso; g += 4) {
+      const int m = n_iso - g < 4 ? n_iso - g : 4;
+      if (g > 0) {   // every read of the previous words is behind the last barrier
+        if (valid) {
+          const int j = p % P, k = p / P;
+#pragma unroll
+          for (int ii = 0; ii < H0; ++ii) {
+            const int i = h * H0 + ii;
+            if (i < P) bits[Q::at(i, j, k)] = iso_bits4<T>(qv[ii], sink->iso, g, n_iso);
+          }
+        }
+        __syncthreads();
+      }
+      // elements outside every isovalue's range of the group have only
+      // trivial cases (NaN nodes count as below; mn is -inf then)
+      bool live = false;
+      for (int s = 0; s < m; ++s)
+        live |= (mx > sink->iso.v[g + s]) && !(mn > sink->iso.v[g + s]);
+      int packed[4] = {0, 0, 0, 0};
+      if (live) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if (t + r * Q::TH >= NC) continue;
-          int cs = 0;
+          const uint32_t word = cell_word<Q::RS, Q::SS>(bits, n0[r]);
 #pragma unroll
-          for (int vtx = 7; vtx >= 0; --vtx) cs = cs + cs + (cv[r][vtx] > c);
-          packed += ntri[cs] + ((cs != 0 && cs != 255) << 16);
+          for (int s = 0; s < 4; ++s)
+            if (s < m) packed[s] += s_tab[(word >> (8 * s)) & 255];
         }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
-      if ((t & 63) == 0) s_sum[t >> 6] = packed;
-      __syncthreads();
-      if (t == 0) {
-        int sum = 0;
-#pragma unroll
-        for (int q2 = 0; q2 < Q::TH / 64; ++q2) sum += s_sum[q2];
-        sink->cnt[(int64_t)s * sink->n_elem + e] = sum & 0xffff;
-        const int a = sum >> 16;
-        if (sink->active && a)
-          atomicAdd((unsigned long long*)&sink->active[s], (unsigned long long)a);
-      }
-      __syncthreads();
+      publish_counts<NW>(packed, m, g, t, s_sum, sink->cnt, sink->n_elem, e, sink->active);
     }
   }
 }
@@ -1230,17 +1285,6 @@ __device__ __forceinline__ int wave_sum_i32(const WaveXor& w, int v) {
   return v;
 }
 
-// Bits (q > c_s) of the isovalues g .. g + 3 (those below n) at bits 0, 8,
-// 16, 24; a NaN compares below every isovalue.
-__device__ __forceinline__ uint32_t iso_bits4(double q, const IsoList<double>& iso, int g,
-                                              int n) {
-  uint32_t b = 0;
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-    if (g + s < n) b |= (uint32_t)(q > iso.v[g + s]) << (8 * s);
-  return b;
-}
-
 // COUNT: also count every isovalue's triangles and active cells per element
 // from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
 template <bool COUNT>
@@ -1818,13 +1862,10 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
   __shared__ float s_in[NF][512];
   __shared__ float s_d[2][3 * kMixDT];
   __shared__ float s_red[8];
-  __shared__ uint32_t s_ntri[COUNT ? 64 : 1];
-  __shared__ int32_t s_sum[4];
+  __shared__ int32_t s_tab[COUNT ? 256 : 1];
+  __shared__ int32_t s_sum[COUNT ? 16 : 1];
   const int t = threadIdx.x, lane = t & 63;
-  (void)s_sum;
-  if constexpr (COUNT) {
-    if (t < 64) s_ntri[t] = reinterpret_cast<const uint32_t*>(sink.ntri)[t];
-  }
+  if constexpr (COUNT) s_tab[t] = case_count_entry(t, sink.ntri[t]);
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int64_t base = (int64_t)blockIdx.x * 512;
   const float* src[6] = {x, y, z, u, v, w};
@@ -1896,6 +1937,8 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
     }
   } else {
     float mn = pos_inf<float>(), mx = neg_inf<float>();
+    float qn[2];
+    uint32_t* bits = reinterpret_cast<uint32_t*>(s_in[0]);   // x was read in the first pass only
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const float(&A)[3][3] = a[h];
@@ -1906,7 +1949,8 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
       const int64_t o = base + t + 256 * h;
       if (o0) o0[o] = qv;
       if (o1) o1[o] = sqrtf(w1 * w1 + w2 * w2 + w3 * w3);
-      if constexpr (COUNT) s_in[0][t + 256 * h] = qv;   // x was read in the first pass only
+      qn[h] = qv;
+      if constexpr (COUNT) bits[t + 256 * h] = iso_bits4<float>(qv, sink.iso, 0, sink.n_iso);
       const float c = qv != qv ? neg_inf<float>() : qv;
       mn = c < mn ? c : mn;
       mx = c > mx ? c : mx;
@@ -1919,44 +1963,37 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
       }
     }
     if constexpr (COUNT) {
-      // cells t and t + 256 (t < 87); corners loaded once
+      // cells t and t + 256 (t < 87); node words in natural order
       constexpr int NC = 343;
-      float cv[2][8];
+      int n0[2];
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const int cc = t + 256 * r < NC ? t + 256 * r : t;
-        const int n0 = cc % 7 + 8 * ((cc / 7) % 7) + 64 * (cc / 49);
-#pragma unroll
-        for (int vtx = 0; vtx < 8; ++vtx)
-          cv[r][vtx] = s_in[0][n0 + (vtx & 1) + 8 * ((vtx >> 1) & 1) + 64 * (vtx >> 2)];
+        n0[r] = cc % 7 + 8 * ((cc / 7) % 7) + 64 * (cc / 49);
       }
-      const uint8_t* ntri = reinterpret_cast<const uint8_t*>(s_ntri);
       const int64_t e = blockIdx.x;
-      for (int s = 0; s < sink.n_iso; ++s) {
-        const float c = sink.iso.v[s];
-        int packed = 0;   // triangles in the low 16 bits, active cells above
-        if ((mx > c) && !(mn > c)) {
+      const int n_iso = sink.n_iso;
+      for (int g = 0; g < n_iso; g += 4) {
+        const int m = n_iso - g < 4 ? n_iso - g : 4;
+        if (g > 0) {   // every read of the previous words is behind the last barrier
+#pragma unroll
+          for (int h = 0; h < 2; ++h) bits[t + 256 * h] = iso_bits4<float>(qn[h], sink.iso, g, n_iso);
+          __syncthreads();
+        }
+        bool live = false;   // (NaN nodes count as below; mn is -inf then)
+        for (int s = 0; s < m; ++s) live |= (mx > sink.iso.v[g + s]) && !(mn > sink.iso.v[g + s]);
+        int packed[4] = {0, 0, 0, 0};
+        if (live) {
 #pragma unroll
           for (int r = 0; r < 2; ++r) {
             if (t + 256 * r >= NC) continue;
-            int cs = 0;
+            const uint32_t word = cell_word<8, 64>(bits, n0[r]);
 #pragma unroll
-            for (int vtx = 7; vtx >= 0; --vtx) cs = cs + cs + (cv[r][vtx] > c);
-            packed += ntri[cs] + ((cs != 0 && cs != 255) << 16);
+            for (int s = 0; s < 4; ++s)
+              if (s < m) packed[s] += s_tab[(word >> (8 * s)) & 255];
           }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
-        if (lane == 0) s_sum[wv] = packed;
-        __syncthreads();
-        if (t == 0) {
-          const int sum = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
-          sink.cnt[(int64_t)s * sink.n_elem + e] = sum & 0xffff;
-          const int a = sum >> 16;
-          if (sink.active && a)
-            atomicAdd((unsigned long long*)&sink.active[s], (unsigned long long)a);
-        }
-        __syncthreads();
+        publish_counts<4>(packed, m, g, t, s_sum, sink.cnt, sink.n_elem, e, sink.active);
       }
     }
   }
