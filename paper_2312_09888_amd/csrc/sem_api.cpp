@@ -160,9 +160,11 @@ int sem_init(int device) {
   // host tables: D of every order in FP64 and FP32, then the case table
   size_t off64[kMaxOrder + 1], off32[kMaxOrder + 1];
   size_t bytes = 0;
+  // FP64 D of order n is followed by its even-odd halves (below)
   for (int n = 1; n <= kMaxOrder; ++n) {
+    const int ne = (n + 2) / 2;
     off64[n] = bytes;
-    bytes += align256(sizeof(double) * (n + 1) * (n + 1));
+    bytes += align256(sizeof(double) * ((n + 1) * (n + 1) + 2 * ne * ne));
   }
   for (int n = 1; n <= kMaxOrder; ++n) {
     off32[n] = bytes;
@@ -182,6 +184,22 @@ int sem_init(int device) {
     gll_basis(n, nullptr, nullptr, d);
     float* f = reinterpret_cast<float*>(host.data() + off32[n]);
     for (int q = 0; q < (n + 1) * (n + 1); ++q) f[q] = (float)d[q];
+    // even-odd halves of D (D[P-1-i][P-1-m] = -D[i][m] on the symmetric GLL
+    // nodes), P = n + 1, H = P / 2 node pairs, NE = ceil(P / 2) rows:
+    // A[i][m] = (D[i][m] + D[i][P-1-m]) / 2 for m < H and A[i][H] = D[i][H]
+    // when P is odd (the middle node); B[i][m] = (D[i][m] - D[i][P-1-m]) / 2.
+    // With e_m = g_m + g_{P-1-m} (e_H = g_H), o_m = g_m - g_{P-1-m}:
+    // (Dg)_i = A_i.e + B_i.o and (Dg)_{P-1-i} = B_i.o - A_i.e.
+    const int p = n + 1, hp = p / 2, ne = (p + 1) / 2;
+    double* a = d + p * p;
+    double* b = a + ne * ne;
+    for (int i = 0; i < ne; ++i) {
+      for (int m = 0; m < hp; ++m) {
+        a[ne * i + m] = 0.5 * (d[p * i + m] + d[p * i + p - 1 - m]);
+        b[hp * i + m] = 0.5 * (d[p * i + m] - d[p * i + p - 1 - m]);
+      }
+      if (p % 2) a[ne * i + hp] = d[p * i + hp];
+    }
   }
   build_mc_table(host.data() + off_ntri, reinterpret_cast<int8_t*>(host.data() + off_tri));
   {
