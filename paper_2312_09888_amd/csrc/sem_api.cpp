@@ -406,7 +406,7 @@ int sem_batch_plan(int n_snap, const sem_snapshot* snaps, sem_dtype dt, void* pl
     hdr->snap_begin[n] = next;
     int var = tab->tuned_variant[dt == SEM_F64 ? 0 : 1][n] - 1;
     if (!batch_variant_ok(n, dt, var)) var = batch_default_variant(n, dt);
-    const int chunk = batch_variant_chunk(var), form = batch_variant_form(var);
+    const int chunk = batch_variant_chunk(n, dt, var), form = batch_variant_form(var);
     int64_t items = 0;
     for (int i = 0; i < n_snap; ++i) {
       const sem_snapshot& sn = snaps[i];

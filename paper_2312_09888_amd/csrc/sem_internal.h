@@ -92,7 +92,7 @@ size_t batch_plan_bytes(int n_snap);
 constexpr int kBatchVariants = 6;
 enum BatchForm { kBatchChunk = 0, kBatchPencil = 1, kBatchDma7 = 2, kBatchNodeTile = 3 };
 bool batch_variant_ok(int order, sem_dtype dt, int variant);
-int batch_variant_chunk(int variant);
+int batch_variant_chunk(int order, sem_dtype dt, int variant);   // elements per work item
 int batch_variant_form(int variant);
 int batch_default_variant(int order, sem_dtype dt);
 // Launch code of a plan: 3 bits per order at bit 3N, 0 = no snapshot of

@@ -314,18 +314,21 @@ qcrit_tile(const double* __restrict__ dmat, const T* __restrict__ x, const T* __
 // P LDS reads of the field and P of D per output.  LDS tiles use a padded
 // row stride of P + 1.
 
-template <int N>
+template <int N, int E = 1>
 struct Pen {
   static constexpr int P = N + 1;
-  static constexpr int NP = P * P;        // lines per direction
-  static constexpr int LT = 64 * ((NP + 63) / 64);  // threads per half
-  static constexpr int TH = 2 * LT;       // threads per element
+  static constexpr int NP = P * P;        // lines per direction and element
+  static constexpr int LE = E * NP;       // lines per half (E elements)
+  static constexpr int LT = 64 * ((LE + 63) / 64);  // threads per half
+  static constexpr int TH = 2 * LT;       // threads per workgroup
   static constexpr int H0 = (P + 1) / 2;  // nodes per thread and half
   static constexpr int RS = P + 1;        // LDS row stride (j)
   static constexpr int SS = P * RS;       // LDS slab stride (k)
-  static constexpr int SZ = P * SS;       // padded tile
-  static_assert(NP <= LT && TH <= 256, "one line per thread of a half");
+  static constexpr int SZ = P * SS;       // padded tile of one element
+  static_assert(LE <= LT && TH <= 1024, "one line per thread of a half");
   __device__ static constexpr int at(int i, int j, int k) { return i + RS * j + SS * k; }
+  // element of line p (lines of consecutive elements follow each other)
+  __device__ static constexpr int elem(int p) { return E == 1 ? 0 : p / NP; }
 };
 
 // Coefficient tables (D, its even-odd halves) are read through the
@@ -383,27 +386,32 @@ __device__ __forceinline__ void line_deriv_all(const double* __restrict__ d, con
 // H0 nodes.  `gf` points at the element's first value.
 // Load the owner's r-line of one field (issued early so that several
 // fields' loads are in flight at once).
+// Line p of a block of elements is the P values at gf + P p; lines from nl
+// on (past the last element) are not loaded.
 template <int N, typename T>
-__device__ __forceinline__ void pencil_load(const T* __restrict__ gf, int p, T (&f)[N + 1]) {
-  using Q = Pen<N>;
-  constexpr int P = Q::P;
-  if (p < Q::NP) {
-    const int j = p % P, k = p / P;
+__device__ __forceinline__ void pencil_load(const T* __restrict__ gf, int p, int nl,
+                                            T (&f)[N + 1]) {
+  constexpr int P = N + 1;
+  if (p < nl) {
 #pragma unroll
-    for (int m = 0; m < P; ++m) f[m] = gf[(k * P + j) * P + m];
+    for (int m = 0; m < P; ++m) f[m] = gf[p * P + m];
   }
 }
 
-template <int N, typename T>
+template <int N, int E = 1, typename T>
 __device__ __forceinline__ void pencil_pass(const T (&f)[N + 1], const double* __restrict__ d,
                                             T* __restrict__ F, T* __restrict__ S,
                                             T* __restrict__ Tt, int h, int p,
                                             T (&fr)[Pen<N>::H0], T (&fs)[Pen<N>::H0],
                                             T (&ft)[Pen<N>::H0]) {
-  using Q = Pen<N>;
+  using Q = Pen<N, E>;
   constexpr int P = Q::P, H0 = Q::H0;
-  const bool valid = p < Q::NP;
-  const int j = p % P, k = p / P;
+  const bool valid = p < Q::LE;
+  const int el = Q::elem(p), line = p - el * Q::NP;
+  F += el * Q::SZ;
+  S += el * Q::SZ;
+  Tt += el * Q::SZ;
+  const int j = line % P, k = line / P;
   if (valid) {
 #pragma unroll
     for (int ii = 0; ii < H0; ++ii) {
@@ -416,7 +424,7 @@ __device__ __forceinline__ void pencil_pass(const T (&f)[N + 1], const double* _
   }
   __syncthreads();
   if (valid) {
-    const int a = p % P, b = p / P;
+    const int a = j, b = k;
     T g[P], out[P];
     if (h == 0) {  // s-line at (i, k) = (a, b)
 #pragma unroll
@@ -445,28 +453,28 @@ __device__ __forceinline__ void pencil_pass(const T (&f)[N + 1], const double* _
   }
 }
 
-template <int N, typename T>
+template <int N, typename T, int E = 1>
 struct PencilTiles {
-  T F[Pen<N>::SZ];
-  T S[Pen<N>::SZ];
-  T Tt[Pen<N>::SZ];
-  T red[2 * Pen<N>::TH / 64];
+  T F[E * Pen<N>::SZ];
+  T S[E * Pen<N>::SZ];
+  T Tt[E * Pen<N>::SZ];
+  T red[2 * Pen<N, E>::TH / 64];
   int flag;
 };
 
 // Geometry of the owner's nodes: J^-1 from the three coordinate passes.
 // The coordinate tiles land in FX, FY, FZ (the same tile when they are not
 // needed afterwards).
-template <int N, typename T>
+template <int N, int E = 1, typename T>
 __device__ __forceinline__ bool pencil_geometry(const T (&lx)[N + 1], const T (&ly)[N + 1],
                                                 const T (&lz)[N + 1], const double* __restrict__ d,
-                                                PencilTiles<N, T>& sm, T* FX, T* FY, T* FZ,
+                                                PencilTiles<N, T, E>& sm, T* FX, T* FY, T* FZ,
                                                 int h, int p, InvJac<T> (&kk)[Pen<N>::H0]) {
   constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
   T xr[H0], xs[H0], xt[H0], yr[H0], ys[H0], yt[H0], zr[H0], zs[H0], zt[H0];
-  pencil_pass<N>(lx, d, FX, sm.S, sm.Tt, h, p, xr, xs, xt);
-  pencil_pass<N>(ly, d, FY, sm.S, sm.Tt, h, p, yr, ys, yt);
-  pencil_pass<N>(lz, d, FZ, sm.S, sm.Tt, h, p, zr, zs, zt);
+  pencil_pass<N, E>(lx, d, FX, sm.S, sm.Tt, h, p, xr, xs, xt);
+  pencil_pass<N, E>(ly, d, FY, sm.S, sm.Tt, h, p, yr, ys, yt);
+  pencil_pass<N, E>(lz, d, FZ, sm.S, sm.Tt, h, p, zr, zs, zt);
   bool ok = true;
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
@@ -489,10 +497,10 @@ derivs_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T*
   const int p = threadIdx.x % Q::LT;
   const int64_t base = (int64_t)blockIdx.x * (P * P * P);
   T lx[P], ly[P], lz[P], lf[P];
-  pencil_load<N>(x + base, p, lx);
-  pencil_load<N>(y + base, p, ly);
-  pencil_load<N>(z + base, p, lz);
-  pencil_load<N>(f + base, p, lf);
+  pencil_load<N>(x + base, p, Q::NP, lx);
+  pencil_load<N>(y + base, p, Q::NP, ly);
+  pencil_load<N>(z + base, p, Q::NP, lz);
+  pencil_load<N>(f + base, p, Q::NP, lf);
   InvJac<T> kk[H0];
   int bad = !pencil_geometry<N>(lx, ly, lz, dmat, sm, sm.F, sm.F, sm.F, h, p, kk);
   T fr[H0], fs[H0], ft[H0];
@@ -518,33 +526,34 @@ derivs_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T*
 
 // Q and |omega| at the owner's nodes; the velocity-gradient rows are folded
 // into Q = -(sum_ij A_ij A_ji)/2 and |omega|^2 as they are produced.
-template <int N, typename T>
+template <int N, int E = 1, typename T>
 __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* gz,
                                              const T* gu, const T* gv, const T* gw,
-                                             const double* __restrict__ d, PencilTiles<N, T>& sm,
-                                             T* FX, T* FY, T* FZ, int h, int p,
-                                             T (&qv)[Pen<N>::H0], T (&om)[Pen<N>::H0]) {
+                                             const double* __restrict__ d,
+                                             PencilTiles<N, T, E>& sm, T* FX, T* FY, T* FZ,
+                                             int h, int p, int nl, T (&qv)[Pen<N>::H0],
+                                             T (&om)[Pen<N>::H0]) {
   constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
   // N <= 7: all six lines are requested before any arithmetic; N = 8, 9:
   // the velocity lines are requested just before their pass (ten values a
   // line would otherwise hold 30 more registers through the geometry)
   constexpr bool kEarly = N <= 7;
   T lx[P], ly[P], lz[P], lu[P], lv[P], lw[P];
-  pencil_load<N>(gx, p, lx);
-  pencil_load<N>(gy, p, ly);
-  pencil_load<N>(gz, p, lz);
+  pencil_load<N>(gx, p, nl, lx);
+  pencil_load<N>(gy, p, nl, ly);
+  pencil_load<N>(gz, p, nl, lz);
   if constexpr (kEarly) {
-    pencil_load<N>(gu, p, lu);
-    pencil_load<N>(gv, p, lv);
-    pencil_load<N>(gw, p, lw);
+    pencil_load<N>(gu, p, nl, lu);
+    pencil_load<N>(gv, p, nl, lv);
+    pencil_load<N>(gw, p, nl, lw);
   }
   InvJac<T> kk[H0];
-  const bool ok = pencil_geometry<N>(lx, ly, lz, d, sm, FX, FY, FZ, h, p, kk);
+  const bool ok = pencil_geometry<N, E>(lx, ly, lz, d, sm, FX, FY, FZ, h, p, kk);
   T fr[H0], fs[H0], ft[H0];
   T a01[H0], a02[H0], a12[H0];
   // row 0 (u)
-  if constexpr (!kEarly) pencil_load<N>(gu, p, lu);
-  pencil_pass<N>(lu, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  if constexpr (!kEarly) pencil_load<N>(gu, p, nl, lu);
+  pencil_pass<N, E>(lu, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
     const InvJac<T>& K = kk[ii];
@@ -554,8 +563,8 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
     qv[ii] = a00 * a00;
   }
   // row 1 (v)
-  if constexpr (!kEarly) pencil_load<N>(gv, p, lv);
-  pencil_pass<N>(lv, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  if constexpr (!kEarly) pencil_load<N>(gv, p, nl, lv);
+  pencil_pass<N, E>(lv, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
     const InvJac<T>& K = kk[ii];
@@ -567,8 +576,8 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
     om[ii] = w3 * w3;
   }
   // row 2 (w)
-  if constexpr (!kEarly) pencil_load<N>(gw, p, lw);
-  pencil_pass<N>(lw, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
+  if constexpr (!kEarly) pencil_load<N>(gw, p, nl, lw);
+  pencil_pass<N, E>(lw, d, sm.F, sm.S, sm.Tt, h, p, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < H0; ++ii) {
     const InvJac<T>& K = kk[ii];
@@ -646,41 +655,138 @@ struct CountSink {
   int64_t n_elem;
 };
 
-template <int N, typename T, bool COUNT = false>
+// Ranges and counts of a workgroup of E > 1 elements: wave w takes the
+// elements w, w + waves, ...; an element's range from its lines' partial
+// (min, max) in part (both halves), its cells' cases from the node words in
+// F (one element tile after another).
+template <int N, typename T, bool COUNT, int E>
+__device__ __forceinline__ void pencil_multi_tail(int64_t e, int t, int ne,
+                                                  const T (&qv)[Pen<N>::H0], T* F,
+                                                  const T* part, T* emm, const int32_t* tab,
+                                                  T* __restrict__ qmm,
+                                                  const CountSink<T>* sink) {
+  using Q = Pen<N, E>;
+  constexpr int P = Q::P, H0 = Q::H0, NW = Q::TH / 64;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
+  for (int el = wave; el < ne; el += NW) {
+    T a = pos_inf<T>(), b = neg_inf<T>();
+    for (int q2 = lane; q2 < 2 * Q::NP; q2 += 64) {
+      const int idx = (q2 < Q::NP ? 0 : Q::LT - Q::NP) + el * Q::NP + q2;
+      a = part[idx] < a ? part[idx] : a;
+      b = part[Q::TH + idx] > b ? part[Q::TH + idx] : b;
+    }
+    a = wave_min(a);
+    b = wave_max(b);
+    if (lane == 0) {
+      if (qmm) {
+        qmm[2 * (e + el)] = a;
+        qmm[2 * (e + el) + 1] = b;
+      }
+      if constexpr (COUNT) {
+        emm[2 * el] = a;
+        emm[2 * el + 1] = b;
+      }
+    }
+  }
+  if constexpr (COUNT) {
+    constexpr int NC = N * N * N;
+    uint32_t* bits = reinterpret_cast<uint32_t*>(F);
+    const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
+    const int p = t % Q::LT;
+    const bool valid = p < ne * Q::NP;
+    const int n_iso = sink->n_iso;
+    __syncthreads();   // publishes emm
+    for (int g = 0; g < n_iso; g += 4) {
+      const int m = n_iso - g < 4 ? n_iso - g : 4;
+      if (g > 0) {
+        __syncthreads();   // every wave is done with the previous words
+        if (valid) {
+          const int el = Q::elem(p), line = p - el * Q::NP;
+          const int j = line % P, k = line / P;
+#pragma unroll
+          for (int ii = 0; ii < H0; ++ii) {
+            const int i = h * H0 + ii;
+            if (i < P)
+              bits[el * Q::SZ + Q::at(i, j, k)] = iso_bits4<T>(qv[ii], sink->iso, g, n_iso);
+          }
+        }
+        __syncthreads();
+      }
+      for (int el = wave; el < ne; el += NW) {
+        // elements outside every isovalue's range of the group have only
+        // trivial cases (NaN nodes count as below; the minimum is -inf then)
+        const T emn = emm[2 * el], emx = emm[2 * el + 1];
+        bool live = false;
+        for (int s = 0; s < m; ++s)
+          live |= (emx > sink->iso.v[g + s]) && !(emn > sink->iso.v[g + s]);
+        int packed[4] = {0, 0, 0, 0};
+        if (live) {
+          for (int c = lane; c < NC; c += 64) {
+            const int n0 = el * Q::SZ + Q::at(c % N, (c / N) % N, c / (N * N));
+            const uint32_t word = cell_word<Q::RS, Q::SS>(bits, n0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              if (s < m) packed[s] += tab[(word >> (8 * s)) & 255];
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          if (s < m) {
+            const int sum = wave_sum(packed[s]);
+            if (lane == 0) {
+              sink->cnt[(int64_t)(g + s) * sink->n_elem + e + el] = sum & 0xffff;
+              const int a = sum >> 16;
+              if (sink->active && a)
+                atomicAdd((unsigned long long*)&sink->active[g + s], (unsigned long long)a);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// One workgroup over the elements e .. e + ne - 1 (E of them at most).
+template <int N, typename T, bool COUNT = false, int E = 1>
 __device__ __forceinline__ void qcrit_pencil_elem(
     int64_t e, int t, const double* __restrict__ dmat, const T* __restrict__ x,
     const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
     const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
-    T* __restrict__ qmm, int32_t* __restrict__ status, const CountSink<T>* sink = nullptr) {
-  using Q = Pen<N>;
+    T* __restrict__ qmm, int32_t* __restrict__ status, const CountSink<T>* sink = nullptr,
+    int ne = 1) {
+  using Q = Pen<N, E>;
   constexpr int P = Q::P, H0 = Q::H0;
-  __shared__ PencilTiles<N, T> sm;
+  __shared__ PencilTiles<N, T, E> sm;
   __shared__ int32_t s_tab[COUNT ? 256 : 1];
-  __shared__ int32_t s_sum[COUNT ? 4 * Q::TH / 64 : 1];
+  __shared__ int32_t s_sum[COUNT && E == 1 ? 4 * Q::TH / 64 : 1];
+  __shared__ T s_part[E > 1 ? 2 * Q::TH : 1];   // per-thread (min, max) of Q
+  __shared__ T s_emm[E > 1 && COUNT ? 2 * E : 1];
   const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
   const int p = t % Q::LT;
   const int64_t base = e * (P * P * P);
+  const int nl = E == 1 ? Q::NP : ne * Q::NP;   // lines of elements that exist
   if constexpr (COUNT) {
     // case table, published by the barriers of the passes
     for (int c = t; c < 256; c += Q::TH) s_tab[c] = case_count_entry(c, sink->ntri[c]);
   }
   T qv[H0], ov[H0];
-  int bad = !pencil_qcrit<N>(x + base, y + base, z + base, u + base, v + base, w + base, dmat,
-                             sm, sm.F, sm.F, sm.F, h, p, qv, ov);
-  const bool valid = p < Q::NP;
+  int bad = !pencil_qcrit<N, E>(x + base, y + base, z + base, u + base, v + base, w + base,
+                                dmat, sm, sm.F, sm.F, sm.F, h, p, nl, qv, ov);
+  const bool valid = p < nl;
   T mn = pos_inf<T>(), mx = neg_inf<T>();
   if (!valid) bad = 0;
   if (valid) {
-    const int j = p % P, k = p / P;
+    const int el = Q::elem(p), line = p - el * Q::NP;
+    const int j = line % P, k = line / P;
 #pragma unroll
     for (int ii = 0; ii < H0; ++ii) {
       const int i = h * H0 + ii;
       if (i < P) {
-        const int64_t o = base + (k * P + j) * P + i;
+        const int64_t o = base + (int64_t)p * P + i;   // line p of the block, node i
         if (q) q[o] = qv[ii];
         if (om) om[o] = ov[ii];
         if constexpr (COUNT)   // F is free after the last pass
-          reinterpret_cast<uint32_t*>(sm.F)[Q::at(i, j, k)] =
+          reinterpret_cast<uint32_t*>(sm.F)[el * Q::SZ + Q::at(i, j, k)] =
               iso_bits4<T>(qv[ii], sink->iso, 0, sink->n_iso);
         const T c = qv[ii] != qv[ii] ? neg_inf<T>() : qv[ii];
         mn = c < mn ? c : mn;
@@ -688,8 +794,16 @@ __device__ __forceinline__ void qcrit_pencil_elem(
       }
     }
   }
+  if constexpr (E > 1) {
+    s_part[t] = mn;
+    s_part[Q::TH + t] = mx;
+  }
   bad = __syncthreads_or(bad);   // also publishes the Q tile
   if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  if constexpr (E > 1) {
+    pencil_multi_tail<N, T, COUNT, E>(e, t, ne, qv, sm.F, s_part, s_emm, s_tab, qmm, sink);
+    return;
+  }
   if (qmm || COUNT) {
     block_minmax<T, Q::TH>(mn, mx, sm.red);
     if (qmm && t == 0) {
@@ -742,26 +856,51 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   }
 }
 
+// Elements per workgroup of the pencil Q kernels: enough that the lines of
+// the low orders fill whole waves ((N + 1)^2 lines per element and half).
+// FP32 N = 6 and 8 stay at one: there the larger workgroup costs a wave of
+// occupancy per SIMD (143 and 129 registers) and measured slower (34.2
+// against 26.6 and 26.0 against 25.4 ps per point).
+constexpr int pencil_elems_of(int n, bool f64) {
+  constexpr int e64[kMaxOrder + 1] = {1, 16, 7, 4, 5, 7, 5, 1, 1, 1};
+  constexpr int e32[kMaxOrder + 1] = {1, 16, 7, 4, 5, 7, 1, 1, 1, 1};
+  return f64 ? e64[n] : e32[n];
+}
 template <int N, typename T>
-__global__ void __launch_bounds__(Pen<N>::TH)
+constexpr int pencil_elems() {
+  return pencil_elems_of(N, std::is_same<T, double>::value);
+}
+template <int N, typename T>
+constexpr int pencil_threads() {
+  return Pen<N, pencil_elems<N, T>()>::TH;
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__((pencil_threads<N, T>()))
 qcrit_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
              const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
              const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
-             T* __restrict__ qmm, int32_t* __restrict__ status) {
-  qcrit_pencil_elem<N, T>(blockIdx.x, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm,
-                          status);
+             T* __restrict__ qmm, int32_t* __restrict__ status, int64_t n_elem) {
+  constexpr int E = pencil_elems<N, T>();
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = n_elem - e0 < E ? (int)(n_elem - e0) : E;
+  qcrit_pencil_elem<N, T, false, E>(e0, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm,
+                                    status, nullptr, ne);
 }
 
 // Q, |omega|, range and the per-(isovalue, element) counts in one pass.
 template <int N, typename T>
-__global__ void __launch_bounds__(Pen<N>::TH)
+__global__ void __launch_bounds__((pencil_threads<N, T>()))
 qcount_pencil(const double* __restrict__ dmat, const T* __restrict__ x,
               const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
               const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q,
               T* __restrict__ om, T* __restrict__ qmm, int32_t* __restrict__ status,
               CountSink<T> sink) {
-  qcrit_pencil_elem<N, T, true>(blockIdx.x, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm,
-                                status, &sink);
+  constexpr int E = pencil_elems<N, T>();
+  const int64_t e0 = (int64_t)blockIdx.x * E;
+  const int ne = sink.n_elem - e0 < E ? (int)(sink.n_elem - e0) : E;
+  qcrit_pencil_elem<N, T, true, E>(e0, threadIdx.x, dmat, x, y, z, u, v, w, q, om, qmm,
+                                   status, &sink, ne);
 }
 
 // ---------------------------------------------------------------------------
@@ -2149,17 +2288,18 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
 }
 
 // One instantiation per (order, precision, form), so that no form's register
-// demand limits another's occupancy.  kBatchNodeTile, kBatchPencil and
-// kBatchDma7 run the per-element bodies of qcrit_tile, qcrit_pencil and
-// qcount_dma7 on one element per work item.
-template <int N, int FORM>
+// demand limits another's occupancy.  kBatchNodeTile and kBatchDma7 run the
+// per-element bodies of qcrit_tile and qcount_dma7 on one element per work
+// item, kBatchPencil the body of qcrit_pencil on its workgroup's elements.
+template <int N, typename T, int FORM>
 constexpr int batch_threads() {
-  return FORM == kBatchPencil ? Pen<N>::TH : FORM == kBatchNodeTile ? Shape<N>::kNodeThreads
-                                                                    : kBatchThreads;
+  return FORM == kBatchPencil     ? pencil_threads<N, T>()
+         : FORM == kBatchNodeTile ? Shape<N>::kNodeThreads
+                                  : kBatchThreads;
 }
 
 template <int N, typename T, int FORM>
-__global__ void __launch_bounds__((batch_threads<N, FORM>()))
+__global__ void __launch_bounds__((batch_threads<N, T, FORM>()))
 qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ snaps,
             int32_t* __restrict__ status) {
   const int s0 = hdr->snap_begin[N], s1 = hdr->snap_begin[N + 1];
@@ -2216,7 +2356,11 @@ qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ s
     } else if constexpr (FORM == kBatchNodeTile) {
       qcrit_tile_elem<N, T>(e0, t, dmat, f0, f1, f2, f3, f4, f5, oq, oom, oqmm, status);
     } else if constexpr (FORM == kBatchPencil) {
-      qcrit_pencil_elem<N, T>(e0, t, dmat, f0, f1, f2, f3, f4, f5, oq, oom, oqmm, status);
+      constexpr int E = pencil_elems<N, T>();   // the item's chunk
+      const int64_t left = n_elem - e0;
+      const int ne = (int)(left < E ? left : E);
+      qcrit_pencil_elem<N, T, false, E>(e0, t, dmat, f0, f1, f2, f3, f4, f5, oq, oom, oqmm,
+                                        status, nullptr, ne);
     } else {
       static_assert(N == 7 && std::is_same<T, double>::value, "direct-to-LDS form: N = 7, FP64");
       qcount_dma7_elem<false>(e0, t, 0, eo, f0, f1, f2, f3, f4, f5, oq, oom, oqmm, 0,
@@ -2317,10 +2461,11 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
       // pencil form wherever it is the faster one: every order in FP32,
       // N <= 7 in FP64 (at N = 8, 9 its FP64 registers spill)
       if constexpr (N <= 7 || !std::is_same<T, double>::value) {
-        hipExtLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)n_elem), dim3(Pen<N>::TH),
-                              0, s, pt.start, pt.stop, 0, d, (const T*)x, (const T*)y, (const T*)z,
-                              (const T*)u, (const T*)v, (const T*)w, (T*)q, (T*)om, (T*)qmm,
-                              status);
+        constexpr int E = (pencil_elems<N, T>());
+        hipExtLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)((n_elem + E - 1) / E)),
+                              dim3(pencil_threads<N, T>()), 0, s, pt.start, pt.stop, 0, d,
+                              (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
+                              (const T*)w, (T*)q, (T*)om, (T*)qmm, status, n_elem);
       } else {
         hipExtLaunchKernelGGL((qcrit_tile<N, T>), dim3((unsigned)n_elem),
                               dim3(Shape<N>::kNodeThreads), 0, s, pt.start, pt.stop, 0, d,
@@ -2510,8 +2655,10 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
         if (active)
           hipLaunchKernelGGL(fill_i64, dim3(1), dim3(64), 0, s, active, n_iso, (int64_t)0);
         const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
-        hipExtLaunchKernelGGL((qcount_pencil<N, T>), dim3((unsigned)n_elem), dim3(Pen<N>::TH),
-                              0, s, pt.start, pt.stop, 0, d, (const T*)x, (const T*)y,
+        constexpr int E = (pencil_elems<N, T>());
+        hipExtLaunchKernelGGL((qcount_pencil<N, T>), dim3((unsigned)((n_elem + E - 1) / E)),
+                              dim3(pencil_threads<N, T>()), 0, s, pt.start, pt.stop, 0, d,
+                              (const T*)x, (const T*)y,
                               (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q,
                               (T*)om, (T*)qmm, status, sink);
         phase_done(pt);
@@ -2563,7 +2710,10 @@ size_t batch_plan_bytes(int n_snap) {
   return 256 + (((size_t)n_snap * sizeof(BatchSnap) + 255) & ~size_t(255));
 }
 
-int batch_variant_chunk(int variant) { return variant < 3 ? 1 << variant : 1; }
+int batch_variant_chunk(int order, sem_dtype dt, int variant) {
+  if (variant < 3) return 1 << variant;
+  return batch_variant_form(variant) == kBatchPencil ? pencil_elems_of(order, dt == SEM_F64) : 1;
+}
 
 int batch_variant_form(int variant) {
   static const int form[kBatchVariants] = {kBatchChunk, kBatchChunk, kBatchChunk, kBatchPencil,
@@ -2576,7 +2726,7 @@ bool batch_variant_ok(int order, sem_dtype dt, int variant) {
   if (order < 1 || order > kMaxOrder) return false;
   const int p3 = (order + 1) * (order + 1) * (order + 1);
   switch (batch_variant_form(variant)) {
-    case kBatchChunk: return batch_variant_chunk(variant) * p3 <= kBatchTile / 6;
+    case kBatchChunk: return batch_variant_chunk(order, dt, variant) * p3 <= kBatchTile / 6;
     case kBatchPencil: return true;
     case kBatchNodeTile: return true;
     default: return order == 7 && dt == SEM_F64;
@@ -2603,8 +2753,9 @@ const void* batch_kernel_nt(int form) {
                              : nullptr;
 }
 
-int batch_threads_of(int n, int form) {
-  if (form == kBatchPencil) return 128 * (((n + 1) * (n + 1) + 63) / 64);
+int batch_threads_of(int n, bool f64, int form) {
+  if (form == kBatchPencil)
+    return 128 * ((pencil_elems_of(n, f64) * (n + 1) * (n + 1) + 63) / 64);
   if (form == kBatchNodeTile) return (((n + 1) * (n + 1) * (n + 1) + 63) / 64) * 64;
   return kBatchThreads;
 }
@@ -2665,7 +2816,7 @@ hipError_t launch_qcrit_batch(sem_dtype dt, const void* plan, unsigned launch_co
     if (!fn) return hipErrorInvalidValue;
     hipEvent_t a = n == first ? e0 : nullptr, b = n == last ? e1 : nullptr;
     void* args[] = {const_cast<BatchHeader**>(&hdr), const_cast<BatchSnap**>(&snaps), &status};
-    const int threads = batch_threads_of(n, form);
+    const int threads = batch_threads_of(n, dt == SEM_F64, form);
     const hipError_t err = hipExtLaunchKernel(fn, dim3(batch_grid(fn, threads, cu_count)),
                                               dim3(threads), args, 0, s, a, b, 0);
     if (err != hipSuccess) return err;

@@ -82,6 +82,18 @@ def test_extract_matches_oracle(n, dt):
         _check_against_oracle(arrs, [-0.9, 0.0, 0.7], dt, n)
 
 
+@pytest.mark.parametrize("n", [2, 3, 5, 7, 9])
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_extract_many_isovalues(n, dt):
+    # nine isovalues: the fused counts take them four at a time (4 + 4 + 1),
+    # on the one- and several-element workgroups alike; 7 and 1 elements
+    # leave partial workgroups
+    isos = list(np.linspace(-1.2, 1.0, 9))
+    for shape, seed in (((7, 1, 1), 11), ((1, 1, 1), 12)):
+        arrs = [a.astype(dt) for a in _inputs(n, shape, seed)]
+        _check_against_oracle(arrs, isos, dt, n)
+
+
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_extract_equals_qcrit_then_isosurface(dt):
     n = 7

@@ -165,7 +165,7 @@ def test_mixed_taylor_green_case_and_count_mismatch(mode):
 def test_mixed_extract_equals_qcrit_then_isosurface(mode):
     arrs = _f32(W.tgv_config(7, shape=(4, 3, 2)))
     t = [dev(a) for a in arrs]
-    isos = [0.05, 0.1, 0.3]
+    isos = [0.02, 0.05, 0.1, 0.2, 0.3, 0.4]   # counted four at a time: 4 + 2
     r = sem.extract(*t, isos, precision=mode)
     q, _, mm = sem.qcrit(*t, precision=mode)
     assert torch.equal(r["q"], q)
