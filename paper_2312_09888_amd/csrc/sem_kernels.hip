@@ -860,9 +860,11 @@ __device__ __forceinline__ void qcrit_pencil_elem(
 // the low orders fill whole waves ((N + 1)^2 lines per element and half).
 // FP32 N = 6 and 8 stay at one: there the larger workgroup costs a wave of
 // occupancy per SIMD (143 and 129 registers) and measured slower (34.2
-// against 26.6 and 26.0 against 25.4 ps per point).
+// against 26.6 and 26.0 against 25.4 ps per point). FP64 N = 5, 6 (over 200
+// registers) keep workgroups of at most four waves: with eight, the batched
+// kernel's registers spill.
 constexpr int pencil_elems_of(int n, bool f64) {
-  constexpr int e64[kMaxOrder + 1] = {1, 16, 7, 4, 5, 7, 5, 1, 1, 1};
+  constexpr int e64[kMaxOrder + 1] = {1, 16, 7, 4, 5, 3, 1, 1, 1, 1};
   constexpr int e32[kMaxOrder + 1] = {1, 16, 7, 4, 5, 7, 1, 1, 1, 1};
   return f64 ? e64[n] : e32[n];
 }
