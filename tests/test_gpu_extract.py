@@ -114,6 +114,56 @@ def test_extract_equals_qcrit_then_isosurface(dt):
         off += c
 
 
+def test_extract_graph_replays_match_eager():
+    # the fused step captured once and replayed, with eager work that
+    # clobbers every output between the replays: each replay equals the
+    # eager call bit for bit
+    n = 7
+    t = [dev(a) for a in W.tgv_config(n)]
+    isos = [0.1, -0.3, 0.45]
+    e, k = t[0].shape[0], len(isos)
+    ws = torch.empty(sem.extract_workspace_bytes(e, n, k, sem.SEM_F64), dtype=torch.uint8,
+                     device=DEV)
+    cnt = torch.zeros(k, dtype=torch.int64, device=DEV)
+    act = torch.zeros(k, dtype=torch.int64, device=DEV)
+    sem.extract_into(*t, isos, [None] * k, cnt, ws)
+    torch.cuda.synchronize()
+    tris = [torch.empty((c, 3, 3), dtype=torch.float64, device=DEV) for c in cnt.tolist()]
+    q, om = torch.empty_like(t[0]), torch.empty_like(t[0])
+    mm = torch.empty((e, 2), dtype=torch.float64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+
+    def step():
+        sem.extract_into(*t, isos, tris, cnt, ws, q=q, omega_mag=om, minmax=mm, active=act,
+                         status=st)
+
+    step()
+    torch.cuda.synchronize()
+    outs = [q, om, mm, cnt, act] + tris
+    eager = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            if o.is_floating_point():
+                o.fill_(float("nan"))
+            else:
+                o.zero_()
+        ws.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, want in zip(outs, eager):
+            assert torch.equal(o, want), rep
+    assert int(st.item()) == 0
+
+
 def test_extract_overflow_per_isovalue_and_count_only():
     n = 7
     t = [dev(a) for a in W.tgv_config(n)]

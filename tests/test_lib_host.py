@@ -317,3 +317,16 @@ def test_compression_entry_points_reject_bad_arguments():
                              FAKE, FAKE, 8, None, None) == _lib.SEM_ERR_WORKSPACE
     assert L.sem_modal_compress(4, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, None, None,
                                 None, FAKE, 1 << 30, None) == _lib.SEM_ERR_ARG   # some recon
+
+
+def test_bench_finds_committed_profile_summaries():
+    # bench.py reads the traffic and matrix-core summaries it reports from
+    # profiles/, named for the kernel without its template arguments
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    path = bench.traffic_file(bench.q_kernel_name("f64"), "f64")
+    assert os.path.basename(path) == "qcount_dma7_channel65536_f64_traffic.json"
+    assert os.path.exists(path)
+    assert os.path.exists(bench.MFMA_FILE)
