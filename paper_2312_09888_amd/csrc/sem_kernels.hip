@@ -1378,19 +1378,44 @@ __device__ __forceinline__ void eo_pair(const double* __restrict__ eo, int i,
   hi = R - P;
 }
 
+// A lane's tile offsets in the swizzled layout, the same for every field:
+// its r-line's four 16-byte chunks and the eight nodes of its s-line (waves
+// 0, 1) or t-line (waves 2, 3).  Computed once per element and held in
+// registers (the swizzle costs several instructions per offset).
+struct Dma7Lane {
+  int r[4];
+  int g[8];
+};
+__device__ __forceinline__ Dma7Lane dma7_lane(int h, int p) {
+  const int j = p & 7, k = p >> 3;
+  Dma7Lane L;
+#pragma unroll
+  for (int ip = 0; ip < 4; ++ip) {
+    L.r[ip] = 2 * dma7::slot(k, j, ip);
+    asm volatile("" : "+v"(L.r[ip]));
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    L.g[m] = h < 2 ? dma7::at(j, m, k) : dma7::at(j, k, m);
+    asm volatile("" : "+v"(L.g[m]));
+  }
+  return L;
+}
+
 // One field with four waves: wave h owns nodes i = h and 7 - h of r-line
 // (j, k) = lane; waves 0, 1 differentiate s-lines, waves 2, 3 t-lines, each
 // the output pairs (r, 7 - r) for r = 2(h&1) and 2(h&1) + 1.
 __device__ __forceinline__ void dma_pass4(const double* __restrict__ raw,
                                           const double* __restrict__ eo, double* __restrict__ S,
                                           double* __restrict__ Tt, int h, int p,
-                                          double (&fr)[2], double (&fs)[2], double (&ft)[2]) {
+                                          const Dma7Lane& L, double (&fr)[2], double (&fs)[2],
+                                          double (&ft)[2]) {
   using Q = Pen<7>;
   const int j = p & 7, k = p >> 3;
   double f[8], e[4], o[4];
 #pragma unroll
   for (int ip = 0; ip < 4; ++ip) {
-    const double2 v = *reinterpret_cast<const double2*>(raw + 2 * dma7::slot(k, j, ip));
+    const double2 v = *reinterpret_cast<const double2*>(raw + L.r[ip]);
     f[2 * ip] = v.x;
     f[2 * ip + 1] = v.y;
   }
@@ -1398,13 +1423,10 @@ __device__ __forceinline__ void dma_pass4(const double* __restrict__ raw,
   eo_pair(eo, h, e, o, fr[0], fr[1]);
   double g[8], out[4];
   const int r0 = 2 * (h & 1);
-  if (h < 2) {   // s-line at (i, k) = (j, k) of this lane's index
+  // s-line at (i, k) = (j, k) of this lane's index (h < 2), else t-line at
+  // (i, j) = (j, k)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, m, k)];
-  } else {       // t-line at (i, j) = (j, k) of this lane's index
-#pragma unroll
-    for (int m = 0; m < 8; ++m) g[m] = raw[dma7::at(j, k, m)];
-  }
+  for (int m = 0; m < 8; ++m) g[m] = raw[L.g[m]];
   eo_split(g, e, o);
   eo_pair(eo, r0, e, o, out[0], out[1]);
   eo_pair(eo, r0 + 1, e, o, out[2], out[3]);
@@ -1494,9 +1516,10 @@ __device__ __forceinline__ void qcount_dma7_elem(
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(3));
   barrier_after_wait();
   double xr[2], xs[2], xt[2], yr[2], ys[2], yt[2], zr[2], zs[2], zt[2];
-  dma_pass4(s_xyz[0], eo, s_S, s_T, h, p, xr, xs, xt);
-  dma_pass4(s_xyz[1], eo, s_S, s_T, h, p, yr, ys, yt);
-  dma_pass4(s_xyz[2], eo, s_S, s_T, h, p, zr, zs, zt);
+  const Dma7Lane lane_off = dma7_lane(h, p);
+  dma_pass4(s_xyz[0], eo, s_S, s_T, h, p, lane_off, xr, xs, xt);
+  dma_pass4(s_xyz[1], eo, s_S, s_T, h, p, lane_off, yr, ys, yt);
+  dma_pass4(s_xyz[2], eo, s_S, s_T, h, p, lane_off, zr, zs, zt);
   InvJac<double> kk[2];
   int bad = 0;
 #pragma unroll
@@ -1511,7 +1534,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
   barrier_after_wait();
   double fr[2], fs[2], ft[2], a01[2], a02[2], a12[2], qv[2], ov[2];
-  dma_pass4(s_uvw[0], eo, s_S, s_T, h, p, fr, fs, ft);
+  dma_pass4(s_uvw[0], eo, s_S, s_T, h, p, lane_off, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii) {
     const InvJac<double>& K = kk[ii];
@@ -1521,7 +1544,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
     qv[ii] = a00 * a00;
     pin(qv[ii]); pin(a01[ii]); pin(a02[ii]);
   }
-  dma_pass4(s_uvw[1], eo, s_S, s_T, h, p, fr, fs, ft);
+  dma_pass4(s_uvw[1], eo, s_S, s_T, h, p, lane_off, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii) {
     const InvJac<double>& K = kk[ii];
@@ -1533,7 +1556,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
     ov[ii] = w3 * w3;
     pin(qv[ii]); pin(ov[ii]); pin(a12[ii]);
   }
-  dma_pass4(s_uvw[2], eo, s_S, s_T, h, p, fr, fs, ft);
+  dma_pass4(s_uvw[2], eo, s_S, s_T, h, p, lane_off, fr, fs, ft);
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii) {
     const InvJac<double>& K = kk[ii];
