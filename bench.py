@@ -4,10 +4,11 @@
 One step = the whole extraction path over one synthetic snapshot already
 resident in HBM: one sem_extract call (Q, |omega|, per-element Q range, and
 the cull / classify / scan-compact / emit of the triangles of every
-isovalue, fused in a single pass).  The timed steps replay the step's
-kernels captured once in a HIP graph (one launch per step); the same steps
-launched eagerly, and the same work as two calls (sem_qcrit, then
-sem_isosurface), are timed beside them for comparison.  Workload: the turbulent-channel snapshot -- 64 x 32 x 32 = 65,536
+isovalue, fused in a single pass).  The K timed steps run as HIP graphs
+(the steps' kernels captured once, up to 100 steps per graph, each graph
+replayed once); the same steps launched eagerly, and the same work as two
+calls (sem_qcrit, then sem_isosurface), are timed beside them for
+comparison.  Workload: the turbulent-channel snapshot -- 64 x 32 x 32 = 65,536
 order-7 hexahedra (33,554,432 GLL points), tanh wall stretching (beta = 2),
 parabolic mean plus a seeded random-phase k^-5/3 velocity field -- with Q
 isosurfaces at the 90th, 95th and 99th percentiles of Q.
@@ -265,32 +266,40 @@ def main():
     log(args, f"eager {args.steps} steps: {ms_step:.4f} ms/step (host enqueue {host_ms:.4f} "
               "ms/step)")
 
-    # the timed steps (the headline figure): the step's kernels captured once
-    # in a HIP graph, one replay per step.  Eager steps leave the GPU idle
-    # whenever the host is slow to launch (now and then about 1 ms per step
-    # on the same box, against 0.04 ms), which the single graph launch per
-    # step does not.
-    graph = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(graph, stream=side):
-            step()
-    torch.cuda.current_stream().wait_stream(side)
-    for _ in range(3):
-        graph.replay()
+    # the timed steps (the headline figure): the K steps' kernels captured
+    # in HIP graphs of up to 100 steps each and replayed once.  Eager steps
+    # leave the GPU idle whenever the host is slow to launch (now and then
+    # about 1 ms per step on the same box, against 0.04 ms); one replay per
+    # step still adds a gap per replay.
+    def capture(m):
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                for _ in range(m):
+                    step()
+        torch.cuda.current_stream().wait_stream(side)
+        return g
+
+    per_graph = min(args.steps, 100)
+    graphs = [capture(per_graph)] * (args.steps // per_graph)
+    if args.steps % per_graph:
+        graphs.append(capture(args.steps % per_graph))
+    for g in set(graphs):
+        g.replay()
     torch.cuda.synchronize()
     t_begin.record()
-    for _ in range(args.steps):
-        graph.replay()
+    for g in graphs:
+        g.replay()
     t_end.record()
     torch.cuda.synchronize()
     ms_graph = t_begin.elapsed_time(t_end) / args.steps
     if int(status.item()) or cnt.cpu().tolist() != counts:
         print("graph replays changed the status or the triangle counts", file=sys.stderr)
         sys.exit(1)
-    log(args, f"timed {args.steps} graph replays: {ms_graph:.4f} ms/step")
-    del graph
+    log(args, f"timed {args.steps} steps in graph replays: {ms_graph:.4f} ms/step")
+    del graphs
 
     # the same path as two calls (sem_qcrit, then sem_isosurface), for comparison
     iws = torch.empty(sem.workspace_bytes(n_elem, n, k_iso), dtype=torch.uint8, device=devn)
@@ -356,7 +365,8 @@ def main():
         },
         "roofline": roof,
         "phase_ms": {k: round(v, 5) for k, v in phase_ms.items() if v},
-        "launch": "one HIP graph replay per step (the step's kernels captured once)",
+        "launch": "HIP graphs of up to 100 steps (the steps' kernels captured once), "
+                  "each replayed once",
         "eager_ms_per_step": round(ms_step, 5),
         "ms_per_step_with_phase_timing": round(ms_phased, 5),
         "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
