@@ -141,26 +141,31 @@ def test_extract_graph_replays_match_eager():
     torch.cuda.synchronize()
     outs = [q, om, mm, cnt, act] + tris
     eager = [o.clone() for o in outs]
-    g = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(g, stream=side):
-            step()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
+    graphs = []
+    for m in (1, 3):   # one step per graph, and three steps in one graph
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                for _ in range(m):
+                    step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graphs.append(g)
     for rep in range(3):
-        for o in outs:
-            if o.is_floating_point():
-                o.fill_(float("nan"))
-            else:
-                o.zero_()
-        ws.zero_()
-        torch.cuda.synchronize()
-        g.replay()
-        torch.cuda.synchronize()
-        for o, want in zip(outs, eager):
-            assert torch.equal(o, want), rep
+        for g in graphs:
+            for o in outs:
+                if o.is_floating_point():
+                    o.fill_(float("nan"))
+                else:
+                    o.zero_()
+            ws.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for o, want in zip(outs, eager):
+                assert torch.equal(o, want), rep
     assert int(st.item()) == 0
 
 
