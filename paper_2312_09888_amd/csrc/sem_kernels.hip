@@ -183,6 +183,24 @@ __device__ __forceinline__ bool invert_jacobian(T xr, T xs, T xt, T yr, T ys, T 
   return det > T(0);
 }
 
+// The adjugate of J (det J times J^-1, same layout as InvJac) and 1 / det J.
+__device__ __forceinline__ bool adjugate_jacobian(double xr, double xs, double xt, double yr,
+                                                  double ys, double yt, double zr, double zs,
+                                                  double zt, InvJac<double>& k, double& inv) {
+  k.rx = ys * zt - yt * zs;
+  k.sx = yt * zr - yr * zt;
+  k.tx = yr * zs - ys * zr;
+  const double det = xr * k.rx + xs * k.sx + xt * k.tx;
+  inv = 1.0 / det;
+  k.ry = xt * zs - xs * zt;
+  k.rz = xs * yt - xt * ys;
+  k.sy = xr * zt - xt * zr;
+  k.sz = xt * yr - xr * yt;
+  k.ty = xs * zr - xr * zs;
+  k.tz = xr * ys - xs * yr;
+  return det > 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // gradient / Q-criterion: one workgroup per element, tiles staged in LDS
 // ---------------------------------------------------------------------------
@@ -1520,16 +1538,19 @@ __device__ __forceinline__ void qcount_dma7_elem(
   dma_pass4(s_xyz[0], eo, s_S, s_T, h, p, lane_off, xr, xs, xt);
   dma_pass4(s_xyz[1], eo, s_S, s_T, h, p, lane_off, yr, ys, yt);
   dma_pass4(s_xyz[2], eo, s_S, s_T, h, p, lane_off, zr, zs, zt);
+  // the chain rule runs on the adjugate of J (det J times J^-1); Q takes
+  // the factor 1 / det^2 and |omega| the factor 1 / |det| once per node
   InvJac<double> kk[2];
+  double inv[2];
   int bad = 0;
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii)
-    bad |= !invert_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii],
-                            zt[ii], kk[ii]);
+    bad |= !adjugate_jacobian(xr[ii], xs[ii], xt[ii], yr[ii], ys[ii], yt[ii], zr[ii], zs[ii],
+                              zt[ii], kk[ii], inv[ii]);
 #pragma unroll
   for (int ii = 0; ii < 2; ++ii) {
     pin(kk[ii].rx); pin(kk[ii].ry); pin(kk[ii].rz); pin(kk[ii].sx); pin(kk[ii].sy);
-    pin(kk[ii].sz); pin(kk[ii].tx); pin(kk[ii].ty); pin(kk[ii].tz);
+    pin(kk[ii].sz); pin(kk[ii].tx); pin(kk[ii].ty); pin(kk[ii].tz); pin(inv[ii]);
   }
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
   barrier_after_wait();
@@ -1563,9 +1584,10 @@ __device__ __forceinline__ void qcount_dma7_elem(
     const double a20 = fr[ii] * K.rx + fs[ii] * K.sx + ft[ii] * K.tx;
     const double a21 = fr[ii] * K.ry + fs[ii] * K.sy + ft[ii] * K.ty;
     const double a22 = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
-    qv[ii] = -0.5 * (qv[ii] + a22 * a22 + 2.0 * (a02[ii] * a20 + a12[ii] * a21));
+    qv[ii] = -0.5 * (qv[ii] + a22 * a22 + 2.0 * (a02[ii] * a20 + a12[ii] * a21)) *
+             (inv[ii] * inv[ii]);
     const double w1 = a21 - a12[ii], w2 = a02[ii] - a20;
-    ov[ii] = sqrt(ov[ii] + w1 * w1 + w2 * w2);
+    ov[ii] = sqrt(ov[ii] + w1 * w1 + w2 * w2) * fabs(inv[ii]);
   }
   const int j = p & 7, k = p >> 3;
   // Q and |omega| go out through LDS tiles (free after the u and v passes):
