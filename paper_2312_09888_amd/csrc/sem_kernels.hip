@@ -1070,9 +1070,12 @@ __device__ __forceinline__ int block_count_prefix(int nt, int32_t* s_wave, int* 
 // running prefix; then thread v computes vertex v of that list.  Every lane
 // does the same amount of work however unevenly the triangles fall on the
 // cells, and consecutive lanes write consecutive vertices.  `node(i, j, k)`
-// maps a node to its tile index.  Returns the element's triangle count.
-template <int N, int TH, typename T, class NodeFn>
-__device__ __forceinline__ int emit_element(T c, NodeFn node, const T* __restrict__ ft,
+// maps a node to its index in the field tile ft, `cnode(i, j, k)` to its
+// index in the coordinate arrays sx, sy, sz (a tile in LDS, or the
+// element's values in global memory).  Returns the element's triangle count.
+template <int N, int TH, typename T, class NodeFn, class CoordFn>
+__device__ __forceinline__ int emit_element(T c, NodeFn node, CoordFn cnode,
+                                            const T* __restrict__ ft,
                                             const T* __restrict__ sx, const T* __restrict__ sy,
                                             const T* __restrict__ sz,
                                             const uint8_t* __restrict__ s_ntri,
@@ -1114,16 +1117,17 @@ __device__ __forceinline__ int emit_element(T c, NodeFn node, const T* __restric
     const int v0 = edge_lo(edge);
     const int ax = edge >> 2;
     const int a0 = ci + (v0 & 1), b0 = cj + ((v0 >> 1) & 1), c0 = ck + (v0 >> 2);
-    const int lo = node(a0, b0, c0);
-    const int hi = node(a0 + (ax == 0), b0 + (ax == 1), c0 + (ax == 2));
+    const int a1 = a0 + (ax == 0), b1 = b0 + (ax == 1), c1 = c0 + (ax == 2);
+    const int lo = node(a0, b0, c0), hi = node(a1, b1, c1);
+    const int clo = cnode(a0, b0, c0), chi = cnode(a1, b1, c1);
     T* o = out + g * 9 + 3 * vtx;
     {
 #pragma clang fp contract(off)
       const T f0 = ft[lo], f1 = ft[hi];
       const T tt = (c - f0) / (f1 - f0);
-      o[0] = sx[lo] + tt * (sx[hi] - sx[lo]);
-      o[1] = sy[lo] + tt * (sy[hi] - sy[lo]);
-      o[2] = sz[lo] + tt * (sz[hi] - sz[lo]);
+      o[0] = sx[clo] + tt * (sx[chi] - sx[clo]);
+      o[1] = sy[clo] + tt * (sy[chi] - sy[clo]);
+      o[2] = sz[clo] + tt * (sz[chi] - sz[clo]);
     }
     if (keys)
       keys[g * 3 + vtx] = (uint64_t)(key_base + a0 + P * (b0 + P * c0)) * 3u + (uint64_t)ax;
@@ -1258,7 +1262,8 @@ iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
       dst = out.ptr[s];
       cap = out.cap[s];
     }
-    emit_element<N, TH>(iso.v[s], StridedNode<P, P * P>{}, sf, sx, sy, sz, s_ntri, s_tri,
+    emit_element<N, TH>(iso.v[s], StridedNode<P, P * P>{}, StridedNode<P, P * P>{}, sf, sx, sy,
+                        sz, s_ntri, s_tri,
                         s_case, s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys,
                         base);
   }
@@ -1736,10 +1741,17 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
             const int64_t* __restrict__ offs, uint64_t* __restrict__ keys) {
   constexpr int P = N + 1, NP = P * P * P, NC = N * N * N;
   constexpr bool SWZ = N == 7 && std::is_same<T, double>::value;
+  // The coordinate tiles are staged in LDS too, except for FP32 at N = 9,
+  // which reads the coordinates where the vertices need them (edge
+  // endpoints only, through the caches) and so needs 16 instead of 28 KB of
+  // LDS. Measured: staged is faster for FP64 N = 7 (0.319 against 0.379 ms)
+  // and FP32 N = 7 (the FP32 step 0.679 against 0.712 ms); reading made the
+  // FP32 batched step (orders 5, 7, 9) 11.90 instead of 12.20 ms.
+  constexpr bool XYZ = std::is_same<T, double>::value || N <= 7;
   __shared__ __attribute__((aligned(16))) T s_f[NP];
-  __shared__ __attribute__((aligned(16))) T s_x[NP];
-  __shared__ __attribute__((aligned(16))) T s_y[NP];
-  __shared__ __attribute__((aligned(16))) T s_z[NP];
+  __shared__ __attribute__((aligned(16))) T s_x[XYZ ? NP : 1];
+  __shared__ __attribute__((aligned(16))) T s_y[XYZ ? NP : 1];
+  __shared__ __attribute__((aligned(16))) T s_z[XYZ ? NP : 1];
   static_assert(256 + 256 * kMcMaxTri * 3 == 4096, "tables fill one 4 KiB block");
   __shared__ uint4 s_tab[256];     // triangle counts (256 B), then the case table
   __shared__ uint8_t s_case[NC];
@@ -1756,7 +1768,7 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
   if (!any) return;
   const int64_t base = e * NP;
   // the two tables (one 4 KiB block: counts, then the case table) and the
-  // four tiles all arrive by direct loads before the one wait below
+  // tiles arrive by direct loads before the one wait below
   lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * (64 * h + p),
              reinterpret_cast<double*>(s_tab) + 128 * h);
   lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * (64 * (h + 2) + p),
@@ -1768,10 +1780,15 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
     dma_tile(z + base, s_z, h, p);
   } else {
     dma_tile_natural<N>(field + base, s_f, h, p);
-    dma_tile_natural<N>(x + base, s_x, h, p);
-    dma_tile_natural<N>(y + base, s_y, h, p);
-    dma_tile_natural<N>(z + base, s_z, h, p);
+    if constexpr (XYZ) {
+      dma_tile_natural<N>(x + base, s_x, h, p);
+      dma_tile_natural<N>(y + base, s_y, h, p);
+      dma_tile_natural<N>(z + base, s_z, h, p);
+    }
   }
+  const T* gx = XYZ ? s_x : x + base;
+  const T* gy = XYZ ? s_y : y + base;
+  const T* gz = XYZ ? s_z : z + base;
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
   barrier_after_wait();
   for (int s = 0; s < n_iso; ++s) {
@@ -1786,11 +1803,12 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
       cap = out.cap[s];
     }
     if constexpr (SWZ)
-      emit_element<7, 128>(iso.v[s], DmaNode{}, s_f, s_x, s_y, s_z, s_ntri, s_tri, s_case,
-                           s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys, base);
+      emit_element<7, 128>(iso.v[s], DmaNode{}, DmaNode{}, s_f, gx, gy, gz, s_ntri, s_tri,
+                           s_case, s_desc, s_wave, dst, g, cap, out.per_iso ? nullptr : keys,
+                           base);
     else
-      emit_element<N, 128>(iso.v[s], StridedNode<P, P * P>{}, s_f, s_x, s_y, s_z, s_ntri,
-                           s_tri, s_case, s_desc, s_wave, dst, g, cap,
+      emit_element<N, 128>(iso.v[s], StridedNode<P, P * P>{}, StridedNode<P, P * P>{}, s_f,
+                           gx, gy, gz, s_ntri, s_tri, s_case, s_desc, s_wave, dst, g, cap,
                            out.per_iso ? nullptr : keys, base);
   }
 }
