@@ -646,7 +646,8 @@ def autotune(order, dtype_code=SEM_F64, device=None):
     """Measure the batched kernel's variants for (order, dtype); returns
     (chosen variant, [ms of variants 0..5], -1 where not applicable).
     Variants 0, 1, 2: LDS-tile form with 1, 2, 4 elements per work item;
-    3: register-pencil form (N <= 7); 4: direct-to-LDS form (N = 7, FP64);
+    3: register-pencil form (several elements per item at low orders);
+    4: direct-to-LDS form (N = 7, FP64);
     5: one thread per node."""
     init(device)
     var = ctypes.c_int(0)
