@@ -185,16 +185,17 @@ def main():
     log(args, f"inputs generated on GPU in {time.time() - t0:.1f} s "
               f"({points} points, {args.dtype})")
 
+    sem.init(0)
     if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=devn).fill_(1.0)
+        src = torch.empty(CALIBRATION_BYTES // 8, dtype=torch.float64, device=devn).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        sem.stream_copy(src, dst)
         torch.cuda.synchronize()
-        log(args, "copy calibration: 1 GiB read + 1 GiB written")
+        log(args, "copy calibration: 1 GiB read + 1 GiB written by stream_copy16")
         del src, dst
+    copy_bw = copy_bandwidth(args, sem, devn)
 
-    sem.init(0)
     k_iso = len(isos)
     dcode = sem.SEM_F64 if args.dtype == "f64" else sem.SEM_F32
     q = torch.empty_like(u)
@@ -301,6 +302,15 @@ def main():
     log(args, f"timed {args.steps} steps in graph replays: {ms_graph:.4f} ms/step")
     del graphs
 
+    # per-step timing protocol: single steps bracketed by their own events,
+    # warm (back to back) and cold (L2 and MALL flushed before each step by
+    # a 512 MiB copy that touches 1 GiB); median and the 10th / 90th
+    # percentiles over the repetitions
+    protocol = step_protocol(args, sem, step, devn)
+    log(args, "per-step protocol: " + ", ".join(
+        f"{k} median {v['median_ms']:.4f} ms (p10 {v['p10_ms']:.4f}, p90 {v['p90_ms']:.4f})"
+        for k, v in protocol.items() if isinstance(v, dict)))
+
     # the same path as two calls (sem_qcrit, then sem_isosurface), for comparison
     iws = torch.empty(sem.workspace_bytes(n_elem, n, k_iso), dtype=torch.uint8, device=devn)
     tri_all = torch.empty((max(total_tri, 1), 3, 3), dtype=tdt, device=devn)
@@ -331,6 +341,10 @@ def main():
     k_bytes = points * 8 * esz + n_elem * 2 * esz + (k_iso * n_elem * 4 if esz == 8 else 0)
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(kname, args.dtype, points)
+    # the whole step: 64 (FP64) / 32 (FP32) B per point and 72 / 36 B per
+    # triangle
+    step_bytes = points * 8 * esz + total_tri * 9 * esz
+    step_gbs = step_bytes / (ms_graph * 1e-3) / 1e9
     roof = {
         "bound": "hbm",
         "kernel": kname,
@@ -339,6 +353,8 @@ def main():
         "unit": "GB/s",
         "frac": round(k_gbs / HBM_PEAK_GBS, 4),
         "traffic": traffic,
+        "copy_gbps": round(copy_bw, 1),
+        "frac_of_copy": round(k_gbs / copy_bw, 4),
         "avg_ms": round(k_ms, 5),
         "algorithmic_bytes_per_launch": k_bytes,
         "dominant": max(phase_ms, key=phase_ms.get) == "qcrit",
@@ -367,6 +383,12 @@ def main():
         "phase_ms": {k: round(v, 5) for k, v in phase_ms.items() if v},
         "launch": "HIP graphs of up to 100 steps (the steps' kernels captured once), "
                   "each replayed once",
+        "step_hbm": {"algorithmic_bytes": step_bytes,
+                     "achieved_gbps": round(step_gbs, 1),
+                     "frac_of_peak": round(step_gbs / HBM_PEAK_GBS, 4),
+                     "frac_of_copy": round(step_gbs / copy_bw, 4)},
+        "copy_bandwidth_gbps": round(copy_bw, 1),
+        "step_protocol": protocol,
         "eager_ms_per_step": round(ms_step, 5),
         "ms_per_step_with_phase_timing": round(ms_phased, 5),
         "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
@@ -383,6 +405,65 @@ def main():
     if args.cpu_baseline == "on":
         result["cpu_baseline"] = cpu_baseline(args, fields, isos, n, n_elem)
     print(json.dumps(result), flush=True)
+
+
+def _pcts(ms):
+    import numpy as np
+    a = np.asarray(ms, dtype=np.float64)
+    return {"median_ms": round(float(np.median(a)), 5),
+            "p10_ms": round(float(np.percentile(a, 10)), 5),
+            "p90_ms": round(float(np.percentile(a, 90)), 5)}
+
+
+def copy_bandwidth(args, sem, dev, nbytes=CALIBRATION_BYTES, reps=20):
+    """Sustained HBM bandwidth of the library's plain copy kernel
+    (sem_stream_copy): nbytes read and nbytes written per call, median over
+    `reps` calls each bracketed by events."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    ms = []
+    for r in range(reps + 2):
+        e0.record()
+        sem.stream_copy(src, dst)
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            ms.append(e0.elapsed_time(e1))
+    med = _pcts(ms)["median_ms"]
+    gbps = 2 * nbytes / (med * 1e-3) / 1e9
+    log(args, f"stream copy: {2 * nbytes / 2**30:.1f} GiB moved in {med:.4f} ms (median of "
+              f"{reps}): {gbps:.1f} GB/s = {gbps / HBM_PEAK_GBS:.3f} of the HBM peak")
+    del src, dst
+    return gbps
+
+
+def step_protocol(args, sem, step, dev, reps=60):
+    """Single steps, each between its own pair of events: warm (back to
+    back) and cold (a 512 MiB copy before each step evicts L2 and the
+    256 MB MALL)."""
+    import torch
+    flush_a = torch.empty(1 << 27, dtype=torch.float32, device=dev).fill_(0.0)
+    flush_b = torch.empty_like(flush_a)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    out = {"reps": reps, "warmup": 5}
+    for mode in ("warm", "cold"):
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        for a, b in ev:
+            if mode == "cold":
+                sem.stream_copy(flush_a, flush_b)
+            a.record()
+            step()
+            b.record()
+        torch.cuda.synchronize()
+        out[mode] = _pcts([a.elapsed_time(b) for a, b in ev])
+    del flush_a, flush_b
+    return out
 
 
 def compression_timing(args, sem):
@@ -799,22 +880,34 @@ def cpu_baseline(args, fields, isos, n, n_elem):
     idx = __import__("torch").from_numpy(els).to(fields[0].device)
     arrs = [f.index_select(0, idx).double().cpu().numpy() for f in fields]
     d = gll.diff_matrix(n)
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
-    t0 = time.perf_counter()
-    q, om, _ = osem.qcrit(*arrs, d)
-    mc.extract(*arrs[:3], q, isos)
-    dt_s = time.perf_counter() - t0
+    # the elements are independent: worker threads take chunks of 512
+    # elements each (numpy releases the interpreter lock inside its array
+    # operations), with BLAS held to one thread per worker, so `cores` is
+    # the number of threads actually computing
+    import concurrent.futures
+    from threadpoolctl import threadpool_limits
+    workers = max(1, min(16, os.cpu_count() or 1))
+    chunk = 512
+
+    def work(a0):
+        sl = slice(a0, min(a0 + chunk, k))
+        part = [a[sl] for a in arrs]
+        q, _, _ = osem.qcrit(*part, d)
+        mc.extract(*part[:3], q, isos)
+
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(work, range(0, k, chunk)))
+        dt_s = time.perf_counter() - t0
     pts = k * (n + 1) ** 3
-    log(args, f"cpu oracle: {k} elements in {dt_s:.2f} s with {threads} threads")
-    return {"value": pts / dt_s, "unit": "GLL points/s", "cores": threads,
+    log(args, f"cpu oracle: {k} elements in {dt_s:.2f} s with {workers} worker threads")
+    return {"value": pts / dt_s, "unit": "GLL points/s", "cores": workers,
             "kind": "oracle",
             "sample": f"{k} random elements of the same snapshot ({pts} points), "
                       f"FP64 numpy oracle, Q + |omega| + {len(isos)} isosurfaces, "
-                      f"{dt_s:.2f} s"}
+                      f"chunks of {chunk} elements on {workers} threads (BLAS one thread "
+                      f"each), {dt_s:.2f} s wall"}
 
 
 def _csv(directory, suffix):
@@ -898,7 +991,7 @@ def summarize_pmc(fetch_dir, write_dir, out, command):
             if r["Counter_Name"] != counter:
                 continue
             per.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
-        copies = [v for v in per.get("__amd_rocclr_copyBuffer", []) if v > 1024.0]
+        copies = [v for v in per.get("stream_copy16", []) if v > 1024.0]
         scale = CALIBRATION_BYTES / (sum(copies) * 1024.0)
         res[counter] = (per, scale)
     dtype = "f64" if "f64" in os.path.basename(out) else "f32"

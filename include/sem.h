@@ -376,6 +376,16 @@ int sem_timing_begin(int max_spans);
  * SEM_ERR_ARG when timing was not on, SEM_ERR_HIP on a runtime error. */
 int64_t sem_timing_end(double* ms_total, int64_t* spans, int n_phases);
 
+/* Copy `bytes` from src to dst (both DEVICE, 16-byte aligned, not
+ * overlapping; bytes a multiple of 16) with a plain streaming kernel: each
+ * 16-byte chunk read once and written once, consecutive lanes on
+ * consecutive chunks.  It is the reference for the HBM bandwidth this GPU
+ * sustains, beside which the extraction kernels' rates are reported.
+ * SEM_ERR_ARG for NULL pointers with bytes > 0, misaligned pointers or a
+ * size that is not a multiple of 16; bytes == 0 does nothing.  Needs no
+ * sem_init. */
+int sem_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* ---------------------------------------------------------------------
  * Learned in-transit compression (order 7, FP32 fields u, v, w, theta)
  * ---------------------------------------------------------------------

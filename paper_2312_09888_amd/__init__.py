@@ -15,5 +15,5 @@ from ._lib import (  # noqa: F401
     SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW, BatchPlan, qcrit_batch, autotune, batch_variant,
     batch_set_variant, BATCH_VARIANTS, SEM_FLAG_RAW_OVERFLOW, SEM_AE_LATENT, SEM_AE_TANH_HIDDEN,
     ae_param_count, ae_blocks, ae_forward, ae_grad, ae_adam, sym_eig, ae_pca_init, ae_train,
-    ae_compress, ae_decompress, modal_compress, compressed_bytes,
+    ae_compress, ae_decompress, modal_compress, compressed_bytes, stream_copy,
 )

@@ -37,7 +37,7 @@ EXPORTS = (
     "sem_status_str", "sem_gll", "sem_mc_table", "sem_init", "sem_finalize",
     "sem_derivs", "sem_qcrit", "sem_isosurface_workspace_bytes", "sem_isosurface",
     "sem_extract_workspace_bytes", "sem_extract",
-    "sem_phase_name", "sem_timing_begin", "sem_timing_end",
+    "sem_phase_name", "sem_timing_begin", "sem_timing_end", "sem_stream_copy",
     "sem_gs_workspace_bytes", "sem_gs_setup", "sem_dsavg", "sem_global_edge_keys",
     "sem_weld_workspace_bytes", "sem_weld",
     "sem_batch_plan_bytes", "sem_batch_plan", "sem_qcrit_batch", "sem_autotune",
@@ -107,6 +107,8 @@ def lib():
         L.sem_timing_begin.argtypes = [i32]
         L.sem_timing_end.restype = i64
         L.sem_timing_end.argtypes = [vp, vp, i32]
+        L.sem_stream_copy.restype = i32
+        L.sem_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.sem_gs_workspace_bytes.restype = ctypes.c_size_t
         L.sem_gs_workspace_bytes.argtypes = [i64, i32, i64]
         L.sem_gs_setup.restype = i32
@@ -500,6 +502,19 @@ def timing_end():
         raise SemError(int(rc), "sem_timing_end")
     return ({phase_name(k): (float(tot[k]), int(cnt[k])) for k in range(SEM_NUM_PHASES)},
             int(rc))
+
+
+def stream_copy(src, dst):
+    """Plain device copy of src into dst (sem_stream_copy): the bandwidth
+    reference kernel.  Both contiguous tensors on one device, same number of
+    bytes (a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    if (not src.is_cuda or src.device != dst.device or not src.is_contiguous()
+            or not dst.is_contiguous() or dst.numel() * dst.element_size() != nbytes):
+        raise ValueError("src and dst must be contiguous tensors of equal size on one device")
+    with _torch().cuda.device(src.device):
+        _check(lib().sem_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(src)),
+               "sem_stream_copy")
 
 
 # ---------------------------------------------------------------------------

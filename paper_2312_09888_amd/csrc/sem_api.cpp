@@ -637,6 +637,16 @@ int sem_timing_begin(int max_spans) {
   return SEM_OK;
 }
 
+int sem_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (bytes == 0) return SEM_OK;
+  if (!src || !dst || bytes % 16 != 0) return SEM_ERR_ARG;
+  if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return SEM_ERR_ARG;
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes) return SEM_ERR_ARG;
+  hipError_t e = launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
 int64_t sem_timing_end(double* ms_total, int64_t* spans, int n_phases) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return SEM_ERR_HIP;

@@ -149,6 +149,9 @@ struct PhaseTimer {
 PhaseTimer phase_timer(int phase);
 void phase_done(const PhaseTimer& t);
 
+// sem_bw.hip: plain 16-byte-vector copy (bandwidth reference)
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 // sem_kernels.hip -- launchers return hipSuccess or the launch error.
 hipError_t launch_derivs(int order, sem_dtype dt, const DeviceTables& tab,
                          int64_t n_elem, const void* x, const void* y,

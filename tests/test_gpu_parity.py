@@ -301,3 +301,14 @@ def test_taylor_green_end_to_end_counts_bit_exact(dt):
     np.testing.assert_array_equal(host(r["active"]), o["active"])
     np.testing.assert_array_equal(host(r["cases"]), o["cases"])
     assert int(o["tri_count"][0]) == 37184 and int(o["active"][0]) == 18624
+
+
+def test_stream_copy_copies_every_byte():
+    """The bandwidth reference kernel: an exact copy, ragged grid tail
+    included (sizes that are not multiples of the grid's stride)."""
+    for nbytes in (16, 4096 + 48, (1 << 24) + 16 * 1234):
+        src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device=DEV)
+        dst = torch.zeros_like(src)
+        sem.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), nbytes

@@ -203,6 +203,17 @@ def test_timing_argument_errors_and_phase_names():
     assert re.search(rf"SEM_NUM_PHASES = {_lib.SEM_NUM_PHASES}\b", text)
 
 
+def test_stream_copy_argument_errors():
+    L = sem.lib()
+    assert L.sem_stream_copy(None, None, 0, None) == _lib.SEM_OK
+    assert L.sem_stream_copy(None, FAKE, 16, None) == _lib.SEM_ERR_ARG
+    assert L.sem_stream_copy(FAKE, FAKE, 24, None) == _lib.SEM_ERR_ARG        # not 16 x k
+    assert L.sem_stream_copy(ctypes.c_void_p(0x1008), ctypes.c_void_p(0x8000), 16,
+                             None) == _lib.SEM_ERR_ARG                       # misaligned
+    assert L.sem_stream_copy(ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1010), 32,
+                             None) == _lib.SEM_ERR_ARG                       # overlapping
+
+
 @pytest.mark.skipif(not _no_gpu(), reason="only meaningful where no device exists")
 def test_timing_end_without_device_or_begin_fails():
     assert sem.lib().sem_timing_end(None, None, 4) < 0
