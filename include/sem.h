@@ -229,6 +229,34 @@ int sem_extract(int64_t n_elem, int order, sem_dtype dt,
                 void* workspace, size_t workspace_bytes,
                 int32_t* status_word, void* stream);
 
+/* Largest n_iso * n_elem that sem_extract_noalloc accepts. */
+#define SEM_NOALLOC_MAX_COUNTS (1 << 20)
+
+/* sem_extract for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, kernels and results as sem_extract, with the
+ * per-(isovalue, element) triangle counts, their exclusive prefix and the
+ * scan's partial sums held in a fixed scratch array that the library keeps
+ * on every initialised GPU (about 12 MiB, resident until the process ends;
+ * its address is looked up once per device by sem_init) instead of a
+ * caller workspace.  q and q_minmax are required outputs here (sem_extract
+ * keeps them in its workspace when they are NULL); omega_mag and
+ * active_cells stay optional.  Nothing in the scratch needs clearing: every
+ * value is written before it is read in each call.  SEM_ERR_WORKSPACE when
+ * n_iso * n_elem > SEM_NOALLOC_MAX_COUNTS; otherwise the arguments and
+ * errors of sem_extract.  The call allocates and frees nothing.  All calls
+ * on one GPU share its scratch: calls that may overlap in time (different
+ * streams, or host threads without ordering) race on it and must not be
+ * issued; calls on one stream are ordered and safe. */
+int sem_extract_noalloc(int64_t n_elem, int order, sem_dtype dt,
+                        const void* x, const void* y, const void* z,
+                        const void* u, const void* v, const void* w,
+                        void* q, void* omega_mag, void* q_minmax,
+                        int n_iso, const double* iso_host,
+                        void* const* tri_xyz, const int64_t* tri_capacity,
+                        int64_t* tri_count, int64_t* active_cells,
+                        int32_t* status_word, void* stream);
+
 /* ---------------------------------------------------------------------
  * Batched snapshots: one persistent launch over many snapshots
  * ---------------------------------------------------------------------

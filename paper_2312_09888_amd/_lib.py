@@ -25,6 +25,7 @@ SEM_ERR_HIP, SEM_ERR_WORKSPACE, SEM_ERR_DTYPE = -4, -5, -6
 SEM_FLAG_BAD_JACOBIAN, SEM_FLAG_TRI_OVERFLOW, SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW = 1, 2, 4, 8
 SEM_MIN_ORDER, SEM_MAX_ORDER = 1, 9
 SEM_MAX_ISO = 64
+SEM_NOALLOC_MAX_COUNTS = 1 << 20   # n_iso * n_elem of sem_extract_noalloc
 SEM_FLAG_RAW_OVERFLOW = 16
 SEM_AE_LATENT = 32
 SEM_AE_TANH_HIDDEN = 0x1B
@@ -36,7 +37,7 @@ SEM_NUM_PHASES = 4
 EXPORTS = (
     "sem_status_str", "sem_gll", "sem_mc_table", "sem_init", "sem_finalize",
     "sem_derivs", "sem_qcrit", "sem_isosurface_workspace_bytes", "sem_isosurface",
-    "sem_extract_workspace_bytes", "sem_extract",
+    "sem_extract_workspace_bytes", "sem_extract", "sem_extract_noalloc",
     "sem_phase_name", "sem_timing_begin", "sem_timing_end", "sem_stream_copy",
     "sem_gs_workspace_bytes", "sem_gs_setup", "sem_dsavg", "sem_global_edge_keys",
     "sem_weld_workspace_bytes", "sem_weld",
@@ -101,6 +102,9 @@ def lib():
         L.sem_extract.restype = i32
         L.sem_extract.argtypes = ([i64, i32, i32] + [vp] * 9 + [i32, vp, vp, vp, vp, vp,
                                                                 vp, ctypes.c_size_t, vp, vp])
+        L.sem_extract_noalloc.restype = i32
+        L.sem_extract_noalloc.argtypes = ([i64, i32, i32] + [vp] * 9 + [i32, vp, vp, vp, vp, vp,
+                                                                        vp, vp])
         L.sem_phase_name.restype = ctypes.c_char_p
         L.sem_phase_name.argtypes = [i32]
         L.sem_timing_begin.restype = i32
@@ -451,6 +455,49 @@ def extract_into(x, y, z, u, v, w, isovalues, tri_list, tri_count, workspace, q=
             ctypes.cast(ptrs, ctypes.c_void_p), caps.ctypes.data, _ptr(tri_count),
             _ptr(active), _ptr(workspace), 0 if workspace is None else workspace.numel(),
             _ptr(status), _stream(x)), "sem_extract")
+
+
+def extract_noalloc_into(x, y, z, u, v, w, isovalues, tri_list, tri_count, q, minmax,
+                         omega_mag=None, active=None, status=None, precision=None):
+    """sem_extract_noalloc: as extract_into, with the library's fixed device
+    scratch in place of a workspace (q and minmax are required outputs;
+    n_iso * n_elem <= SEM_NOALLOC_MAX_COUNTS)."""
+    torch = _torch()
+    _field_check(x, y, z, u, v, w)
+    _field_check(x, q, omega_mag)
+    _status_check(status, x)
+    n = _order_of(x)
+    init(x.device.index)
+    iso = np.ascontiguousarray(np.asarray(isovalues, dtype=np.float64))
+    k, e = len(iso), x.shape[0]
+    if len(tri_list) != k:
+        raise ValueError("one triangle buffer (or None) per isovalue")
+    caps = np.zeros(k, dtype=np.int64)
+    ptrs = (ctypes.c_void_p * k)()
+    for s, t in enumerate(tri_list):
+        if t is None:
+            continue
+        if (not t.is_cuda or t.device != x.device or t.dtype != x.dtype
+                or not t.is_contiguous() or t.dim() != 3 or tuple(t.shape[1:]) != (3, 3)):
+            raise ValueError("triangle buffers must be contiguous (cap, 3, 3) tensors")
+        caps[s] = t.shape[0]
+        ptrs[s] = t.data_ptr() if t.shape[0] else None
+    for t, numel, what in ((tri_count, k, "tri_count"), (active, k, "active")):
+        if t is not None and (t.dtype != torch.int64 or t.numel() < numel
+                              or t.device != x.device or not t.is_contiguous()):
+            raise ValueError(f"{what} must be an int64 tensor of >= {numel} values")
+    if tri_count is None or q is None or minmax is None:
+        raise ValueError("tri_count, q and minmax are required")
+    if (minmax.numel() < 2 * e or minmax.dtype != x.dtype or not minmax.is_contiguous()
+            or minmax.device != x.device):
+        raise ValueError("minmax must be a contiguous (E, 2) tensor of the field dtype")
+    code = _dtype_code(x, precision)
+    with torch.cuda.device(x.device):
+        _check(lib().sem_extract_noalloc(
+            e, n, code, _ptr(x), _ptr(y), _ptr(z), _ptr(u), _ptr(v), _ptr(w),
+            _ptr(q), _ptr(omega_mag), _ptr(minmax), k, iso.ctypes.data,
+            ctypes.cast(ptrs, ctypes.c_void_p), caps.ctypes.data, _ptr(tri_count),
+            _ptr(active), _ptr(status), _stream(x)), "sem_extract_noalloc")
 
 
 def extract(x, y, z, u, v, w, isovalues, status=None, want_fields=True, precision=None):

@@ -18,7 +18,8 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsem.so")
 
 SOURCES = ["sem_api.cpp", "sem_basis.cpp", "sem_mctable.cpp", "sem_kernels.hip", "sem_c0.hip",
-           "sem_ae.hip", "sem_bw.hip"]
+           "sem_ae.hip", "sem_bw.hip",
+           "sem_noalloc.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

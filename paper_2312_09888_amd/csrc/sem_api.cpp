@@ -218,12 +218,17 @@ int sem_init(int device) {
   if (hipGetDevice(&prev) != hipSuccess) return SEM_ERR_HIP;
   if (hipSetDevice(device) != hipSuccess) return SEM_ERR_HIP;
   void* buf = nullptr;
+  void* scratch = nullptr;
   int rc = SEM_OK;
-  if (hipMalloc(&buf, bytes) != hipSuccess ||
-      hipMemcpy(buf, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+  // this device's copy of the fixed scratch array (sem_extract_noalloc)
+  if (noalloc_scratch(&scratch) != hipSuccess || !scratch) {
+    rc = SEM_ERR_HIP;
+  } else if (hipMalloc(&buf, bytes) != hipSuccess ||
+             hipMemcpy(buf, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
     if (buf) (void)hipFree(buf);
     rc = SEM_ERR_HIP;
   } else {
+    st.tab.scratch = scratch;
     st.buf = buf;
     char* b = static_cast<char*>(buf);
     for (int n = 0; n <= kMaxOrder; ++n) {
@@ -323,6 +328,40 @@ int sem_extract(int64_t n_elem, int order, sem_dtype dt, const void* x, const vo
   hipError_t e = launch_extract(order, dt, *tab, n_elem, x, y, z, u, v, w, q, omega_mag,
                                 q_minmax, n_iso, iso_host, tri_xyz, tri_capacity, tri_count,
                                 active_cells, ws, status_word, s);
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
+int sem_extract_noalloc(int64_t n_elem, int order, sem_dtype dt, const void* x, const void* y,
+                        const void* z, const void* u, const void* v, const void* w, void* q,
+                        void* omega_mag, void* q_minmax, int n_iso, const double* iso_host,
+                        void* const* tri_xyz, const int64_t* tri_capacity, int64_t* tri_count,
+                        int64_t* active_cells, int32_t* status_word, void* stream) {
+  int rc = check_common(n_elem, order, dt);
+  if (rc) return rc;
+  if (n_iso < 1 || n_iso > SEM_MAX_ISO || !iso_host || !tri_count) return SEM_ERR_ARG;
+  if (!tri_xyz || !tri_capacity) return SEM_ERR_ARG;
+  for (int k = 0; k < n_iso; ++k)
+    if (tri_capacity[k] < 0 || (tri_capacity[k] > 0 && !tri_xyz[k])) return SEM_ERR_ARG;
+  if (n_elem > 0 && (!x || !y || !z || !u || !v || !w || !q || !q_minmax)) return SEM_ERR_ARG;
+  // the counts, offsets and scan partials must fit the fixed scratch
+  if ((int64_t)n_iso * n_elem > SEM_NOALLOC_MAX_COUNTS) return SEM_ERR_WORKSPACE;
+  if (iso_workspace_layout(nullptr, n_elem, n_iso).bytes > noalloc_scratch_bytes())
+    return SEM_ERR_WORKSPACE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the device address looked up for this GPU by sem_init, never the
+  // array's host-side name
+  const IsoWorkspace ws =
+      n_elem > 0 ? iso_workspace_layout(tab->scratch, n_elem, n_iso) : IsoWorkspace{};
+  hipError_t e =
+      n_elem == 0
+          ? launch_isosurface(order, dt, *tab, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              n_iso, iso_host, nullptr, 0, nullptr, tri_count, active_cells,
+                              nullptr, IsoWorkspace{}, status_word, s)
+          : launch_extract(order, dt, *tab, n_elem, x, y, z, u, v, w, q, omega_mag, q_minmax,
+                           n_iso, iso_host, tri_xyz, tri_capacity, tri_count, active_cells, ws,
+                           status_word, s);
   return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
 }
 

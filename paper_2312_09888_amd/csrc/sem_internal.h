@@ -27,6 +27,8 @@ struct DeviceTables {
   const int8_t* tri;                  // [256][kMcMaxTri][3]
   const double* eo7;                  // N = 7 even-odd form of D: A[4][4], B[4][4]
   int cu_count;                       // compute units (persistent grids)
+  void* scratch;                      // device address of this GPU's copy of the
+                                      // fixed scratch array (sem_noalloc.hip)
   int tuned_variant[2][kMaxOrder + 1];  // batch variant + 1 per (dtype, order); 0 = not tuned
 };
 
@@ -148,6 +150,11 @@ struct PhaseTimer {
 };
 PhaseTimer phase_timer(int phase);
 void phase_done(const PhaseTimer& t);
+
+// sem_noalloc.hip: device address of the fixed scratch array on the current
+// device (looked up once per device by sem_init) and its size in bytes.
+hipError_t noalloc_scratch(void** ptr);
+size_t noalloc_scratch_bytes();
 
 // sem_bw.hip: plain 16-byte-vector copy (bandwidth reference)
 hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

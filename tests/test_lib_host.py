@@ -203,6 +203,29 @@ def test_timing_argument_errors_and_phase_names():
     assert re.search(rf"SEM_NUM_PHASES = {_lib.SEM_NUM_PHASES}\b", text)
 
 
+def test_extract_noalloc_argument_errors():
+    L = sem.lib()
+    iso = (ctypes.c_double * 2)(0.1, 0.2)
+    caps = (ctypes.c_int64 * 2)(0, 0)
+    ptrs = (ctypes.c_void_p * 2)(None, None)
+
+    def call(n, n_iso=1, q=FAKE, mm=FAKE, order=7):
+        return L.sem_extract_noalloc(n, order, 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, q, None,
+                                     mm, n_iso, iso, ptrs, caps, FAKE, None, None, None)
+
+    # the scratch holds SEM_NOALLOC_MAX_COUNTS (isovalue, element) counts
+    assert call(_lib.SEM_NOALLOC_MAX_COUNTS + 1) == _lib.SEM_ERR_WORKSPACE
+    assert call(_lib.SEM_NOALLOC_MAX_COUNTS // 2 + 1, n_iso=2) == _lib.SEM_ERR_WORKSPACE
+    # Q and its element ranges are required outputs
+    assert call(4, q=None) == _lib.SEM_ERR_ARG
+    assert call(4, mm=None) == _lib.SEM_ERR_ARG
+    assert call(4, order=0) == _lib.SEM_ERR_ORDER
+    assert call(4, n_iso=0) == _lib.SEM_ERR_ARG
+    text = open(HEADER).read()
+    assert re.search(r"#define SEM_NOALLOC_MAX_COUNTS \(1 << 20\)", text)
+    assert _lib.SEM_NOALLOC_MAX_COUNTS == 1 << 20
+
+
 def test_stream_copy_argument_errors():
     L = sem.lib()
     assert L.sem_stream_copy(None, None, 0, None) == _lib.SEM_OK
