@@ -587,8 +587,10 @@ def batched_timing(args, sem):
     Times: sem_qcrit per snapshot (16 launches) against sem_qcrit_batch (one
     persistent launch per order: with the default forms, then with the
     autotuned ones); and the whole step -- batched Q, then the
-    isosurfaces of Q, |omega| and theta at 4 isovalues each per snapshot --
-    eager against replayed as one captured HIP graph."""
+    isosurfaces of Q, |omega| and theta at 4 isovalues each per snapshot in
+    one batched isosurface call (persistent count and emission kernels per
+    order, one scan) -- eager and replayed as one captured HIP graph, beside
+    the same step with 48 separate isosurface calls."""
     import torch
 
     import workloads as W
@@ -660,27 +662,55 @@ def batched_timing(args, sem):
         isos.append(per)
     total_tri = sum(int(t[2].shape[0]) for per in isos for t in per)
 
-    def step():
+    def step_per_call():
         sem.qcrit_batch(plan)
         for sn, per in zip(snaps, isos):
             for f, iv, tri, cnt, ws in per:
                 sem.isosurface_into(sn["x"], sn["y"], sn["z"], f, iv, tri, cnt, ws)
 
+    # the same 48 isosurfaces as one batched call: persistent count, one
+    # scan, persistent emission
+    jobs = []
+    for i, (sn, per) in enumerate(zip(snaps, isos)):
+        for (f, iv, _, _, _), name in zip(per, ("q", "omega_mag", None)):
+            jobs.append({"snap": i, "field": name if name else f, "isovalues": iv})
+    iso_plan = sem.IsoBatchPlan(snaps, jobs)
+    b_tri = torch.empty((max(total_tri, 1), 3, 3), dtype=torch.float32, device=dev)
+    b_cnt = torch.zeros(4 * len(jobs), dtype=torch.int64, device=dev)
+    b_off = torch.zeros_like(b_cnt)
+
+    def step():
+        sem.qcrit_batch(plan)
+        sem.isosurface_batch_into(iso_plan, b_tri, b_cnt, b_off)
+
+    def graph_of(fn):
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        return g
+
+    percall_eager_ms = timed(step_per_call)
+    g_percall = graph_of(step_per_call)
+    percall_graph_ms = timed(g_percall.replay)
+    del g_percall
     eager_ms = timed(step)
-    g = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(g, stream=side):
-            step()
-    torch.cuda.current_stream().wait_stream(side)
-    torch.cuda.synchronize()
+    g = graph_of(step)
     graph_ms = timed(g.replay)
+    # isosurface phase alone (Q already computed)
+    iso_ms = timed(lambda: sem.isosurface_batch_into(iso_plan, b_tri, b_cnt, b_off))
+    assert int(b_cnt.sum().item()) == total_tri
     log(args, f"batched: sem_qcrit x16 {per_ms:.3f} ms, sem_qcrit_batch default forms "
               f"{default_ms:.3f} ms, tuned {batch_ms:.3f} ms "
-              f"({points / (batch_ms * 1e-3) / 1e9:.1f} G points/s); whole step (Q + 48 "
-              f"isosurface calls) eager {eager_ms:.3f} ms, graph {graph_ms:.3f} ms; "
-              f"variants {({n: t['variant'] for n, t in tuned.items()})}")
+              f"({points / (batch_ms * 1e-3) / 1e9:.1f} G points/s); whole step (Q batch + "
+              f"batched isosurfaces) eager {eager_ms:.3f} ms, graph {graph_ms:.3f} ms; "
+              f"with 48 isosurface calls eager {percall_eager_ms:.3f} ms, graph "
+              f"{percall_graph_ms:.3f} ms; variants "
+              f"{({n: t['variant'] for n, t in tuned.items()})}")
     out = {"snapshots": 16, "points": points,
            "orders": [sp[0] for sp in specs], "elements": [sp[1][0] * sp[1][1] * sp[1][2]
                                                            for sp in specs],
@@ -694,8 +724,14 @@ def batched_timing(args, sem):
                sp[1][0] * sp[1][1] * sp[1][2] for sp in specs), batch_ms),
            "step_eager_ms": round(eager_ms, 4), "step_graph_ms": round(graph_ms, 4),
            "step_graph_points_per_s": points / (graph_ms * 1e-3),
+           "isosurface_batch_ms": round(iso_ms, 4),
+           "step_launches": "Q: one persistent kernel per order; isosurfaces: one persistent "
+                            "count kernel per order, one scan (3 kernels + totals), one "
+                            "persistent emission kernel per order",
+           "step_per_call_eager_ms": round(percall_eager_ms, 4),
+           "step_per_call_graph_ms": round(percall_graph_ms, 4),
            "triangles": total_tri}
-    del snaps, theta, isos, plan, plan_default, g
+    del snaps, theta, isos, plan, plan_default, g, iso_plan, b_tri
     torch.cuda.empty_cache()
     out["small"] = batched_small(args, sem, timed)
     return out

@@ -321,6 +321,68 @@ int sem_batch_variant(int order, sem_dtype dt);
 int sem_batch_set_variant(int order, sem_dtype dt, int variant);
 
 /* ---------------------------------------------------------------------
+ * Batched isosurfaces: persistent count, one scan, persistent emission
+ * ---------------------------------------------------------------------
+ * The marching-cubes extraction of sem_isosurface (Lorensen & Cline 1987;
+ * the cases, order and vertex rule are sem_isosurface's) over many
+ * (snapshot, field, isovalue set) jobs at once: one persistent count kernel
+ * per order present walks every (job, element) work item, one exclusive
+ * scan runs over the counts of every job, and one persistent emission
+ * kernel per order writes the triangles.  Every job's triangles go into one
+ * soup, ordered by job (the caller's order), isovalue, element, cell and
+ * case-table slot; each (job, isovalue) gets its first triangle and count.
+ * A job's triangles are bit-identical to those sem_isosurface writes for
+ * the same field and isovalues. */
+enum { SEM_JOB_Q = 0, SEM_JOB_OMEGA = 1, SEM_JOB_SCALAR = 2 };
+typedef struct {
+  int snap;              /* index into the snapshot array of the plan call      */
+  int field;             /* SEM_JOB_Q: the snapshot's q (its q_minmax, if any,
+                            culls elements); SEM_JOB_OMEGA: its omega_mag;
+                            SEM_JOB_SCALAR: `scalar`                             */
+  const void* scalar;    /* DEVICE field in the sem layout (SEM_JOB_SCALAR)     */
+  int n_iso;             /* 1 <= n_iso <= 4                                     */
+  double iso[4];         /* isovalues, cast to the plan's precision             */
+} sem_iso_job;
+
+typedef struct {
+  unsigned launch_code;  /* bit N set when some job has order N                 */
+  sem_dtype dt;          /* the plan's precision                                */
+  int n_job;
+  int64_t n_slots;       /* (job, isovalue, element) count slots                */
+  size_t workspace_bytes;/* workspace sem_isosurface_batch needs                */
+} sem_iso_batch_info;
+
+/* Bytes of an isosurface plan for n_job jobs (1 <= n_job <= 16384; else 0). */
+size_t sem_iso_batch_plan_bytes(int n_job);
+
+/* Write the plan of n_job jobs (HOST array) over n_snap snapshots (HOST
+ * array; only their order, element count, coordinates, q, omega_mag and
+ * q_minmax are used) into the DEVICE buffer plan, and its launch facts into
+ * *info (HOST).  SEM_ERR_ARG for a job naming a snapshot outside
+ * [0, n_snap), an unknown field, a NULL field the job needs, n_iso outside
+ * [1, 4] or a NaN isovalue; SEM_ERR_ORDER for a snapshot order outside
+ * [SEM_MIN_ORDER, SEM_MAX_ORDER].  A setup call: it copies synchronously
+ * (not capturable); the plan records the pointers given now. */
+int sem_iso_batch_plan(int n_snap, const sem_snapshot* snaps, int n_job,
+                       const sem_iso_job* jobs, sem_dtype dt, void* plan, size_t plan_bytes,
+                       sem_iso_batch_info* info);
+
+/* Isosurfaces of every job of the plan into tri_xyz (DEVICE
+ * [tri_capacity][3][3], dt), on `stream`; info is the plan call's and dt
+ * its precision (SEM_ERR_DTYPE otherwise): tri_offset (DEVICE [4 * n_job],
+ * may be NULL) receives the first triangle of (job j, isovalue s) at
+ * 4j + s, tri_count (DEVICE [4 * n_job]) its count (0 for s >= the job's
+ * n_iso), active_cells (DEVICE [4 * n_job], may be NULL) its active cells.
+ * Counts are exact when the soup does not fit; triangles past tri_capacity
+ * are not written and SEM_FLAG_TRI_OVERFLOW is set.  workspace (DEVICE,
+ * >= info->workspace_bytes) needs no clearing.  Asynchronous; capturable in
+ * a HIP graph (no host data is read at launch time). */
+int sem_isosurface_batch(const void* plan, const sem_iso_batch_info* info, sem_dtype dt,
+                         void* tri_xyz, int64_t tri_capacity, int64_t* tri_offset,
+                         int64_t* tri_count, int64_t* active_cells, void* workspace,
+                         size_t workspace_bytes, int32_t* status_word, void* stream);
+
+/* ---------------------------------------------------------------------
  * C0 averaging over shared GLL nodes and welded isosurface output
  * ---------------------------------------------------------------------
  * Elements store their own copy of every node.  gid[e][node] (DEVICE int64,

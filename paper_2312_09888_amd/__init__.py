@@ -16,5 +16,6 @@ from ._lib import (  # noqa: F401
     batch_set_variant, BATCH_VARIANTS, SEM_FLAG_RAW_OVERFLOW, SEM_AE_LATENT, SEM_AE_TANH_HIDDEN,
     ae_param_count, ae_blocks, ae_forward, ae_grad, ae_adam, sym_eig, ae_pca_init, ae_train,
     ae_compress, ae_decompress, modal_compress, compressed_bytes, stream_copy,
-    extract_noalloc_into, SEM_NOALLOC_MAX_COUNTS,
+    extract_noalloc_into, SEM_NOALLOC_MAX_COUNTS, IsoBatchPlan, isosurface_batch,
+    isosurface_batch_into, SEM_JOB_Q, SEM_JOB_OMEGA, SEM_JOB_SCALAR,
 )

@@ -43,6 +43,7 @@ EXPORTS = (
     "sem_weld_workspace_bytes", "sem_weld",
     "sem_batch_plan_bytes", "sem_batch_plan", "sem_qcrit_batch", "sem_autotune",
     "sem_batch_variant", "sem_batch_set_variant",
+    "sem_iso_batch_plan_bytes", "sem_iso_batch_plan", "sem_isosurface_batch",
     "sem_ae_param_count", "sem_ae_workspace_bytes", "sem_ae_blocks", "sem_ae_forward",
     "sem_ae_grad", "sem_ae_adam", "sem_eig_workspace_bytes", "sem_sym_eig",
     "sem_ae_pca_workspace_bytes", "sem_ae_pca_init", "sem_ae_compress_workspace_bytes",
@@ -55,6 +56,21 @@ class _Snapshot(ctypes.Structure):
     _fields_ = [("n_elem", ctypes.c_int64), ("order", ctypes.c_int)] + [
         (k, ctypes.c_void_p) for k in ("x", "y", "z", "u", "v", "w", "q", "omega_mag",
                                        "q_minmax")]
+
+
+class _IsoJob(ctypes.Structure):
+    """sem_iso_job of include/sem.h."""
+    _fields_ = [("snap", ctypes.c_int), ("field", ctypes.c_int), ("scalar", ctypes.c_void_p),
+                ("n_iso", ctypes.c_int), ("iso", ctypes.c_double * 4)]
+
+
+class _IsoBatchInfo(ctypes.Structure):
+    """sem_iso_batch_info of include/sem.h."""
+    _fields_ = [("launch_code", ctypes.c_uint), ("dt", ctypes.c_int), ("n_job", ctypes.c_int),
+                ("n_slots", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
+
+
+SEM_JOB_Q, SEM_JOB_OMEGA, SEM_JOB_SCALAR = 0, 1, 2
 
 
 class SemError(RuntimeError):
@@ -137,6 +153,13 @@ def lib():
         L.sem_batch_variant.argtypes = [i32, i32]
         L.sem_batch_set_variant.restype = i32
         L.sem_batch_set_variant.argtypes = [i32, i32, i32]
+        L.sem_iso_batch_plan_bytes.restype = ctypes.c_size_t
+        L.sem_iso_batch_plan_bytes.argtypes = [i32]
+        L.sem_iso_batch_plan.restype = i32
+        L.sem_iso_batch_plan.argtypes = [i32, vp, i32, vp, i32, vp, ctypes.c_size_t, vp]
+        L.sem_isosurface_batch.restype = i32
+        L.sem_isosurface_batch.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, vp,
+                                           ctypes.c_size_t, vp, vp]
         sz, flt = ctypes.c_size_t, ctypes.c_float
         L.sem_ae_param_count.restype = i64
         L.sem_ae_param_count.argtypes = []
@@ -730,6 +753,122 @@ def batch_set_variant(order, dtype_code, variant, device=None):
     init(device)
     _check(lib().sem_batch_set_variant(int(order), int(dtype_code), int(variant)),
            "sem_batch_set_variant")
+
+
+def _snapshot_array(snapshots):
+    arr = (_Snapshot * len(snapshots))()
+    for i, sn in enumerate(snapshots):
+        x = sn["x"]
+        arr[i].n_elem = x.shape[0]
+        arr[i].order = _order_of(x)
+        for k in ("x", "y", "z", "u", "v", "w"):
+            setattr(arr[i], k, _ptr(sn.get(k)))
+        arr[i].q = _ptr(sn.get("q"))
+        arr[i].omega_mag = _ptr(sn.get("omega_mag"))
+        arr[i].q_minmax = _ptr(sn.get("minmax"))
+    return arr
+
+
+class IsoBatchPlan:
+    """Device plan of batched isosurfaces (sem_iso_batch_plan).  `snapshots`
+    are dicts as for BatchPlan (x, y, z and the fields the jobs use: q,
+    omega_mag, minmax); each job is a dict with "snap" (index), "field"
+    ("q", "omega_mag" or a scalar tensor of the snapshot's shape) and
+    "isovalues" (1 to 4 floats).  Holds references to every tensor it points
+    at."""
+
+    def __init__(self, snapshots, jobs):
+        torch = _torch()
+        if not snapshots or not jobs:
+            raise ValueError("no snapshots or no jobs")
+        ref = snapshots[0]["x"]
+        self.dtype_code = _dtype_code(ref)
+        self.device = ref.device
+        init(ref.device.index)
+        for sn in snapshots:
+            x = sn["x"]
+            _field_check(x, sn["y"], sn["z"], sn.get("q"), sn.get("omega_mag"))
+            if x.dtype != ref.dtype or x.device != ref.device:
+                raise ValueError("all snapshots share one dtype and device")
+            mm = sn.get("minmax")
+            if mm is not None and (mm.numel() < 2 * x.shape[0] or mm.dtype != x.dtype):
+                raise ValueError("minmax must hold (E, 2) values of the field dtype")
+        arr = _snapshot_array(snapshots)
+        jarr = (_IsoJob * len(jobs))()
+        self._keep = [snapshots]
+        for k, jb in enumerate(jobs):
+            f = jb["field"]
+            jarr[k].snap = int(jb["snap"])       # range checked by the library
+            if isinstance(f, str):
+                jarr[k].field = {"q": SEM_JOB_Q, "omega_mag": SEM_JOB_OMEGA}[f]
+                jarr[k].scalar = None
+            else:
+                if 0 <= jb["snap"] < len(snapshots):
+                    _field_check(snapshots[jb["snap"]]["x"], f)
+                jarr[k].field = SEM_JOB_SCALAR
+                jarr[k].scalar = _ptr(f)
+                self._keep.append(f)
+            iv = [float(c) for c in jb["isovalues"]]
+            jarr[k].n_iso = len(iv)              # 1..4, checked by the library
+            for q, c in enumerate(iv[:4]):
+                jarr[k].iso[q] = c
+        nb = int(lib().sem_iso_batch_plan_bytes(len(jobs)))
+        if nb == 0:
+            raise SemError(SEM_ERR_ARG, "sem_iso_batch_plan_bytes")
+        self.buf = torch.empty(nb, dtype=torch.uint8, device=ref.device)
+        self.info = _IsoBatchInfo()
+        with torch.cuda.device(ref.device):
+            torch.cuda.current_stream(ref.device).synchronize()
+            _check(lib().sem_iso_batch_plan(len(snapshots), ctypes.addressof(arr), len(jobs),
+                                            ctypes.addressof(jarr), self.dtype_code,
+                                            _ptr(self.buf), nb, ctypes.addressof(self.info)),
+                   "sem_iso_batch_plan")
+        self.n_job = len(jobs)
+        self.workspace = torch.empty(max(int(self.info.workspace_bytes), 1), dtype=torch.uint8,
+                                     device=ref.device)
+        self.dtype = ref.dtype
+
+
+def isosurface_batch_into(plan, tri_xyz, tri_count, tri_offset=None, active=None, status=None):
+    """Isosurfaces of every job of the plan into tri_xyz ((cap, 3, 3), the
+    plan's dtype): tri_count and tri_offset ((4 * n_job,) int64) receive the
+    count and first triangle of (job j, isovalue s) at 4j + s.  Asynchronous
+    and capturable; the counts are exact when the soup overflows."""
+    torch = _torch()
+    cap = 0 if tri_xyz is None else tri_xyz.shape[0]
+    for t in (tri_count, tri_offset, active):
+        if t is not None and (t.dtype != torch.int64 or t.numel() < 4 * plan.n_job):
+            raise ValueError("per-(job, isovalue) arrays hold 4 * n_job int64")
+    if tri_xyz is not None and tri_xyz.dtype != plan.dtype:
+        raise ValueError("tri_xyz must have the plan's dtype")
+    with torch.cuda.device(plan.device):
+        _check(lib().sem_isosurface_batch(
+            _ptr(plan.buf), ctypes.addressof(plan.info), plan.dtype_code,
+            _ptr(tri_xyz) if cap else None, cap, _ptr(tri_offset), _ptr(tri_count),
+            _ptr(active), _ptr(plan.workspace), plan.workspace.numel(), _ptr(status),
+            torch.cuda.current_stream(plan.device).cuda_stream), "sem_isosurface_batch")
+
+
+def isosurface_batch(plan, status=None, active=False):
+    """Counts, then a soup of exactly that size: returns a dict with tri_xyz
+    (T, 3, 3), tri_count and tri_offset ((n_job, 4) int64) and, if asked,
+    active ((n_job, 4))."""
+    torch = _torch()
+    dev = plan.device
+    cnt = torch.zeros(4 * plan.n_job, dtype=torch.int64, device=dev)
+    off = torch.zeros(4 * plan.n_job, dtype=torch.int64, device=dev)
+    act = torch.zeros(4 * plan.n_job, dtype=torch.int64, device=dev) if active else None
+    # count-only call: with no capacity the overflow flag is set by design,
+    # so it does not touch the caller's status word
+    isosurface_batch_into(plan, None, cnt, off, act, None)
+    total = int(cnt.sum().item())
+    tri = torch.empty((max(total, 1), 3, 3), dtype=plan.dtype, device=dev)
+    isosurface_batch_into(plan, tri, cnt, off, act, status)
+    out = {"tri_xyz": tri[:total], "tri_count": cnt.view(plan.n_job, 4).cpu(),
+           "tri_offset": off.view(plan.n_job, 4).cpu()}
+    if active:
+        out["active"] = act.view(plan.n_job, 4).cpu()
+    return out
 
 
 # ---------------------------------------------------------------------------

@@ -493,6 +493,123 @@ int sem_qcrit_batch(const void* plan, unsigned launch_code, sem_dtype dt, int32_
   return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
 }
 
+size_t sem_iso_batch_plan_bytes(int n_job) {
+  if (n_job < 1 || n_job > kIsoBatchMaxJob) return 0;
+  return iso_batch_plan_bytes(n_job);
+}
+
+int sem_iso_batch_plan(int n_snap, const sem_snapshot* snaps, int n_job,
+                       const sem_iso_job* jobs, sem_dtype dt, void* plan, size_t plan_bytes,
+                       sem_iso_batch_info* info) {
+  if (n_snap < 1 || n_snap > kBatchMaxSnap || !snaps || !info) return SEM_ERR_ARG;
+  if (n_job < 1 || n_job > kIsoBatchMaxJob || !jobs) return SEM_ERR_ARG;
+  if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;
+  if (!plan || plan_bytes < iso_batch_plan_bytes(n_job)) return SEM_ERR_WORKSPACE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  for (int i = 0; i < n_snap; ++i) {
+    const sem_snapshot& sn = snaps[i];
+    if (sn.order < SEM_MIN_ORDER || sn.order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
+    if (sn.n_elem < 0 || sn.n_elem > (int64_t)0x7fffffff) return SEM_ERR_ARG;
+  }
+  std::vector<const void*> field(n_job), mm(n_job);
+  for (int k = 0; k < n_job; ++k) {
+    const sem_iso_job& jb = jobs[k];
+    if (jb.snap < 0 || jb.snap >= n_snap) return SEM_ERR_ARG;
+    if (jb.n_iso < 1 || jb.n_iso > 4) return SEM_ERR_ARG;
+    for (int q = 0; q < jb.n_iso; ++q)
+      if (jb.iso[q] != jb.iso[q]) return SEM_ERR_ARG;
+    const sem_snapshot& sn = snaps[jb.snap];
+    if (jb.field == SEM_JOB_Q) {
+      field[k] = sn.q;
+      mm[k] = sn.q_minmax;
+    } else if (jb.field == SEM_JOB_OMEGA) {
+      field[k] = sn.omega_mag;
+      mm[k] = nullptr;
+    } else if (jb.field == SEM_JOB_SCALAR) {
+      field[k] = jb.scalar;
+      mm[k] = nullptr;
+    } else {
+      return SEM_ERR_ARG;
+    }
+    if (sn.n_elem > 0 && (!field[k] || !sn.x || !sn.y || !sn.z)) return SEM_ERR_ARG;
+  }
+  std::vector<unsigned char> host(iso_batch_plan_bytes(n_job), 0);
+  IsoBatchHeader* hdr = reinterpret_cast<IsoBatchHeader*>(host.data());
+  IsoBatchJob* out = reinterpret_cast<IsoBatchJob*>(host.data() + 256);
+  // count slots in the caller's job order (the soup's order)
+  std::vector<int64_t> slot(n_job);
+  int64_t n_slots = 0;
+  for (int k = 0; k < n_job; ++k) {
+    slot[k] = n_slots;
+    n_slots += (int64_t)jobs[k].n_iso * snaps[jobs[k].snap].n_elem;
+  }
+  unsigned code = 0;
+  int next = 0;
+  for (int n = SEM_MIN_ORDER; n <= kMaxOrder; ++n) {
+    hdr->job_begin[n] = next;
+    int64_t items = 0;
+    for (int k = 0; k < n_job; ++k) {
+      const sem_iso_job& jb = jobs[k];
+      const sem_snapshot& sn = snaps[jb.snap];
+      if (sn.order != n) continue;
+      IsoBatchJob& d = out[next++];
+      d.n_elem = sn.n_elem;
+      d.item_begin = items;
+      d.slot_begin = slot[k];
+      d.order = n;
+      d.n_iso = jb.n_iso;
+      d.job = k;
+      d.x = sn.x;
+      d.y = sn.y;
+      d.z = sn.z;
+      d.field = field[k];
+      d.mm = mm[k];
+      for (int q = 0; q < 4; ++q) {
+        const double c = q < jb.n_iso ? jb.iso[q] : 0.0;
+        d.isod[q] = c;
+        d.isof[q] = (float)c;
+      }
+      items += sn.n_elem;
+    }
+    hdr->items[n] = items;
+    if (items > 0) code |= 1u << n;
+  }
+  hdr->job_begin[0] = 0;
+  hdr->job_begin[kMaxOrder + 1] = next;
+  hdr->n_job = n_job;
+  hdr->dt = dt;
+  hdr->n_slots = n_slots;
+  info->launch_code = code;
+  info->dt = dt;
+  info->n_job = n_job;
+  info->n_slots = n_slots;
+  info->workspace_bytes = iso_workspace_layout(nullptr, n_slots, 1).bytes;
+  return hipMemcpy(plan, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess
+             ? SEM_OK
+             : SEM_ERR_HIP;
+}
+
+int sem_isosurface_batch(const void* plan, const sem_iso_batch_info* info, sem_dtype dt,
+                         void* tri_xyz, int64_t tri_capacity, int64_t* tri_offset,
+                         int64_t* tri_count, int64_t* active_cells, void* workspace,
+                         size_t workspace_bytes, int32_t* status_word, void* stream) {
+  if (!plan || !info || !tri_count) return SEM_ERR_ARG;
+  if ((dt != SEM_F64 && dt != SEM_F32) || dt != info->dt) return SEM_ERR_DTYPE;
+  if (info->n_job < 1 || info->n_job > kIsoBatchMaxJob || info->n_slots < 0) return SEM_ERR_ARG;
+  if (info->launch_code & ~(((1u << (kMaxOrder + 1)) - 1u) & ~1u)) return SEM_ERR_ARG;
+  if (tri_capacity < 0 || (tri_capacity > 0 && !tri_xyz)) return SEM_ERR_ARG;
+  IsoWorkspace ws = iso_workspace_layout(workspace, info->n_slots, 1);
+  if (!workspace || workspace_bytes < ws.bytes) return SEM_ERR_WORKSPACE;
+  const DeviceTables* tab = current_tables();
+  if (!tab) return SEM_ERR_NOT_INIT;
+  const hipError_t e = launch_iso_batch(dt, *tab, plan, info->launch_code, info->n_job,
+                                        info->n_slots, tri_xyz, tri_capacity, tri_offset,
+                                        tri_count, active_cells, ws, status_word,
+                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? SEM_OK : SEM_ERR_HIP;
+}
+
 int sem_autotune(int order, sem_dtype dt, int* variant_out, float* ms_out) {
   if (order < SEM_MIN_ORDER || order > SEM_MAX_ORDER) return SEM_ERR_ORDER;
   if (dt != SEM_F64 && dt != SEM_F32) return SEM_ERR_DTYPE;

@@ -102,6 +102,43 @@ int batch_default_variant(int order, sem_dtype dt);
 inline int launch_code_form(unsigned code, int n) { return (int)((code >> (3 * n)) & 7u) - 1; }
 hipError_t launch_qcrit_batch(sem_dtype dt, const void* plan, unsigned launch_code, int grid,
                               int32_t* status, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// Batched isosurfaces: a plan (device) holds a header and one descriptor
+// per job (one field of one snapshot at up to four isovalues), grouped by
+// order; persistent count and emission kernels walk each order's work
+// items (one element each).
+struct IsoBatchHeader {
+  int32_t n_job;
+  int32_t dt;
+  int32_t job_begin[kMaxOrder + 2];   // descriptors sorted by order: [begin(N), begin(N+1))
+  int64_t items[kMaxOrder + 1];       // work items of each order
+  int64_t n_slots;                    // count slots of every job
+};
+struct IsoBatchJob {
+  int64_t n_elem;
+  int64_t item_begin;   // first work item of this job among those of its order
+  int64_t slot_begin;   // count of (isovalue s, element e) at slot_begin + s * n_elem + e
+  int32_t order;
+  int32_t n_iso;        // 1..4
+  int32_t job;          // index in the caller's job array
+  int32_t pad;
+  const void* x;
+  const void* y;
+  const void* z;
+  const void* field;
+  const void* mm;       // element ranges of the field, or NULL
+  double isod[4];       // isovalues in the plan's precision
+  float isof[4];
+};
+static_assert(sizeof(IsoBatchHeader) <= 256, "header fits the plan's first 256 bytes");
+constexpr int kIsoBatchMaxJob = 16384;
+size_t iso_batch_plan_bytes(int n_job);
+// Launch code of an isosurface plan: bit N set when some job has order N.
+hipError_t launch_iso_batch(sem_dtype dt, const DeviceTables& tab, const void* plan,
+                            unsigned launch_code, int n_job, int64_t n_slots, void* tri,
+                            int64_t cap, int64_t* tri_offset, int64_t* tri_count,
+                            int64_t* active, const IsoWorkspace& ws, int32_t* status,
+                            hipStream_t s);
+
 // synthetic well-shaped elements for timing (x, y, z, u, v, w)
 hipError_t launch_tune_fill(sem_dtype dt, int order, int64_t n_elem, void* const* f,
                             hipStream_t s);

@@ -1732,13 +1732,32 @@ __device__ __forceinline__ void dma_tile_natural(const T* __restrict__ src, T* r
 
 // emit_direct<N, T>: the element's tiles and the case tables by direct loads,
 // two waves per element (odd N; N = 7 FP64 uses the swizzled tile).
+// Element tile of any order into LDS for two waves: direct loads where the
+// tile is a whole number of 16-byte chunks at a 16-byte aligned address
+// (odd N), plain loads otherwise.  Consumers wait with
+// s_waitcnt(vm, lgkm = 0) and a barrier.
 template <int N, typename T>
-__global__ void __launch_bounds__(128)
-emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
-            const T* __restrict__ z, const T* __restrict__ field, int n_iso,
-            IsoList<T> iso, IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
-            const int8_t* __restrict__ tri_tab, const int32_t* __restrict__ cnt,
-            const int64_t* __restrict__ offs, uint64_t* __restrict__ keys) {
+__device__ __forceinline__ void tile2_lds(const T* __restrict__ src, T* dst, int h, int lane) {
+  constexpr int NP = (N + 1) * (N + 1) * (N + 1);
+  if constexpr (N % 2 == 1) {
+    dma_tile_natural<N>(src, dst, h, lane);
+  } else {
+    for (int q = 64 * h + lane; q < NP; q += 128) dst[q] = src[q];
+  }
+}
+
+// Emission of element e (two waves): every isovalue with a nonzero count
+// writes its triangles at offs[s * n_elem + e] of out (or of out.ptr[s],
+// relative to the isovalue's first offset, when out.per_iso).
+template <int N, typename T, class IL = IsoList<T>, class OUT = IsoOut<T>>
+__device__ __forceinline__ void emit_elem(int64_t e, int t, int64_t n_elem,
+                                          const T* __restrict__ x, const T* __restrict__ y,
+                                          const T* __restrict__ z, const T* __restrict__ field,
+                                          int n_iso, const IL& iso, const OUT& out,
+                                          const uint8_t* __restrict__ ntri_tab,
+                                          const int32_t* __restrict__ cnt,
+                                          const int64_t* __restrict__ offs,
+                                          uint64_t* __restrict__ keys) {
   constexpr int P = N + 1, NP = P * P * P, NC = N * N * N;
   constexpr bool SWZ = N == 7 && std::is_same<T, double>::value;
   // The coordinate tiles are staged in LDS too, except for FP32 at N = 9,
@@ -1759,10 +1778,9 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
   __shared__ int32_t s_wave[2];
   const uint8_t* s_ntri = reinterpret_cast<const uint8_t*>(s_tab);
   const int8_t* s_tri = reinterpret_cast<const int8_t*>(s_tab) + 256;
-  const int t = threadIdx.x;
+  __builtin_assume(t >= 0 && t < 128);
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int p = t & 63;
-  const int64_t e = blockIdx.x;
   bool any = false;
   for (int s = 0; s < n_iso; ++s) any = any || cnt[(int64_t)s * n_elem + e] > 0;
   if (!any) return;
@@ -1779,11 +1797,11 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
     dma_tile(y + base, s_y, h, p);
     dma_tile(z + base, s_z, h, p);
   } else {
-    dma_tile_natural<N>(field + base, s_f, h, p);
+    tile2_lds<N>(field + base, s_f, h, p);
     if constexpr (XYZ) {
-      dma_tile_natural<N>(x + base, s_x, h, p);
-      dma_tile_natural<N>(y + base, s_y, h, p);
-      dma_tile_natural<N>(z + base, s_z, h, p);
+      tile2_lds<N>(x + base, s_x, h, p);
+      tile2_lds<N>(y + base, s_y, h, p);
+      tile2_lds<N>(z + base, s_z, h, p);
     }
   }
   const T* gx = XYZ ? s_x : x + base;
@@ -1813,25 +1831,37 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
   }
 }
 
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
+            const T* __restrict__ z, const T* __restrict__ field, int n_iso,
+            IsoList<T> iso, IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
+            const int32_t* __restrict__ cnt, const int64_t* __restrict__ offs,
+            uint64_t* __restrict__ keys) {
+  emit_elem<N, T>(blockIdx.x, threadIdx.x, n_elem, x, y, z, field, n_iso, iso, out, ntri_tab,
+                  cnt, offs, keys);
+}
+
 // count_direct<N, T>: the count pass of the two-pass isosurface for odd N:
 // the field tile (and the triangle-count table) by direct loads, two waves
 // per element, one packed block sum (triangles | active cells << 16) per
 // isovalue; elements the range excludes write zero counts without loading.
-template <int N, typename T>
-__global__ void __launch_bounds__(128)
-count_direct(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ mm,
-             int n_iso, IsoList<T> iso, const uint8_t* __restrict__ ntri_tab,
-             int32_t* __restrict__ cnt, int64_t* __restrict__ active_total,
-             uint8_t* __restrict__ case_idx) {
+template <int N, typename T, class IL = IsoList<T>>
+__device__ __forceinline__ void count_elem(int64_t e, int t, int64_t n_elem,
+                                           const T* __restrict__ field, const T* __restrict__ mm,
+                                           int n_iso, const IL& iso,
+                                           const uint8_t* __restrict__ ntri_tab,
+                                           int32_t* __restrict__ cnt,
+                                           int64_t* __restrict__ active_total,
+                                           uint8_t* __restrict__ case_idx) {
   constexpr int P = N + 1, NP = P * P * P, NC = N * N * N, R = (NC + 127) / 128;
   __shared__ __attribute__((aligned(16))) T sf[NP];
   __shared__ __attribute__((aligned(16))) uint8_t s_ntri[256];
   __shared__ T red[4];
   __shared__ int32_t s_sum[2];
-  const int t = threadIdx.x;
+  __builtin_assume(t >= 0 && t < 128);
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lane = t & 63;
-  const int64_t e = blockIdx.x;
   T mn = pos_inf<T>(), mx = neg_inf<T>();
   bool need = true;
   if (mm) {
@@ -1855,7 +1885,7 @@ count_direct(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ 
   if (h == 0 && lane < 16)
     lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * lane,
                reinterpret_cast<double*>(s_ntri));
-  dma_tile_natural<N>(field + e * NP, sf, h, lane);
+  tile2_lds<N>(field + e * NP, sf, h, lane);
   __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(0));
   barrier_after_wait();
   if (!mm) {
@@ -1916,6 +1946,16 @@ count_direct(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ 
     }
     __syncthreads();
   }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+count_direct(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ mm,
+             int n_iso, IsoList<T> iso, const uint8_t* __restrict__ ntri_tab,
+             int32_t* __restrict__ cnt, int64_t* __restrict__ active_total,
+             uint8_t* __restrict__ case_idx) {
+  count_elem<N, T>(blockIdx.x, threadIdx.x, n_elem, field, mm, n_iso, iso, ntri_tab, cnt,
+                   active_total, case_idx);
 }
 
 // ---------------------------------------------------------------------------
@@ -2439,6 +2479,145 @@ qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ s
   }
 }
 
+// ---------------------------------------------------------------------------
+// batched isosurfaces: persistent count and emission over (job, element)
+// ---------------------------------------------------------------------------
+//
+// A job is one field of one snapshot at up to four isovalues.  The plan
+// lists the jobs grouped by order; within an order, work item k is element
+// k - item_begin of the job whose item range holds k.  Count slots of a job
+// are [slot_begin, slot_begin + n_iso * n_elem), isovalue-major, so one
+// exclusive scan over every slot of every job gives each (job, isovalue,
+// element) its first triangle in one soup ordered by job, isovalue,
+// element, cell and slot.
+
+// Isovalues read through a pointer (the job descriptor's copy).
+template <typename T>
+struct IsoPtr {
+  const T* v;
+};
+
+// One soup with global offsets (the per-isovalue form of IsoOut is never
+// taken, so nothing is indexed by isovalue).
+template <typename T>
+struct SoupOut {
+  T* ptr[1];
+  int64_t cap[1];
+  static constexpr int per_iso = 0;
+};
+
+template <typename T>
+__device__ __forceinline__ const T* job_iso(const IsoBatchJob& jb);
+template <>
+__device__ __forceinline__ const double* job_iso<double>(const IsoBatchJob& jb) {
+  return jb.isod;
+}
+template <>
+__device__ __forceinline__ const float* job_iso<float>(const IsoBatchJob& jb) {
+  return jb.isof;
+}
+
+// The job descriptor a workgroup is in, kept in scalar registers and looked
+// up again (binary search over the jobs' first items) only when the work
+// item passes the next job's first item.
+template <typename T>
+struct JobCursor {
+  int cur = -1;
+  int64_t begin = 0, next_begin = 0, n_elem = 0, slot = 0;
+  int n_iso = 0, job = 0;
+  const T *x = nullptr, *y = nullptr, *z = nullptr, *field = nullptr, *mm = nullptr;
+  const T* iso = nullptr;
+
+  __device__ __forceinline__ void seek(const IsoBatchJob* __restrict__ jobs, int j0, int j1,
+                                       int64_t total, int64_t item) {
+    if (cur >= j0 && item < next_begin) return;
+    int lo = cur < j0 ? j0 : cur, hi = j1 - 1;   // last job with item_begin <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].item_begin <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    cur = __builtin_amdgcn_readfirstlane(lo);
+    const IsoBatchJob& jb = jobs[cur];
+    begin = uniform_i64(jb.item_begin);
+    next_begin = uniform_i64(cur + 1 < j1 ? jobs[cur + 1].item_begin : total);
+    n_elem = uniform_i64(jb.n_elem);
+    slot = uniform_i64(jb.slot_begin);
+    n_iso = __builtin_amdgcn_readfirstlane(jb.n_iso);
+    job = __builtin_amdgcn_readfirstlane(jb.job);
+    x = uniform_ptr(static_cast<const T*>(jb.x));
+    y = uniform_ptr(static_cast<const T*>(jb.y));
+    z = uniform_ptr(static_cast<const T*>(jb.z));
+    field = uniform_ptr(static_cast<const T*>(jb.field));
+    mm = uniform_ptr(static_cast<const T*>(jb.mm));
+    iso = uniform_ptr(job_iso<T>(jb));
+  }
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+iso_batch_count(const IsoBatchHeader* __restrict__ hdr, const IsoBatchJob* __restrict__ jobs,
+                const uint8_t* __restrict__ ntri_tab, int32_t* __restrict__ cnt,
+                int64_t* __restrict__ active) {
+  const int j0 = hdr->job_begin[N], j1 = hdr->job_begin[N + 1];
+  const int64_t total = hdr->items[N];
+  JobCursor<T> c;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    c.seek(jobs, j0, j1, total, item);
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    count_elem<N, T>(item - c.begin, t, c.n_elem, c.field, c.mm, c.n_iso, IsoPtr<T>{c.iso},
+                     ntri_tab, cnt + c.slot, active ? active + 4 * c.job : nullptr, nullptr);
+    __syncthreads();                   // the next item reuses the LDS
+  }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128)
+iso_batch_emit(const IsoBatchHeader* __restrict__ hdr, const IsoBatchJob* __restrict__ jobs,
+               const uint8_t* __restrict__ ntri_tab, const int32_t* __restrict__ cnt,
+               const int64_t* __restrict__ offs, T* __restrict__ tri, int64_t cap) {
+  const int j0 = hdr->job_begin[N], j1 = hdr->job_begin[N + 1];
+  const int64_t total = hdr->items[N];
+  SoupOut<T> out;
+  out.ptr[0] = tri;
+  out.cap[0] = cap;
+  JobCursor<T> c;
+  for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+    c.seek(jobs, j0, j1, total, item);
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    emit_elem<N, T>(item - c.begin, t, c.n_elem, c.x, c.y, c.z, c.field, c.n_iso,
+                    IsoPtr<T>{c.iso}, out, ntri_tab, cnt + c.slot, offs + c.slot, nullptr);
+    __syncthreads();
+  }
+}
+
+// Per (job, isovalue): first triangle and count (isovalues past a job's
+// n_iso get count 0 at the job's end); the overflow flag if the soup does
+// not fit.
+__global__ void __launch_bounds__(256)
+iso_batch_totals(const IsoBatchHeader* __restrict__ hdr, const IsoBatchJob* __restrict__ jobs,
+                 const int64_t* __restrict__ offs, int64_t* __restrict__ tri_offset,
+                 int64_t* __restrict__ tri_count, int64_t cap, int32_t* __restrict__ status) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx < 4 * hdr->n_job) {
+    const IsoBatchJob& jb = jobs[idx >> 2];
+    const int s = idx & 3;
+    const int64_t lo = jb.slot_begin + (int64_t)(s < jb.n_iso ? s : jb.n_iso) * jb.n_elem;
+    const int64_t hi = s < jb.n_iso ? lo + jb.n_elem : lo;
+    if (tri_offset) tri_offset[4 * jb.job + s] = offs[lo];
+    tri_count[4 * jb.job + s] = offs[hi] - offs[lo];
+  }
+  if (idx == 0 && status && offs[hdr->n_slots] > cap) atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
+}
+
+__global__ void __launch_bounds__(256) fill_i64_n(int64_t* __restrict__ p, int64_t n,
+                                                  int64_t value) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
 // Synthetic unit-cube elements on a 16 x 16 x ... lattice with node
 // spacing 1/N and a smooth velocity: timing input for the autotuner.
 template <typename T>
@@ -2615,7 +2794,7 @@ hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, con
     if constexpr (N % 2 == 1) {
       hipExtLaunchKernelGGL((emit_direct<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
                             pe.start, pe.stop, 0, n_elem, (const T*)x, (const T*)y,
-                            (const T*)z, (const T*)field, n_iso, iso, out, tab.ntri, tab.tri,
+                            (const T*)z, (const T*)field, n_iso, iso, out, tab.ntri,
                             (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys);
     } else {
       hipExtLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem),
@@ -2885,6 +3064,99 @@ hipError_t launch_qcrit_batch(sem_dtype dt, const void* plan, unsigned launch_co
     const hipError_t err = hipExtLaunchKernel(fn, dim3(batch_grid(fn, threads, cu_count)),
                                               dim3(threads), args, 0, s, a, b, 0);
     if (err != hipSuccess) return err;
+  }
+  return hipGetLastError();
+}
+
+size_t iso_batch_plan_bytes(int n_job) {
+  return 256 + (((size_t)n_job * sizeof(IsoBatchJob) + 255) & ~size_t(255));
+}
+
+namespace {
+template <int N>
+hipError_t iso_batch_phase(bool f64, bool emit, const IsoBatchHeader* hdr,
+                           const IsoBatchJob* jobs, const DeviceTables& tab,
+                           const IsoWorkspace& ws, int64_t* active, void* tri, int64_t cap,
+                           hipStream_t s, hipEvent_t a, hipEvent_t b) {
+  const void* fn;
+  if (emit)
+    fn = f64 ? reinterpret_cast<const void*>(&iso_batch_emit<N, double>)
+             : reinterpret_cast<const void*>(&iso_batch_emit<N, float>);
+  else
+    fn = f64 ? reinterpret_cast<const void*>(&iso_batch_count<N, double>)
+             : reinterpret_cast<const void*>(&iso_batch_count<N, float>);
+  const uint8_t* ntri = tab.ntri;
+  int32_t* cnt = ws.cnt;
+  int64_t* offs = ws.offs;
+  void* count_args[] = {&hdr, &jobs, &ntri, &cnt, &active};
+  void* emit_args[] = {&hdr, &jobs, &ntri, &cnt, &offs, &tri, &cap};
+  // Four times the workgroups the CUs hold at once: the cost of an element
+  // varies with its triangles, and with a grid of exactly the resident
+  // workgroups the unluckiest one sets the end (measured on the batched
+  // benchmark snapshots: 4.54 ms at 1x, 3.58 at 4x, 3.60 at 16x, 3.84 at 64x;
+  // 48 separate sem_isosurface calls: 4.4 ms).  Workgroups that start later
+  // take the slots the early finishers free.
+  return hipExtLaunchKernel(fn, dim3(4 * batch_grid(fn, 128, tab.cu_count)), dim3(128),
+                            emit ? emit_args : count_args, 0, s, a, b, 0);
+}
+}  // namespace
+
+hipError_t launch_iso_batch(sem_dtype dt, const DeviceTables& tab, const void* plan,
+                            unsigned launch_code, int n_job, int64_t n_slots, void* tri,
+                            int64_t cap, int64_t* tri_offset, int64_t* tri_count,
+                            int64_t* active, const IsoWorkspace& ws, int32_t* status,
+                            hipStream_t s) {
+  const IsoBatchHeader* hdr = static_cast<const IsoBatchHeader*>(plan);
+  const IsoBatchJob* jobs =
+      reinterpret_cast<const IsoBatchJob*>(static_cast<const char*>(plan) + 256);
+  const bool f64 = dt == SEM_F64;
+  if (active && n_job > 0)
+    hipLaunchKernelGGL(fill_i64_n, dim3((unsigned)((4 * (int64_t)n_job + 255) / 256)), dim3(256),
+                       0, s, active, 4 * (int64_t)n_job, (int64_t)0);
+  int first = -1, last = -1;
+  for (int n = 1; n <= kMaxOrder; ++n)
+    if (launch_code >> n & 1u) {
+      if (first < 0) first = n;
+      last = n;
+    }
+  for (int pass = 0; pass < 2; ++pass) {
+    const PhaseTimer pt = phase_timer(pass == 0 ? SEM_PHASE_COUNT : SEM_PHASE_EMIT);
+    for (int n = first; n >= 1 && n <= last; ++n) {
+      if (!(launch_code >> n & 1u)) continue;
+      hipEvent_t a = n == first ? pt.start : nullptr, b = n == last ? pt.stop : nullptr;
+      hipError_t err = hipSuccess;
+      switch (n) {
+        case 1: err = iso_batch_phase<1>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 2: err = iso_batch_phase<2>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 3: err = iso_batch_phase<3>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 4: err = iso_batch_phase<4>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 5: err = iso_batch_phase<5>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 6: err = iso_batch_phase<6>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 7: err = iso_batch_phase<7>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 8: err = iso_batch_phase<8>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        case 9: err = iso_batch_phase<9>(f64, pass, hdr, jobs, tab, ws, active, tri, cap, s, a, b); break;
+        default: err = hipErrorInvalidValue;
+      }
+      if (err != hipSuccess) return err;
+    }
+    phase_done(pt);
+    if (pass == 0) {
+      // one exclusive scan over every count slot, then the per-(job,
+      // isovalue) totals
+      const PhaseTimer ps = phase_timer(SEM_PHASE_SCAN);
+      const int64_t nb = scan_blocks(n_slots);
+      hipExtLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ps.start,
+                            nullptr, 0, ws.cnt, n_slots, ws.partial);
+      hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, ws.partial, nb);
+      hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.cnt,
+                         n_slots, ws.partial, nb, ws.offs);
+      const unsigned tb = (unsigned)((4 * (int64_t)n_job + 255) / 256);
+      hipExtLaunchKernelGGL(iso_batch_totals, dim3(tb > 0 ? tb : 1), dim3(256), 0, s, nullptr,
+                            ps.stop, 0, hdr, jobs, (const int64_t*)ws.offs, tri_offset,
+                            tri_count, cap, status);
+      phase_done(ps);
+      if (cap <= 0) break;
+    }
   }
   return hipGetLastError();
 }
