@@ -1505,6 +1505,17 @@ __device__ __forceinline__ int wave_sum_i32(const WaveXor& w, int v) {
   return v;
 }
 
+// Sum over the 16 lanes of each row of the wave, by DPP row shifts (lanes
+// shifted in from outside the row read 0): lane 15 of the row ends with the
+// row's sum (the others with partial sums).  Four VALU operations, no LDS.
+__device__ __forceinline__ uint32_t row_sum16(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  return v;
+}
+
 // COUNT: also count every isovalue's triangles and active cells per element
 // from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
 template <bool COUNT>
@@ -1523,7 +1534,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
   __shared__ double s_S[Pen<7>::SZ];
   __shared__ double s_T[Pen<7>::SZ];
   __shared__ double s_red[8];
-  __shared__ int32_t s_wave[16];
+  __shared__ uint32_t s_rows[32];
   const int h = __builtin_amdgcn_readfirstlane(t >> 6);
   const int p = t & 63;
   const int64_t base = e * 512;
@@ -1618,17 +1629,18 @@ __device__ __forceinline__ void qcount_dma7_elem(
   // (Q > c_s) at bit 8s, so the eight corner words of a cell, each shifted
   // by its vertex number and summed, give the four cell cases as bytes. The
   // derivative tiles are free now: S holds the node words, T the case table
-  // as triangles + (1 << 16) per non-trivial case.
+  // as triangles + (1 << 8) per non-trivial case.
   uint32_t* s_bits = reinterpret_cast<uint32_t*>(s_S);
   int32_t* s_tab = reinterpret_cast<int32_t*>(s_T);
   const int node0 = h + 8 * j + 64 * k, node1 = 7 - h + 8 * j + 64 * k;
   if constexpr (COUNT) {
-    s_tab[t] = (int)nt_own + ((t != 0 && t != 255) << 16);
+    s_tab[t] = (int)nt_own + ((t != 0 && t != 255) << 8);
     s_bits[node0] = iso_bits4(qv[0], iso, 0, n_iso);
     s_bits[node1] = iso_bits4(qv[1], iso, 0, n_iso);
   }
-  bad = __syncthreads_or(bad);   // also publishes the tiles, s_red and the node words
-  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  // an inverted element (rare) is flagged by its own lanes: no block vote
+  if (bad && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  __syncthreads();               // publishes the tiles, s_red and the node words
   {
     // node pair (2t, 2t + 1) of the natural layout sits in one 16-byte slot
     const int n = 2 * t;
@@ -1650,8 +1662,11 @@ __device__ __forceinline__ void qcount_dma7_elem(
     constexpr int NC2 = NC - 256;
     const bool two = t < NC2;
     const int c1 = two ? t + 256 : t;
-    const int cb[2] = {t % 7 + 8 * ((t / 7) % 7) + 64 * (t / 49),
-                       c1 % 7 + 8 * ((c1 / 7) % 7) + 64 * (c1 / 49)};
+    // cell c = i + 7 j + 49 k has corner 0 at node i + 8 j + 64 k =
+    // c + c / 7 + 8 (c / 49); the divisions by multiply and shift (exact for
+    // c < 512: the rounding errors stay below the gap to the next integer)
+    const int cb[2] = {t + ((t * 9363) >> 16) + 8 * ((t * 1338) >> 16),
+                       c1 + ((c1 * 9363) >> 16) + 8 * ((c1 * 1338) >> 16)};
     for (int g = 0; g < n_iso; g += 4) {
       const int m = n_iso - g < 4 ? n_iso - g : 4;
       if (g > 0) {   // every read of the previous words is behind the last barrier
@@ -1663,7 +1678,10 @@ __device__ __forceinline__ void qcount_dma7_elem(
       // trivial cases (NaN nodes count as below; mn is -inf then)
       bool live = false;
       for (int s = 0; s < m; ++s) live |= (mx > iso.v[g + s]) && !(mn > iso.v[g + s]);
-      int packed[4] = {0, 0, 0, 0};
+      // A lane's cells give, per isovalue s, triangles + (active << 8) in
+      // the 16-bit half s & 1 of word s >> 1 (at most 2 cells x 5 triangles
+      // per lane, so a row of 16 lanes stays below 160 + (32 << 8)).
+      uint32_t pw[2] = {0u, 0u};
       if (live) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
@@ -1675,23 +1693,27 @@ __device__ __forceinline__ void qcount_dma7_elem(
           if (r == 0 || two) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-              if (s < m) packed[s] += s_tab[(word >> (8 * s)) & 255];
+              if (s < m) pw[s >> 1] += (uint32_t)s_tab[(word >> (8 * s)) & 255] << (16 * (s & 1));
           }
         }
       }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        if (s < m) {
-          const int sum = wave_sum_i32(wx, packed[s]);
-          if (p == 0) s_wave[4 * s + h] = sum;
-        }
+      // row sums, then the 16 rows of the element's four waves in wave 0
+      pw[0] = row_sum16(pw[0]);
+      if (m > 2) pw[1] = row_sum16(pw[1]);
+      if ((p & 15) == 15) {
+        s_rows[2 * (4 * h + (p >> 4))] = pw[0];
+        s_rows[2 * (4 * h + (p >> 4)) + 1] = pw[1];
       }
       __syncthreads();
-      if (t < m) {
-        const int sum = s_wave[4 * t] + s_wave[4 * t + 1] + s_wave[4 * t + 2] + s_wave[4 * t + 3];
-        cnt[(int64_t)(g + t) * n_elem + e] = sum & 0xffff;
-        const int a = sum >> 16;
-        if (active && a) atomicAdd((unsigned long long*)&active[g + t], (unsigned long long)a);
+      if (h == 0) {
+        const int row = p & 15, s = p >> 4;   // lane: one row's field of isovalue s
+        const uint32_t f = (s_rows[2 * row + (s >> 1)] >> (16 * (s & 1))) & 0xffffu;
+        const uint32_t sum = row_sum16((f & 255u) | ((f >> 8) << 16));
+        if (row == 15 && s < m) {
+          cnt[(int64_t)(g + s) * n_elem + e] = (int)(sum & 0xffffu);
+          const unsigned a = sum >> 16;
+          if (active && a) atomicAdd((unsigned long long*)&active[g + s], (unsigned long long)a);
+        }
       }
     }
   }
