@@ -25,7 +25,14 @@ direction, and every step below is a textbook definition:
 * Latent stored in IEEE binary16 (round to nearest even); training passes
   the rounded latent forward and its gradient through unchanged (the
   straight-through estimator, Bengio, Leonard & Courville 2013).
-* Loss: mean squared error over every value of the batch's blocks.
+* Loss: mean squared error over every value of the batch's blocks; or the
+  max-error loss, the mean over (block, channel) of the squared largest
+  absolute error over the block's 512 nodes, the smooth-in-the-square form
+  of the relative L-inf bound that decides the raw fallback below.  Its
+  gradient at a (block, channel) is 2 m sign(y - x) / (blocks x channels)
+  at the node(s) where |y - x| reaches the maximum m, shared equally when
+  several nodes tie (a subgradient, independent of the node order), and 0
+  elsewhere.
 * Gradients by the chain rule (reverse mode), written out per layer.
 * Optimiser: Adam (Kingma & Ba 2015, algorithm 1).
 * Initialisation by layer-wise principal components (uncentred; in the
@@ -64,6 +71,8 @@ LATENT = 32
 ARCH = (("conv", 4, 32), ("conv", 32, 64), ("conv", 64, 32),
         ("convT", 32, 64), ("convT", 64, 32), ("convT", 32, 4))
 LATENT_LAYER = 2
+LOSS_MSE = 0            # mean squared error
+LOSS_MAX = 1            # mean squared per-(block, channel) maximum error
 TANH_NONE = 0           # the library's network: every layer linear
 TANH_HIDDEN = 0b011011  # tanh after layers 0, 1, 3, 4 (not the latent or output)
 REL_BOUND = 1e-3
@@ -197,16 +206,34 @@ def forward(params, x, quantize=True, tanh_mask=TANH_NONE):
     return acts
 
 
-def loss(out, x):
-    return float(np.mean((out - np.asarray(x, dtype=np.float64)) ** 2))
+def loss(out, x, kind=LOSS_MSE):
+    d = out - np.asarray(x, dtype=np.float64)
+    if kind == LOSS_MAX:
+        m = np.abs(d).reshape(d.shape[0], CHANNELS, -1).max(axis=2)
+        return float(np.mean(m ** 2))
+    return float(np.mean(d ** 2))
 
 
-def gradient(params, x, quantize=True, tanh_mask=TANH_NONE):
+def loss_gradient(out, x, kind=LOSS_MSE):
+    """dL/d(out) of ``loss``."""
+    d = out - np.asarray(x, dtype=np.float64)
+    if kind != LOSS_MAX:
+        return 2.0 * d / d.size
+    a = np.abs(d).reshape(d.shape[0], CHANNELS, -1)
+    m = a.max(axis=2, keepdims=True)
+    top = (a == m) & (m > 0)
+    ties = np.maximum(top.sum(axis=2, keepdims=True), 1)
+    g = np.where(top, 2.0 * m * np.sign(d.reshape(a.shape)) / (d.shape[0] * CHANNELS) / ties,
+                 0.0)
+    return g.reshape(d.shape)
+
+
+def gradient(params, x, quantize=True, tanh_mask=TANH_NONE, loss_kind=LOSS_MSE):
     """(loss, dL/dparams) for the batch x, by reverse mode."""
     x = np.asarray(x, dtype=np.float64)
     acts = forward(params, x, quantize, tanh_mask)
     layers = unpack(params)
-    g = 2.0 * (acts[-1] - x) / x.size
+    g = loss_gradient(acts[-1], x, loss_kind)
     grads = [None] * len(ARCH)
     for l in range(len(ARCH) - 1, -1, -1):
         kind = ARCH[l][0]
@@ -216,7 +243,7 @@ def gradient(params, x, quantize=True, tanh_mask=TANH_NONE):
         gx, gw, gb = (conv_grads if kind == "conv" else conv_t_grads)(acts[l], w, g)
         grads[l] = (gw, gb)
         g = gx                     # straight through the latent rounding
-    return loss(acts[-1], x), pack(grads)
+    return loss(acts[-1], x, loss_kind), pack(grads)
 
 
 def adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

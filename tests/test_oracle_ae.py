@@ -103,6 +103,58 @@ def test_gradient_matches_central_differences(mask):
     assert abs(fd - g @ d) <= 1e-6 * abs(fd)
 
 
+def test_max_loss_gradient_matches_central_differences():
+    """Away from ties (random data has none) the max-error loss is smooth,
+    so central differences pin its gradient, bias terms included."""
+    p = _small_params(5)
+    x = RNG.uniform(-1, 1, size=(3, 4, 8, 8, 8))
+    _, g = ae.gradient(p, x, quantize=False, loss_kind=ae.LOSS_MAX)
+
+    def lf(q):
+        return ae.loss(ae.forward(q, x, False)[-1], x, ae.LOSS_MAX)
+
+    h = 1e-6
+    idx = np.concatenate([RNG.choice(p.size, 40, replace=False),
+                          np.cumsum([0] + [w + b for w, b in ae.layer_sizes()][:-1])
+                          + np.array([w for w, _ in ae.layer_sizes()])])
+    for k in idx:
+        e = np.zeros_like(p)
+        e[k] = h
+        fd = (lf(p + e) - lf(p - e)) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-5 * abs(fd) + 1e-9, k
+    d = RNG.normal(size=p.size)
+    fd = (lf(p + h * d) - lf(p - h * d)) / (2 * h)
+    assert abs(fd - g @ d) <= 1e-5 * abs(fd)
+
+
+def test_max_loss_closed_form_and_tie_split():
+    """One block, two channels with errors: the loss is the mean over the
+    four channels of the squared maxima; two tied maxima share the gradient
+    equally, so moving both outward by eps raises the loss by the
+    directional derivative 2 m eps / 4 to first order."""
+    x = np.zeros((1, 4, 8, 8, 8))
+    out = np.zeros_like(x)
+    out[0, 0, 1, 2, 3] = 0.3
+    out[0, 0, 4, 4, 4] = -0.1
+    out[0, 2, 0, 0, 0] = -0.5
+    out[0, 2, 7, 7, 7] = 0.5          # tie with the node above at |d| = 0.5
+    assert ae.loss(out, x, ae.LOSS_MAX) == pytest.approx((0.3 ** 2 + 0.5 ** 2) / 4)
+    g = ae.loss_gradient(out, x, ae.LOSS_MAX)
+    assert g[0, 0, 1, 2, 3] == pytest.approx(2 * 0.3 / 4)
+    assert g[0, 0, 4, 4, 4] == 0.0
+    assert g[0, 2, 0, 0, 0] == pytest.approx(-2 * 0.5 / 4 / 2)
+    assert g[0, 2, 7, 7, 7] == pytest.approx(2 * 0.5 / 4 / 2)
+    assert np.count_nonzero(g) == 3
+    eps = 1e-7
+    moved = out.copy()
+    moved[0, 2, 0, 0, 0] -= eps
+    moved[0, 2, 7, 7, 7] += eps
+    rise = ae.loss(moved, x, ae.LOSS_MAX) - ae.loss(out, x, ae.LOSS_MAX)
+    assert rise == pytest.approx(-g[0, 2, 0, 0, 0] * eps + g[0, 2, 7, 7, 7] * eps, rel=1e-5)
+    # a block without error has zero gradient
+    assert not ae.loss_gradient(x, x, ae.LOSS_MAX).any()
+
+
 def test_straight_through_gradient_when_rounding_is_exact():
     p = _small_params(5)
     # latent layer: zero weights, biases exactly representable in binary16

@@ -372,3 +372,48 @@ def test_pca_init_with_trailing_eigenvectors_is_caught():
         return lam[:r], u[:, :r]                        # smallest, not largest
     with patched(ae, "_leading_eigvecs", bad):
         _fails(T.test_pca_init_is_exact_on_data_of_low_rank)
+
+
+def _max_loss_gradient(factor, split):
+    """The max-error loss gradient with a planted slip: a scale `factor`
+    on 2 m sign(d), and tied maxima either shared (`split`) or each given
+    the full amount."""
+    from oracle import ae
+
+    def bad(out, x, kind=ae.LOSS_MSE):
+        d = out - np.asarray(x, dtype=np.float64)
+        if kind != ae.LOSS_MAX:
+            return 2.0 * d / d.size
+        a = np.abs(d).reshape(d.shape[0], ae.CHANNELS, -1)
+        m = a.max(axis=2, keepdims=True)
+        top = (a == m) & (m > 0)
+        ties = np.maximum(top.sum(axis=2, keepdims=True), 1) if split else 1
+        g = np.where(top, factor * m * np.sign(d.reshape(a.shape))
+                     / (d.shape[0] * ae.CHANNELS) / ties, 0.0)
+        return g.reshape(d.shape)
+    return bad
+
+
+def test_max_loss_gradient_without_the_factor_two_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+    with patched(ae, "loss_gradient", _max_loss_gradient(1.0, True)):
+        _fails(T.test_max_loss_gradient_matches_central_differences)
+
+
+def test_max_loss_gradient_with_flipped_sign_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+    with patched(ae, "loss_gradient", _max_loss_gradient(-2.0, True)):
+        _fails(T.test_max_loss_gradient_matches_central_differences)
+
+
+def test_max_loss_gradient_without_the_tie_split_is_caught():
+    import test_oracle_ae as T
+    from oracle import ae
+    with patched(ae, "loss_gradient", _max_loss_gradient(2.0, False)):
+        _fails(T.test_max_loss_closed_form_and_tie_split)
+    # the unplanted form passes both pins
+    with patched(ae, "loss_gradient", _max_loss_gradient(2.0, True)):
+        T.test_max_loss_closed_form_and_tie_split()
+        T.test_max_loss_gradient_matches_central_differences()
