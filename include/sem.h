@@ -517,13 +517,21 @@ int sem_ae_forward(int64_t n, const float* blocks, const float* params, int tanh
                    float* recon, uint16_t* latent, void* workspace, size_t workspace_bytes,
                    void* stream);
 
-/* Mean-squared-error loss (*loss, device float, may be NULL) and its
- * gradient grad[sem_ae_param_count()] on the batch pool[idx[r]], r < n (idx
- * NULL: the first n blocks of the pool).  The latent is rounded to binary16
- * in the forward pass and its gradient passed through unchanged.  An index
- * outside [0, n_pool) sets SEM_FLAG_BAD_ID and contributes a zero block. */
+/* Loss (*loss, device float, may be NULL) and its gradient
+ * grad[sem_ae_param_count()] on the batch pool[idx[r]], r < n (idx NULL:
+ * the first n blocks of the pool).  loss_kind SEM_AE_LOSS_MSE: mean squared
+ * error over every value; SEM_AE_LOSS_MAX: mean over (block, channel) of
+ * the squared largest absolute error over the block's nodes (the squared
+ * form of the relative L-inf bound of the raw fallback), whose gradient
+ * 2 m sign(y - x) / (4 n) sits at the node(s) of the maximum m, shared
+ * equally by ties; any other value is SEM_ERR_ARG.  The latent is rounded
+ * to binary16 in the forward pass and its gradient passed through
+ * unchanged.  An index outside [0, n_pool) sets SEM_FLAG_BAD_ID and
+ * contributes a zero block. */
+#define SEM_AE_LOSS_MSE 0
+#define SEM_AE_LOSS_MAX 1
 int sem_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
-                const float* params, int tanh_mask, float* grad, float* loss,
+                const float* params, int tanh_mask, int loss_kind, float* grad, float* loss,
                 void* workspace, size_t workspace_bytes, int32_t* status_word, void* stream);
 
 /* One Adam step (Kingma & Ba 2015) on n values; step counts from 1. */

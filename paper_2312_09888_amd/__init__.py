@@ -13,7 +13,7 @@ from ._lib import (  # noqa: F401
     init, isosurface, isosurface_into, lib, mc_table, phase_name, qcrit, status_str,
     timing_begin, timing_end, workspace_bytes, GatherScatter, dsavg, global_edge_keys, weld,
     SEM_FLAG_BAD_ID, SEM_FLAG_VERT_OVERFLOW, BatchPlan, qcrit_batch, autotune, batch_variant,
-    batch_set_variant, BATCH_VARIANTS, SEM_FLAG_RAW_OVERFLOW, SEM_AE_LATENT, SEM_AE_TANH_HIDDEN,
+    batch_set_variant, BATCH_VARIANTS, SEM_FLAG_RAW_OVERFLOW, SEM_AE_LATENT, SEM_AE_TANH_HIDDEN, SEM_AE_LOSS_MSE, SEM_AE_LOSS_MAX,
     ae_param_count, ae_blocks, ae_forward, ae_grad, ae_adam, sym_eig, ae_pca_init, ae_train,
     ae_compress, ae_decompress, modal_compress, compressed_bytes, stream_copy,
     extract_noalloc_into, SEM_NOALLOC_MAX_COUNTS, IsoBatchPlan, isosurface_batch,

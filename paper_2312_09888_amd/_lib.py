@@ -8,6 +8,7 @@ fails to load, every entry point raises.
 """
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -29,6 +30,7 @@ SEM_NOALLOC_MAX_COUNTS = 1 << 20   # n_iso * n_elem of sem_extract_noalloc
 SEM_FLAG_RAW_OVERFLOW = 16
 SEM_AE_LATENT = 32
 SEM_AE_TANH_HIDDEN = 0x1B
+SEM_AE_LOSS_MSE, SEM_AE_LOSS_MAX = 0, 1
 BATCH_VARIANTS = 6          # variants of the batched kernel (sem_autotune)
 SEM_MC_MAX_TRI = 5
 SEM_PHASE_QCRIT, SEM_PHASE_COUNT, SEM_PHASE_SCAN, SEM_PHASE_EMIT = 0, 1, 2, 3
@@ -170,7 +172,7 @@ def lib():
         L.sem_ae_forward.restype = i32
         L.sem_ae_forward.argtypes = [i64, vp, vp, i32, vp, vp, vp, sz, vp]
         L.sem_ae_grad.restype = i32
-        L.sem_ae_grad.argtypes = [i64, vp, i64, vp, vp, i32, vp, vp, vp, sz, vp, vp]
+        L.sem_ae_grad.argtypes = [i64, vp, i64, vp, vp, i32, i32, vp, vp, vp, sz, vp, vp]
         L.sem_ae_adam.restype = i32
         L.sem_ae_adam.argtypes = [i64, vp, vp, vp, vp, i32, flt, flt, flt, flt, vp]
         L.sem_eig_workspace_bytes.restype = sz
@@ -922,8 +924,9 @@ def ae_forward(blocks, params, tanh_mask=0):
 
 
 def ae_grad(pool, params, idx=None, n=None, tanh_mask=0, grad=None, workspace=None,
-            status=None):
-    """(loss [1] float32, grad) of the batch pool[idx] (or the first n)."""
+            status=None, loss_kind=SEM_AE_LOSS_MSE):
+    """(loss [1] float32, grad) of the batch pool[idx] (or the first n);
+    loss_kind SEM_AE_LOSS_MSE or SEM_AE_LOSS_MAX."""
     torch = _torch()
     if idx is not None:
         if idx.dtype != torch.int64 or not idx.is_contiguous():
@@ -937,7 +940,7 @@ def ae_grad(pool, params, idx=None, n=None, tanh_mask=0, grad=None, workspace=No
     if workspace is None:
         workspace = _ws(lib().sem_ae_workspace_bytes(n), pool)
     _check(lib().sem_ae_grad(n, pool.data_ptr(), pool.shape[0], _ptr(idx), params.data_ptr(),
-                             int(tanh_mask), grad.data_ptr(), loss.data_ptr(),
+                             int(tanh_mask), int(loss_kind), grad.data_ptr(), loss.data_ptr(),
                              workspace.data_ptr(), workspace.numel(), _ptr(status),
                              _stream(pool)), "sem_ae_grad")
     return loss, grad
@@ -980,9 +983,12 @@ def ae_pca_init(pool):
 
 
 def ae_train(pool, params, steps, batch=2048, lr=1e-4, seed=0, tanh_mask=0, m=None, v=None,
-             step0=0, loss_every=0):
-    """Adam on the mean-squared error of random batches of the pool (indices
-    drawn on the device from a seeded generator); returns (m, v, losses)."""
+             step0=0, loss_every=0, loss_kind=SEM_AE_LOSS_MSE, warmup=0, cosine=False):
+    """Adam on the loss of random batches of the pool (indices drawn on the
+    device from a seeded generator), the library's gradient and Adam
+    kernels; learning rate lr, optionally ramped up linearly over `warmup`
+    steps and decayed along a half cosine to 0 at `steps`; returns (m, v,
+    losses)."""
     torch = _torch()
     if m is None:
         m = torch.zeros_like(params)
@@ -994,8 +1000,12 @@ def ae_train(pool, params, steps, batch=2048, lr=1e-4, seed=0, tanh_mask=0, m=No
     losses = []
     for t in range(1, steps + 1):
         idx = torch.randint(0, pool.shape[0], (batch,), device=pool.device, generator=gen)
-        loss, _ = ae_grad(pool, params, idx=idx, tanh_mask=tanh_mask, grad=grad, workspace=ws)
-        ae_adam(params, grad, m, v, step0 + t, lr)
+        loss, _ = ae_grad(pool, params, idx=idx, tanh_mask=tanh_mask, grad=grad, workspace=ws,
+                          loss_kind=loss_kind)
+        rate = lr * (min(1.0, t / warmup) if warmup else 1.0)
+        if cosine:
+            rate *= 0.5 * (1.0 + math.cos(math.pi * (t - 1) / steps))
+        ae_adam(params, grad, m, v, step0 + t, rate)
         if loss_every and (t % loss_every == 0 or t == steps):
             losses.append((t, float(loss.item())))
     return m, v, losses

@@ -310,6 +310,55 @@ out_grad(const float* __restrict__ y, const float* __restrict__ x, int64_t n, fl
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Max-error loss, one block of 512 nodes x 4 channels per workgroup: per
+// channel m = max |y - x| over the nodes; part[b] = sum_c m^2; the gradient
+// is inv2 m sign(y - x) at the nodes where |y - x| = m (shared equally by
+// tied nodes; none when m = 0), 0 elsewhere.  inv2 = 2 / (blocks x 4).
+__global__ void __launch_bounds__(kT)
+out_grad_max(const float* __restrict__ y, const float* __restrict__ x, float inv2,
+             float* __restrict__ g, double* __restrict__ part) {
+  __shared__ float red[kT / 64];
+  __shared__ int ired[kT / 64];
+  const int64_t b = blockIdx.x;
+  const float4* yb = reinterpret_cast<const float4*>(y + b * 2048);
+  const float4* xb = reinterpret_cast<const float4*>(x + b * 2048);
+  float4* gb = reinterpret_cast<float4*>(g + b * 2048);
+  float d[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const float4 a = yb[threadIdx.x + 256 * h], c = xb[threadIdx.x + 256 * h];
+    d[h][0] = a.x - c.x;
+    d[h][1] = a.y - c.y;
+    d[h][2] = a.z - c.z;
+    d[h][3] = a.w - c.w;
+  }
+  float m[4], share[4];
+  double sq = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float a0 = fabsf(d[0][c]), a1 = fabsf(d[1][c]);
+    m[c] = block_max_pos(a0 > a1 ? a0 : a1, red);
+    int k = (a0 == m[c]) + (a1 == m[c]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) k += __shfl_xor(k, off);
+    if ((threadIdx.x & 63) == 0) ired[threadIdx.x >> 6] = k;
+    __syncthreads();
+    k = ired[0] + ired[1] + ired[2] + ired[3];
+    __syncthreads();
+    share[c] = m[c] > 0.f ? inv2 * m[c] / (float)k : 0.f;
+    sq += (double)m[c] * m[c];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float o[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      o[c] = (m[c] > 0.f && fabsf(d[h][c]) == m[c]) ? copysignf(share[c], d[h][c]) : 0.f;
+    gb[threadIdx.x + 256 * h] = make_float4(o[0], o[1], o[2], o[3]);
+  }
+  if (threadIdx.x == 0) part[b] = sq;
+}
+
 __global__ void __launch_bounds__(1024)
 loss_reduce(const double* __restrict__ part, int64_t nb, double inv_n, float* __restrict__ loss) {
   __shared__ double red[16];
@@ -928,21 +977,29 @@ hipError_t launch_ae_forward(int64_t n, const float* blocks, const float* params
 }
 
 hipError_t launch_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
-                          const float* params, int tanh_mask, float* grad, float* loss,
-                          void* ws, int32_t* status, hipStream_t s) {
+                          const float* params, int tanh_mask, int loss_kind, float* grad,
+                          float* loss, void* ws, int32_t* status, hipStream_t s) {
   AeWs w = ae_layout(ws, n);
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(gather_blocks, dim3((unsigned)n), dim3(kT), 0, s, pool, idx, n, n_pool,
                      w.act[0], status);
   hipError_t e = forward_all(n, params, tanh_mask, w, s);
   if (e != hipSuccess) return e;
-  const int64_t cnt = n * 2048;
-  const int64_t nb = cdiv(cnt, kT);
-  hipLaunchKernelGGL(out_grad, dim3((unsigned)nb), dim3(kT), 0, s, w.act[kLayers], w.act[0], cnt,
-                     (float)(2.0 / (double)cnt), w.g0, w.lpart);
-  if (loss)
-    hipLaunchKernelGGL(loss_reduce, dim3(1), dim3(1024), 0, s, w.lpart, nb, 1.0 / (double)cnt,
-                       loss);
+  if (loss_kind == SEM_AE_LOSS_MAX) {
+    hipLaunchKernelGGL(out_grad_max, dim3((unsigned)n), dim3(kT), 0, s, w.act[kLayers],
+                       w.act[0], (float)(2.0 / (4.0 * (double)n)), w.g0, w.lpart);
+    if (loss)
+      hipLaunchKernelGGL(loss_reduce, dim3(1), dim3(1024), 0, s, w.lpart, n,
+                         1.0 / (4.0 * (double)n), loss);
+  } else {
+    const int64_t cnt = n * 2048;
+    const int64_t nb = cdiv(cnt, kT);
+    hipLaunchKernelGGL(out_grad, dim3((unsigned)nb), dim3(kT), 0, s, w.act[kLayers], w.act[0],
+                       cnt, (float)(2.0 / (double)cnt), w.g0, w.lpart);
+    if (loss)
+      hipLaunchKernelGGL(loss_reduce, dim3(1), dim3(1024), 0, s, w.lpart, nb, 1.0 / (double)cnt,
+                         loss);
+  }
   float* g = w.g0;      // dL/d(output of layer l), tanh factor not yet applied
   float* gn = w.g1;
   for (int l = kLayers - 1; l >= 0; --l) {

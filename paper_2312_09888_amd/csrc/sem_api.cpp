@@ -868,15 +868,16 @@ int sem_ae_forward(int64_t n, const float* blocks, const float* params, int tanh
 }
 
 int sem_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
-                const float* params, int tanh_mask, float* grad, float* loss,
+                const float* params, int tanh_mask, int loss_kind, float* grad, float* loss,
                 void* workspace, size_t workspace_bytes, int32_t* status_word, void* stream) {
   if (n < 1 || n > (int64_t)0x7fffffff || n_pool < 1 || !ae_mask_ok(tanh_mask))
     return SEM_ERR_ARG;
+  if (loss_kind != SEM_AE_LOSS_MSE && loss_kind != SEM_AE_LOSS_MAX) return SEM_ERR_ARG;
   if (!idx && n > n_pool) return SEM_ERR_ARG;
   if (!pool || !params || !grad) return SEM_ERR_ARG;
   if (!workspace || workspace_bytes < ae_workspace_bytes(n)) return SEM_ERR_WORKSPACE;
-  return launch_ae_grad(n, pool, n_pool, idx, params, tanh_mask, grad, loss, workspace,
-                        status_word, static_cast<hipStream_t>(stream)) == hipSuccess
+  return launch_ae_grad(n, pool, n_pool, idx, params, tanh_mask, loss_kind, grad, loss,
+                        workspace, status_word, static_cast<hipStream_t>(stream)) == hipSuccess
              ? SEM_OK
              : SEM_ERR_HIP;
 }

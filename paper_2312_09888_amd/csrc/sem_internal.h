@@ -239,8 +239,8 @@ hipError_t launch_ae_pack(int64_t e_begin, int64_t n, const float* const* f, con
 hipError_t launch_ae_forward(int64_t n, const float* blocks, const float* params, int tanh_mask,
                              float* recon, uint16_t* latent, void* ws, hipStream_t s);
 hipError_t launch_ae_grad(int64_t n, const float* pool, int64_t n_pool, const int64_t* idx,
-                          const float* params, int tanh_mask, float* grad, float* loss,
-                          void* ws, int32_t* status, hipStream_t s);
+                          const float* params, int tanh_mask, int loss_kind, float* grad,
+                          float* loss, void* ws, int32_t* status, hipStream_t s);
 hipError_t launch_ae_adam(int64_t n, float* p, const float* g, float* m, float* v, int step,
                           float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_sym_eig(int n, const double* a_in, int r, double* lam, float* w, void* ws,

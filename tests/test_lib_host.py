@@ -332,10 +332,14 @@ def test_compression_entry_points_reject_bad_arguments():
     assert L.sem_ae_forward(4, FAKE, FAKE, 0, FAKE, None, FAKE, 16, None) == \
         _lib.SEM_ERR_WORKSPACE
     assert L.sem_ae_forward(0, None, None, 0, None, None, None, 0, None) == _lib.SEM_OK
-    assert L.sem_ae_grad(0, FAKE, 1, None, FAKE, 0, FAKE, None, FAKE, 1 << 30, None,
+    assert L.sem_ae_grad(0, FAKE, 1, None, FAKE, 0, 0, FAKE, None, FAKE, 1 << 30, None,
                          None) == _lib.SEM_ERR_ARG
-    assert L.sem_ae_grad(5, FAKE, 4, None, FAKE, 0, FAKE, None, FAKE, 1 << 30, None,
+    assert L.sem_ae_grad(5, FAKE, 4, None, FAKE, 0, 0, FAKE, None, FAKE, 1 << 30, None,
                          None) == _lib.SEM_ERR_ARG          # first n > pool without indices
+    assert L.sem_ae_grad(4, FAKE, 4, None, FAKE, 0, 2, FAKE, None, FAKE, 1 << 30, None,
+                         None) == _lib.SEM_ERR_ARG          # unknown loss
+    assert L.sem_ae_grad(4, FAKE, 4, None, FAKE, 0, -1, FAKE, None, FAKE, 1 << 30, None,
+                         None) == _lib.SEM_ERR_ARG
     assert L.sem_ae_adam(10, FAKE, FAKE, FAKE, FAKE, 0, 1e-3, 0.9, 0.999, 1e-8, None) == \
         _lib.SEM_ERR_ARG                                     # steps count from 1
     assert L.sem_ae_adam(10, FAKE, FAKE, FAKE, FAKE, 1, 1e-3, 1.0, 0.999, 1e-8, None) == \
