@@ -539,10 +539,14 @@ int sem_ae_adam(int64_t n, float* params, const float* grad, float* m, float* v,
                 float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Symmetric eigenproblem of the n x n FP64 matrix a (n even, 2 <= n <= 512),
- * cyclic Jacobi: the r largest eigenvalues in decreasing order into lam[r]
- * (may be NULL) and their eigenvectors into vec[n][r] (FP32, each signed so
- * that its largest-magnitude entry is positive); *sweeps (device int, may
- * be NULL) receives the sweeps used. */
+ * cyclic Jacobi (Golub & Van Loan, Matrix Computations, section 8.5, with
+ * the round-robin parallel ordering): the r largest eigenvalues in
+ * decreasing order into lam[r] (may be NULL) and their eigenvectors into
+ * vec[n][r] (FP32, each signed so that its largest-magnitude entry is
+ * positive); *sweeps (device int, may be NULL) receives the sweeps used.
+ * Each round of rotations runs over the whole GPU; the call synchronises
+ * `stream` once per sweep to read the convergence test (a setup call, not
+ * capturable). */
 size_t sem_eig_workspace_bytes(int n);
 int sem_sym_eig(int n, const double* a, int r, double* lam, float* vec, void* workspace,
                 size_t workspace_bytes, int* sweeps, void* stream);
@@ -552,7 +556,8 @@ int sem_sym_eig(int n, const double* a, int r, double* lam, float* vec, void* wo
  * 0 the identity on each 2^3 patch, layers 1 and 2 the 64 and 32 leading
  * eigenvectors of the second-moment matrices of their inputs, decoder
  * layers the transposes, biases zero; lam (may be NULL) receives the 64 +
- * 32 eigenvalues. */
+ * 32 eigenvalues.  Synchronises `stream` (the eigensolver's convergence
+ * tests). */
 size_t sem_ae_pca_workspace_bytes(int64_t n_pool);
 int sem_ae_pca_init(int64_t n_pool, const float* pool, float* params, double* lam,
                     void* workspace, size_t workspace_bytes, void* stream);

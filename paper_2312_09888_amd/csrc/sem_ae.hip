@@ -167,21 +167,34 @@ struct GemmArgs {
   const float* D;        // tanh-derivative source, layout of C
 };
 
-// BM x BN tile; 256 threads as 16 x 16, each with (BM / 16) x (BN / 16)
-// outputs.  Narrow layers (N = 32) use 128 x 32 tiles so that no thread
-// computes padding columns.
+// BM x BN tile on the matrix cores: four waves in a 2 x 2 arrangement, each
+// with a (BM / 2) x (BN / 2) block of 16 x 16 tiles of
+// v_mfma_f32_16x16x4f32 (FP32 products, FP32 sums).  Lane l of a wave
+// holds A(row l % 16, k l / 16) and B(k l / 16, col l % 16) of a 4-deep
+// step, and C rows 4 (l / 16) + r, r < 4, of column l % 16.  The k-major
+// LDS tiles have rows of BM + 16 (BN + 16) floats, so the four k rows of a
+// step fall on disjoint bank halves.  Narrow layers (N = 32) use 128 x 32
+// tiles.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <int BM, int BN>
 __global__ void __launch_bounds__(kT) gemm_f32(GemmArgs g) {
-  constexpr int TM = BM / 16, TN = BN / 16;
-  __shared__ float As[kBK][BM + 4];
-  __shared__ float Bs[kBK][BN + 4];
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  __shared__ float As[kBK][BM + 16];
+  __shared__ float Bs[kBK][BN + 16];
   const int t = threadIdx.x;
-  const int tx = t & 15, ty = t >> 4;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const int lr = lane & 15, lk = lane >> 4;
   const int64_t m0 = (int64_t)blockIdx.x * BM;   // rows on x: up to 2^31 - 1 tiles
   const int n0 = blockIdx.y * BN;
   const int64_t kb = (int64_t)blockIdx.z * g.k_split;
   const int64_t ke = kb + g.k_split < g.K ? kb + g.k_split : g.K;
-  float acc[TM][TN] = {};
+  f32x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
     // A tile: BM x kBK; the index order follows the contiguous operand axis
 #pragma unroll
@@ -205,37 +218,41 @@ __global__ void __launch_bounds__(kT) gemm_f32(GemmArgs g) {
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kBK; ++kk) {
-      float a[TM], b[TN];
+    for (int kk = 0; kk < kBK; kk += 4) {
+      float a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < FM; ++i) a[i] = As[kk + lk][wm + 16 * i + lr];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < FN; ++j) b[j] = Bs[kk + lk][wn + 16 * j + lr];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
   float* C = g.C + (int64_t)blockIdx.z * g.c_split;
 #pragma unroll
-  for (int i = 0; i < TM; ++i) {
-    const int64_t m = m0 + ty + 16 * i;
-    if (m >= g.M) continue;
+  for (int i = 0; i < FM; ++i) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int n = n0 + tx + 16 * j;
-      if (n >= g.N) continue;
-      float v = acc[i][j];
-      if (g.bias) v += g.bias[n % g.bias_mod];
-      if (g.flags & kEpiTanh) v = tanhf(v);
-      if (g.flags & kEpiHalf) v = half_round(v);
-      if (g.flags & kEpiTanhGrad) {
-        const float d = g.D[m * g.ldc + n];
-        v *= 1.f - d * d;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + wm + 16 * i + 4 * lk + r;
+      if (m >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int n = n0 + wn + 16 * j + lr;
+        if (n >= g.N) continue;
+        float v = acc[i][j][r];
+        if (g.bias) v += g.bias[n % g.bias_mod];
+        if (g.flags & kEpiTanh) v = tanhf(v);
+        if (g.flags & kEpiHalf) v = half_round(v);
+        if (g.flags & kEpiTanhGrad) {
+          const float d = g.D[m * g.ldc + n];
+          v *= 1.f - d * d;
+        }
+        C[m * g.ldc + n] = v;
       }
-      C[m * g.ldc + n] = v;
     }
   }
 }
@@ -473,108 +490,136 @@ __global__ void sum_splits_f64(const double* __restrict__ part, int64_t n, int s
   out[i] = s;
 }
 
-// Cyclic Jacobi on the symmetric n x n matrix a (n even, in place, one
-// workgroup): each round rotates n/2 disjoint pairs (p, q) of the
-// round-robin tournament ordering at once, a <- J^T a J, v <- v J, with the
-// rotation that zeroes a_pq (t = sign(th) / (|th| + sqrt(th^2 + 1)),
-// th = (a_qq - a_pp) / (2 a_pq); Rutishauser's formulas, e.g. Golub & Van
-// Loan, Matrix Computations, section 8.5).  Sweeps of n - 1 rounds repeat
-// until the off-diagonal mass (sum of squares) is below 1e-28 of the total,
-// or below 1e-20 and no longer falling fourfold per sweep (the rounding
-// floor of a large matrix), or 40 sweeps.
+// Cyclic Jacobi on the symmetric n x n matrix a (n even, in place): each
+// round rotates the n/2 disjoint pairs (p, q) of the round-robin tournament
+// ordering at once, a <- J^T a J, v <- v J, with the rotation that zeroes
+// a_pq (t = sign(th) / (|th| + sqrt(th^2 + 1)), th = (a_qq - a_pp) /
+// (2 a_pq); Rutishauser's formulas, e.g. Golub & Van Loan, Matrix
+// Computations, section 8.5).  Sweeps of n - 1 rounds repeat until the
+// off-diagonal mass (sum of squares) is below 1e-28 of the total, or below
+// 1e-20 and no longer falling fourfold per sweep (the rounding floor of a
+// large matrix), or 40 sweeps.
+//
+// A round is two launches over the whole GPU: jacobi_rot computes the n/2
+// rotations from a (one workgroup), jacobi_apply updates every 2 x 2 block
+// (rows of pair i, columns of pair j) of a as R_i^T A_ij R_j and every
+// row's pair columns of v, one thread each; the convergence test
+// (jacobi_check) runs once per sweep.
 constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxN = 512;
 
-__global__ void __launch_bounds__(kJacobiThreads)
-jacobi_sym(int n, double* __restrict__ a, double* __restrict__ v, int* __restrict__ sweeps_out) {
-  __shared__ double cs[kJacobiMaxN / 2], sn[kJacobiMaxN / 2];
-  __shared__ int pp[kJacobiMaxN / 2], qq[kJacobiMaxN / 2];
-  __shared__ double red[kJacobiThreads / 64];
-  __shared__ int done;
-  const int t = threadIdx.x;
+struct JacobiState {
+  double prev_off;
+  int done;
+  int sweep;
+};
+
+__global__ void jacobi_init(int n, double* __restrict__ v, JacobiState* __restrict__ st) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i < (int64_t)n * n) v[i] = (i / n == i % n) ? 1.0 : 0.0;
+  if (i == 0) {
+    st->prev_off = 0.0;
+    st->done = 0;
+    st->sweep = 0;
+  }
+}
+
+// pairs and rotations of round r: pq[2i], pq[2i + 1] = p < q; cs[2i] = c,
+// cs[2i + 1] = s
+__global__ void __launch_bounds__(kT)
+jacobi_rot(int n, int r, const double* __restrict__ a, int* __restrict__ pq,
+           double* __restrict__ cs, const JacobiState* __restrict__ st) {
+  if (st->done) return;
   const int half = n / 2;
-  for (int64_t i = t; i < (int64_t)n * n; i += kJacobiThreads)
-    v[i] = (i / n == i % n) ? 1.0 : 0.0;
-  int sweep = 0;
-  double prev_off = 0.0;
-  for (; sweep < 40; ++sweep) {
-    // convergence test on the off-diagonal mass
-    double off = 0.0, tot = 0.0;
-    for (int64_t i = t; i < (int64_t)n * n; i += kJacobiThreads) {
-      const double x = a[i] * a[i];
-      tot += x;
-      if (i / n != i % n) off += x;
+  for (int i = threadIdx.x; i < half; i += kT) {
+    const int x = i == 0 ? 0 : 1 + (i - 1 + r) % (n - 1);
+    const int y = 1 + (n - 2 - i + r) % (n - 1);
+    const int p = x < y ? x : y, q = x < y ? y : x;
+    const double apq = a[(int64_t)p * n + q];
+    double c = 1.0, sn = 0.0;
+    if (apq != 0.0) {
+      const double th = (a[(int64_t)q * n + q] - a[(int64_t)p * n + p]) / (2.0 * apq);
+      const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+      c = 1.0 / sqrt(tt * tt + 1.0);
+      sn = tt * c;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) off += __shfl_xor(off, o);
-    if ((t & 63) == 0) red[t >> 6] = off;
-    __syncthreads();
-    if (t == 0) {
-      double s = 0.0;
-      for (int i = 0; i < kJacobiThreads / 64; ++i) s += red[i];
-      off = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-    if ((t & 63) == 0) red[t >> 6] = tot;
-    __syncthreads();
-    if (t == 0) {
-      double s = 0.0;
-      for (int i = 0; i < kJacobiThreads / 64; ++i) s += red[i];
-      done = !(off > 1e-28 * s) || (sweep > 0 && off >= 0.25 * prev_off && off <= 1e-20 * s);
-      prev_off = off;
-    }
-    __syncthreads();
-    if (done) break;
-    for (int r = 0; r < n - 1; ++r) {
-      // pairs of round r: player 0 fixed, players 1..n-1 rotate
-      for (int i = t; i < half; i += kJacobiThreads) {
-        const int x = i == 0 ? 0 : 1 + (i - 1 + r) % (n - 1);
-        const int y = 1 + (n - 2 - i + r) % (n - 1);
-        const int p = x < y ? x : y, q = x < y ? y : x;
-        const double apq = a[(int64_t)p * n + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double th = (a[(int64_t)q * n + q] - a[(int64_t)p * n + p]) / (2.0 * apq);
-          const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-          c = 1.0 / sqrt(tt * tt + 1.0);
-          s = tt * c;
-        }
-        pp[i] = p;
-        qq[i] = q;
-        cs[i] = c;
-        sn[i] = s;
-      }
-      __syncthreads();
-      // columns: a <- a J, v <- v J
-      for (int64_t w = t; w < (int64_t)n * half; w += kJacobiThreads) {
-        const int row = (int)(w / half), i = (int)(w % half);
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        double* ar = a + (int64_t)row * n;
-        const double ap = ar[p], aq = ar[q];
-        ar[p] = c * ap - s * aq;
-        ar[q] = s * ap + c * aq;
-        double* vr = v + (int64_t)row * n;
-        const double vp = vr[p], vq = vr[q];
-        vr[p] = c * vp - s * vq;
-        vr[q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      // rows: a <- J^T a
-      for (int64_t w = t; w < (int64_t)n * half; w += kJacobiThreads) {
-        const int col = (int)(w % n), i = (int)(w / n);
-        const int p = pp[i], q = qq[i];
-        const double c = cs[i], s = sn[i];
-        const double ap = a[(int64_t)p * n + col], aq = a[(int64_t)q * n + col];
-        a[(int64_t)p * n + col] = c * ap - s * aq;
-        a[(int64_t)q * n + col] = s * ap + c * aq;
-      }
-      __syncthreads();
+    pq[2 * i] = p;
+    pq[2 * i + 1] = q;
+    cs[2 * i] = c;
+    cs[2 * i + 1] = sn;
+  }
+}
+
+// Column rotation of pair j: col p <- c col p - s col q, col q <- s col p +
+// c col q; row rotation likewise on rows.
+__global__ void __launch_bounds__(kT)
+jacobi_apply(int n, const int* __restrict__ pq, const double* __restrict__ cs,
+             double* __restrict__ a, double* __restrict__ v, const JacobiState* __restrict__ st) {
+  if (st->done) return;
+  const int half = n / 2;
+  const int64_t nblk = (int64_t)half * half;
+  for (int64_t w = (int64_t)blockIdx.x * kT + threadIdx.x; w < nblk + (int64_t)n * half;
+       w += (int64_t)gridDim.x * kT) {
+    if (w < nblk) {
+      const int bi = (int)(w / half), bj = (int)(w % half);
+      const int pi = pq[2 * bi], qi = pq[2 * bi + 1], pj = pq[2 * bj], qj = pq[2 * bj + 1];
+      const double ci = cs[2 * bi], si = cs[2 * bi + 1], cj = cs[2 * bj], sj = cs[2 * bj + 1];
+      double* rp = a + (int64_t)pi * n;
+      double* rq = a + (int64_t)qi * n;
+      const double x00 = rp[pj], x01 = rp[qj], x10 = rq[pj], x11 = rq[qj];
+      const double y00 = cj * x00 - sj * x01, y01 = sj * x00 + cj * x01;
+      const double y10 = cj * x10 - sj * x11, y11 = sj * x10 + cj * x11;
+      rp[pj] = ci * y00 - si * y10;
+      rq[pj] = si * y00 + ci * y10;
+      rp[qj] = ci * y01 - si * y11;
+      rq[qj] = si * y01 + ci * y11;
+    } else {
+      const int64_t u = w - nblk;
+      const int row = (int)(u / half), bj = (int)(u % half);
+      const int pj = pq[2 * bj], qj = pq[2 * bj + 1];
+      const double cj = cs[2 * bj], sj = cs[2 * bj + 1];
+      double* vr = v + (int64_t)row * n;
+      const double vp = vr[pj], vq = vr[qj];
+      vr[pj] = cj * vp - sj * vq;
+      vr[qj] = sj * vp + cj * vq;
     }
   }
-  if (t == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// Convergence test before sweep st->sweep (one workgroup): sets st->done.
+__global__ void __launch_bounds__(kJacobiThreads)
+jacobi_check(int n, const double* __restrict__ a, JacobiState* __restrict__ st) {
+  __shared__ double red[2][kJacobiThreads / 64];
+  const int t = threadIdx.x;
+  if (st->done) return;
+  double off = 0.0, tot = 0.0;
+  for (int64_t i = t; i < (int64_t)n * n; i += kJacobiThreads) {
+    const double x = a[i] * a[i];
+    tot += x;
+    if (i / n != i % n) off += x;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    off += __shfl_xor(off, o);
+    tot += __shfl_xor(tot, o);
+  }
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = off;
+    red[1][t >> 6] = tot;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double so = 0.0, stot = 0.0;
+    for (int i = 0; i < kJacobiThreads / 64; ++i) {
+      so += red[0][i];
+      stot += red[1][i];
+    }
+    const int sweep = st->sweep;
+    st->done = !(so > 1e-28 * stot) ||
+               (sweep > 0 && so >= 0.25 * st->prev_off && so <= 1e-20 * stot) || sweep >= 40;
+    st->prev_off = so;
+    if (!st->done) st->sweep = sweep + 1;
+  }
 }
 
 // The r largest eigenvalues (diagonal of a) in decreasing order into lam and
@@ -1071,15 +1116,52 @@ hipError_t launch_ae_adam(int64_t n, float* p, const float* g, float* m, float* 
   return hipGetLastError();
 }
 
-size_t eig_workspace_bytes(int n) { return align256((size_t)n * n * 8) * 2 + 256; }
+size_t eig_workspace_bytes(int n) {
+  return align256((size_t)n * n * 8) * 2 + align256((size_t)n * 8) + align256((size_t)n * 4) +
+         256;
+}
+
+__global__ void jacobi_sweeps_out(const JacobiState* __restrict__ st, int* __restrict__ out) {
+  *out = st->sweep;
+}
+
+// Sweeps until jacobi_check sets the done flag: the host reads the flag
+// once per sweep (a stream synchronisation), so the launches stop there.
+hipError_t jacobi_run(int n, double* a, double* v, int* pq, double* cs, JacobiState* st,
+                      int* sweeps, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_init, dim3((unsigned)cdiv((int64_t)n * n, kT)), dim3(kT), 0, s, n,
+                     v, st);
+  const int64_t work = (int64_t)(n / 2) * (n / 2) + (int64_t)n * (n / 2);
+  const unsigned grid = (unsigned)cdiv(work, kT);
+  for (int sweep = 0; sweep <= 40; ++sweep) {
+    hipLaunchKernelGGL(jacobi_check, dim3(1), dim3(kJacobiThreads), 0, s, n, a, st);
+    int done = 0;
+    hipError_t e = hipMemcpyAsync(&done, &st->done, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (done) break;
+    for (int r = 0; r < n - 1; ++r) {
+      hipLaunchKernelGGL(jacobi_rot, dim3(1), dim3(kT), 0, s, n, r, a, pq, cs, st);
+      hipLaunchKernelGGL(jacobi_apply, dim3(grid), dim3(kT), 0, s, n, pq, cs, a, v, st);
+    }
+  }
+  if (sweeps) hipLaunchKernelGGL(jacobi_sweeps_out, dim3(1), dim3(1), 0, s, st, sweeps);
+  return hipGetLastError();
+}
 
 hipError_t launch_sym_eig(int n, const double* a_in, int r, double* lam, float* w, void* ws,
                           int* sweeps, hipStream_t s) {
   char* p = static_cast<char*>(ws);
+  const size_t nn = align256((size_t)n * n * 8);
   double* a = reinterpret_cast<double*>(p);
-  double* v = reinterpret_cast<double*>(p + align256((size_t)n * n * 8));
-  hipMemcpyAsync(a, a_in, (size_t)n * n * 8, hipMemcpyDeviceToDevice, s);
-  hipLaunchKernelGGL(jacobi_sym, dim3(1), dim3(kJacobiThreads), 0, s, n, a, v, sweeps);
+  double* v = reinterpret_cast<double*>(p + nn);
+  double* cs = reinterpret_cast<double*>(p + 2 * nn);
+  int* pq = reinterpret_cast<int*>(p + 2 * nn + align256((size_t)n * 8));
+  JacobiState* st = reinterpret_cast<JacobiState*>(p + 2 * nn + align256((size_t)n * 8) +
+                                                   align256((size_t)n * 4));
+  hipError_t e = hipMemcpyAsync(a, a_in, (size_t)n * n * 8, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = jacobi_run(n, a, v, pq, cs, st, sweeps, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(select_leading, dim3(1), dim3(kJacobiThreads), 0, s, n, r, a, v, lam, w);
   return hipGetLastError();
 }
