@@ -832,6 +832,289 @@ modal_k(const float* __restrict__ u, const float* __restrict__ v, const float* _
   if (threadIdx.x == 0) flag[e] = bad;
 }
 
+// ---------------------------------------------------------------------------
+// fused compression for the linear network (no tanh)
+// ---------------------------------------------------------------------------
+//
+// With every layer linear, layers 0 and 1 compose into one map per octant
+// (256 Morton-ordered inputs of the octant -> 64 outputs), and layers 4 and
+// 5 likewise (64 -> the octant's 256 outputs):
+//   W01[(d1 32 + d0 4 + c) 64 + o] = sum_j W1[(d1 32 + j) 64 + o] W0[(d0 4 + c) 32 + j]
+//   b01[o] = b1[o] + sum_{d1, j} W1[(d1 32 + j) 64 + o] b0[j]
+//   W45[i 256 + d4 32 + d5 4 + c] = sum_j W4[(i 8 + d4) 32 + j] W5[(j 8 + d5) 4 + c]
+//   b45[d4 32 + d5 4 + c] = b5[c] + sum_j b4[j] W5[(j 8 + d5) 4 + c]
+// (the same function, rounded differently).  The encoder kernel then takes
+// four elements per workgroup from the GLL fields to their binary16
+// latents, computing the element maxima on the way, and the decoder kernel
+// from the latents to the error check (compression) or to the fields
+// (decompression); neither writes an activation to memory.
+
+constexpr int kFoldFloats = 256 * 64 + 64 + 64 * 256 + 256;
+constexpr int kEncE = 4;        // elements per workgroup
+constexpr int kRowPad = 48;     // k-major LDS rows for the 32 GEMM rows: the four
+                                // k rows of an MFMA step fall on disjoint bank halves
+
+__global__ void __launch_bounds__(kT)
+ae_fold(const float* __restrict__ prm, int64_t ow0, int64_t ob0, int64_t ow1, int64_t ob1,
+        int64_t ow4, int64_t ob4, int64_t ow5, int64_t ob5, float* __restrict__ fold) {
+  const int idx = blockIdx.x * kT + threadIdx.x;
+  float* w01 = fold;
+  float* b01 = w01 + 256 * 64;
+  float* w45 = b01 + 64;
+  float* b45 = w45 + 64 * 256;
+  if (idx < 256 * 64) {
+    const int o = idx % 64, r = idx / 64, d1 = r / 32, dc = r % 32;
+    float acc = 0.f;
+    for (int j = 0; j < 32; ++j)
+      acc = fmaf(prm[ow1 + (d1 * 32 + j) * 64 + o], prm[ow0 + dc * 32 + j], acc);
+    w01[idx] = acc;
+  } else if (idx < 256 * 64 + 64) {
+    const int o = idx - 256 * 64;
+    float acc = prm[ob1 + o];
+    for (int d1 = 0; d1 < 8; ++d1)
+      for (int j = 0; j < 32; ++j)
+        acc = fmaf(prm[ow1 + (d1 * 32 + j) * 64 + o], prm[ob0 + j], acc);
+    b01[o] = acc;
+  } else if (idx < 256 * 64 + 64 + 64 * 256) {
+    const int q = idx - (256 * 64 + 64);
+    const int i = q / 256, col = q % 256, d4 = col / 32, d5 = (col / 4) % 8, c = col % 4;
+    float acc = 0.f;
+    for (int j = 0; j < 32; ++j)
+      acc = fmaf(prm[ow4 + (i * 8 + d4) * 32 + j], prm[ow5 + (j * 8 + d5) * 4 + c], acc);
+    w45[q] = acc;
+  } else if (idx < kFoldFloats) {
+    const int col = idx - (256 * 64 + 64 + 64 * 256), d5 = (col / 4) % 8, c = col % 4;
+    float acc = prm[ob5 + c];
+    for (int j = 0; j < 32; ++j) acc = fmaf(prm[ob4 + j], prm[ow5 + (j * 8 + d5) * 4 + c], acc);
+    b45[col] = acc;
+  }
+}
+
+__device__ __forceinline__ int morton_node(int m) {
+  // inverse of morton8: bits (i0 j0 k0 i1 j1 k1 i2 j2 k2) -> node i + 8 j + 64 k
+  const int i = (m & 1) | ((m >> 2) & 2) | ((m >> 4) & 4);
+  const int j = ((m >> 1) & 1) | ((m >> 3) & 2) | ((m >> 5) & 4);
+  const int k = ((m >> 2) & 1) | ((m >> 4) & 2) | ((m >> 6) & 4);
+  return i + 8 * j + 64 * k;
+}
+
+// Fields -> element maxima (scale), per-workgroup channel maxima (gpart)
+// and binary16 latents.  Wave w loads element 4 b + w; the normalised
+// values go k-major into LDS (k = the octant's Morton input index, row =
+// element x 8 + octant) for the folded layers 0-1 on the matrix cores; their
+// outputs (32 rows x 64) are layer 2's input rows, one per element.
+__global__ void __launch_bounds__(kT)
+ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__ v,
+          const float* __restrict__ w, const float* __restrict__ th,
+          const float* __restrict__ fold, const float* __restrict__ w2,
+          const float* __restrict__ b2, float* __restrict__ scale, float* __restrict__ gpart,
+          uint16_t* __restrict__ latent) {
+  __shared__ float xs[256 * kRowPad];   // xT[k][row], then h1[element][512]
+  __shared__ float smax[kEncE][4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t e0 = (int64_t)blockIdx.x * kEncE;
+  {
+    const int64_t e = e0 + wv;
+    const bool ok = e < n_elem;
+    const float* f[4] = {u, v, w, th};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float val[8];
+      float mx = 0.f;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        val[q] = ok ? f[c][e * 512 + lane + 64 * q] : 0.f;
+        const float a = fabsf(val[q]);
+        mx = a > mx ? a : mx;
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float o = __shfl_xor(mx, off);
+        mx = o > mx ? o : mx;
+      }
+      if (lane == 0) {
+        smax[wv][c] = mx;
+        if (ok) scale[e * 4 + c] = mx;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int n = lane + 64 * q;
+        const int m = morton8(n & 7, (n >> 3) & 7, n >> 6);
+        xs[(4 * (m & 63) + c) * kRowPad + wv * 8 + (m >> 6)] = mx > 0.f ? val[q] / mx : 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  if (t < 4) {
+    float g = 0.f;
+#pragma unroll
+    for (int q = 0; q < kEncE; ++q) g = smax[q][t] > g ? smax[q][t] : g;
+    gpart[blockIdx.x * 4 + t] = g;
+  }
+  // layers 0-1 folded: [32 rows x 256] x W01 [256 x 64]; wave w: rows 16 (w & 1),
+  // columns 32 (w >> 1) .. + 31
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rt = wv & 1, c0 = 32 * (wv >> 1);
+  f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+  for (int k = 0; k < 256; k += 4) {
+    const float a = xs[(k + lk) * kRowPad + 16 * rt + lr];
+    const float bb0 = fold[(k + lk) * 64 + c0 + lr];
+    const float bb1 = fold[(k + lk) * 64 + c0 + 16 + lr];
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb0, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb1, acc1, 0, 0, 0);
+  }
+  __syncthreads();                          // every read of xs is done
+  float* h1 = xs;                           // h1[el][p1 64 + o]
+  const float* b01 = fold + 256 * 64;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * rt + 4 * lk + r;
+    const int base = (row >> 3) * 512 + (row & 7) * 64;
+    h1[base + c0 + lr] = acc0[r] + b01[c0 + lr];
+    h1[base + c0 + 16 + lr] = acc1[r] + b01[c0 + 16 + lr];
+  }
+  __syncthreads();
+  // layer 2: z[el][o] = b2[o] + sum_k h1[el][k] W2[k 32 + o]; wave w = element,
+  // lane halves split k
+  const int o2 = lane & 31, half = lane >> 5;
+  float z0 = 0.f, z1 = 0.f, z2 = 0.f, z3 = 0.f;
+  const float* hr = h1 + wv * 512 + 256 * half;
+  const float* wr = w2 + (int64_t)(256 * half) * 32 + o2;
+#pragma unroll 4
+  for (int k = 0; k < 256; k += 4) {
+    z0 = fmaf(hr[k], wr[k * 32], z0);
+    z1 = fmaf(hr[k + 1], wr[(k + 1) * 32], z1);
+    z2 = fmaf(hr[k + 2], wr[(k + 2) * 32], z2);
+    z3 = fmaf(hr[k + 3], wr[(k + 3) * 32], z3);
+  }
+  float z = (z0 + z1) + (z2 + z3);
+  z += __shfl_xor(z, 32);
+  const int64_t e = e0 + wv;
+  if (half == 0 && e < n_elem)
+    latent[e * 32 + o2] = __half_as_ushort(__float2half_rn(z + b2[o2]));
+}
+
+// Latents -> reconstruction, four elements per workgroup: layer 3 on the
+// vector units, folded layers 4-5 on the matrix cores, the reconstruction
+// s x_hat placed in LDS at the GLL positions.  CHECK: compared with the
+// fields (flag[e] = some channel exceeds the fallback bound); else written
+// to the fields, raw blocks copied for flagged elements.
+template <bool CHECK>
+__global__ void __launch_bounds__(kT)
+ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __restrict__ scale,
+          const uint32_t* __restrict__ gmax_bits, const float* __restrict__ fold,
+          const float* __restrict__ w3, const float* __restrict__ b3,
+          const float* __restrict__ iu, const float* __restrict__ iv,
+          const float* __restrict__ iw, const float* __restrict__ ith,
+          float* __restrict__ ou, float* __restrict__ ov, float* __restrict__ ow,
+          float* __restrict__ oth, const int32_t* __restrict__ flag,
+          const int64_t* __restrict__ offs, const float* __restrict__ raw, int64_t raw_count,
+          int32_t* __restrict__ flag_out, int32_t* __restrict__ status) {
+  __shared__ float fl[kEncE][4][512];       // fields (CHECK) or reconstruction
+  __shared__ float h3[64 * kRowPad];        // layer 3 output, k-major: [o][el 8 + d]
+  __shared__ float zs[kEncE][32];
+  __shared__ uint32_t emax[kEncE][4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t e0 = (int64_t)blockIdx.x * kEncE;
+  if (t < kEncE * 32) {
+    const int64_t e = e0 + t / 32;
+    zs[t / 32][t % 32] = e < n_elem ? __half2float(__ushort_as_half(latent[e * 32 + t % 32])) : 0.f;
+  }
+  if (t < kEncE * 4) emax[t / 4][t % 4] = 0u;
+  if (CHECK) {
+    const int64_t e = e0 + wv;
+    const float* f[4] = {iu, iv, iw, ith};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        fl[wv][c][lane + 64 * q] = e < n_elem ? f[c][e * 512 + lane + 64 * q] : 0.f;
+  }
+  __syncthreads();
+  // layer 3: h3[el][d 64 + o] = b3[o] + sum_i z[el][i] W3[i 512 + d 64 + o]
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int col = t + 256 * h;
+    float a[kEncE];
+#pragma unroll
+    for (int el = 0; el < kEncE; ++el) a[el] = b3[col & 63];
+    for (int i = 0; i < 32; ++i) {
+      const float wi = w3[i * 512 + col];
+#pragma unroll
+      for (int el = 0; el < kEncE; ++el) a[el] = fmaf(zs[el][i], wi, a[el]);
+    }
+#pragma unroll
+    for (int el = 0; el < kEncE; ++el) h3[(col & 63) * kRowPad + el * 8 + (col >> 6)] = a[el];
+  }
+  __syncthreads();
+  // layers 4-5 folded: [32 rows x 64] x W45 [64 x 256]; wave w: rows 16 (w & 1),
+  // columns 128 (w >> 1) .. + 127
+  const int lr = lane & 15, lk = lane >> 4;
+  const int rt = wv & 1, c0 = 128 * (wv >> 1);
+  const float* w45 = fold + 256 * 64 + 64;
+  const float* b45 = w45 + 64 * 256;
+  f32x4 acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int k = 0; k < 64; k += 4) {
+    const float a = h3[(k + lk) * kRowPad + 16 * rt + lr];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+          a, w45[(k + lk) * 256 + c0 + 16 * j + lr], acc[j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int col = c0 + 16 * j + lr, d4 = col >> 5, d5 = (col >> 2) & 7, c = col & 3;
+    const float bias = b45[col];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rt + 4 * lk + r, el = row >> 3;
+      const int node = morton_node(64 * (row & 7) + 8 * d4 + d5);
+      const int64_t e = e0 + el;
+      const float sc = e < n_elem ? scale[e * 4 + c] : 0.f;
+      const float rec = sc * (acc[j][r] + bias);
+      if (CHECK) {
+        const float d = fabsf(fl[el][c][node] - rec);
+        atomicMax(&emax[el][c], __float_as_uint(d));
+      } else {
+        fl[el][c][node] = rec;
+      }
+    }
+  }
+  __syncthreads();
+  if (CHECK) {
+    if (t < kEncE) {
+      const int64_t e = e0 + t;
+      if (e < n_elem) {
+        int bad = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          bad |= __uint_as_float(emax[t][c]) > fallback_bound(scale[e * 4 + c], gmax_bits[c]);
+        flag_out[e] = bad;
+      }
+    }
+  } else {
+    const int64_t e = e0 + wv;
+    if (e < n_elem) {
+      const bool flagged = flag && flag[e];
+      const int64_t o = flagged ? offs[e] : 0;
+      const bool is_raw = flagged && raw && o < raw_count;
+      if (flagged && !is_raw && lane == 0 && status) atomicOr(status, SEM_FLAG_RAW_OVERFLOW);
+      float* f[4] = {ou, ov, ow, oth};
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int n = lane + 64 * q;
+          f[c][e * 512 + n] = is_raw ? raw[(o * 4 + c) * 512 + n] : fl[wv][c][n];
+        }
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1233,6 +1516,8 @@ struct CompressWs {
   int64_t* offs;
   int64_t* partial;
   uint32_t* gmax;
+  float* fold;      // folded layers 0-1 and 4-5 (linear network)
+  float* gpart;     // per-workgroup channel maxima of the fused encoder
   size_t bytes;
 };
 
@@ -1251,8 +1536,18 @@ CompressWs compress_layout(void* base, int64_t n_elem) {
   c.offs = reinterpret_cast<int64_t*>(take((size_t)(n_elem + 1) * 8));
   c.partial = reinterpret_cast<int64_t*>(take((size_t)(scan_blocks(n_elem + 1) + 1) * 8));
   c.gmax = reinterpret_cast<uint32_t*>(take(16));
+  c.fold = reinterpret_cast<float*>(take((size_t)kFoldFloats * 4));
+  c.gpart = reinterpret_cast<float*>(take((size_t)(cdiv(n_elem, kEncE) + 1) * 4 * 4));
   c.bytes = off;
   return c;
+}
+
+hipError_t launch_fold(const float* params, float* fold, hipStream_t s) {
+  const Layer* L = layers();
+  hipLaunchKernelGGL(ae_fold, dim3((unsigned)cdiv(kFoldFloats, kT)), dim3(kT), 0, s, params,
+                     L[0].w_off, L[0].b_off, L[1].w_off, L[1].b_off, L[4].w_off, L[4].b_off,
+                     L[5].w_off, L[5].b_off, fold);
+  return hipGetLastError();
 }
 
 size_t compress_workspace_bytes(int64_t n_elem) { return compress_layout(nullptr, n_elem).bytes; }
@@ -1262,9 +1557,27 @@ hipError_t launch_ae_compress(int64_t n_elem, const float* const* f, const float
                               float* raw, int64_t raw_cap, int64_t* n_raw, void* ws,
                               int32_t* status, hipStream_t s) {
   CompressWs c = compress_layout(ws, n_elem);
-  hipError_t e = launch_ae_scales(n_elem, f, scale, c.gmax, s);
-  if (e != hipSuccess) return e;
-  for (int64_t b = 0; b < n_elem; b += kChunk) {
+  hipError_t e;
+  if (tanh_mask == 0 && n_elem > 0) {
+    // linear network: fused encoder and decoder-check
+    const Layer* L = layers();
+    const unsigned grid = (unsigned)cdiv(n_elem, kEncE);
+    e = launch_fold(params, c.fold, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ae_encode, dim3(grid), dim3(kT), 0, s, n_elem, f[0], f[1], f[2], f[3],
+                       c.fold, params + L[2].w_off, params + L[2].b_off, scale, c.gpart, latent);
+    hipLaunchKernelGGL(fill_u32, dim3(1), dim3(kT), 0, s, c.gmax, 4, 0u);
+    hipLaunchKernelGGL(gmax_k, dim3(grid < 1024 * kT ? (unsigned)cdiv(grid, kT) : 1024u),
+                       dim3(kT), 0, s, c.gpart, (int64_t)grid, c.gmax);
+    hipLaunchKernelGGL((ae_decode<true>), dim3(grid), dim3(kT), 0, s, n_elem, latent, scale,
+                       c.gmax, c.fold, params + L[3].w_off, params + L[3].b_off, f[0], f[1],
+                       f[2], f[3], nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       (int64_t)0, c.flag, status);
+  } else {
+    e = launch_ae_scales(n_elem, f, scale, c.gmax, s);
+    if (e != hipSuccess) return e;
+  }
+  for (int64_t b = 0; b < n_elem && tanh_mask != 0; b += kChunk) {
     const int64_t n = n_elem - b < kChunk ? n_elem - b : kChunk;
     e = launch_ae_pack(b, n, f, scale, c.ae.act[0], s);
     if (e != hipSuccess) return e;
@@ -1294,6 +1607,16 @@ hipError_t launch_ae_decompress(int64_t n_elem, const uint16_t* latent, const fl
                      n_elem, c.flag);
   hipError_t e = launch_exclusive_scan(c.flag, n_elem, c.partial, c.offs, s);
   if (e != hipSuccess) return e;
+  if (tanh_mask == 0) {
+    const Layer* L = layers();
+    e = launch_fold(params, c.fold, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ae_decode<false>), dim3((unsigned)cdiv(n_elem, kEncE)), dim3(kT), 0, s,
+                       n_elem, latent, scale, nullptr, c.fold, params + L[3].w_off,
+                       params + L[3].b_off, nullptr, nullptr, nullptr, nullptr, f[0], f[1], f[2],
+                       f[3], c.flag, c.offs, raw, raw_count, nullptr, status);
+    return hipGetLastError();
+  }
   for (int64_t b = 0; b < n_elem; b += kChunk) {
     const int64_t n = n_elem - b < kChunk ? n_elem - b : kChunk;
     hipLaunchKernelGGL(from_half_bits, dim3((unsigned)cdiv(n * 32, kT)), dim3(kT), 0, s,
