@@ -914,17 +914,27 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t e0 = (int64_t)blockIdx.x * kEncE;
   {
+    // wave wv: element e0 + wv, every value of its four channels by 16-byte
+    // loads, all issued before the first use (elements past the end read
+    // element 0 and are zeroed)
     const int64_t e = e0 + wv;
     const bool ok = e < n_elem;
+    const int64_t eb = (ok ? e : 0) * 512;
     const float* f[4] = {u, v, w, th};
+    float4 val[4][2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        val[c][q] = reinterpret_cast<const float4*>(f[c] + eb)[lane + 64 * q];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      float val[8];
+      float* vv = reinterpret_cast<float*>(val[c]);
       float mx = 0.f;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        val[q] = ok ? f[c][e * 512 + lane + 64 * q] : 0.f;
-        const float a = fabsf(val[q]);
+        if (!ok) vv[q] = 0.f;
+        const float a = fabsf(vv[q]);
         mx = a > mx ? a : mx;
       }
 #pragma unroll
@@ -938,9 +948,9 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int n = lane + 64 * q;
+        const int n = 4 * (lane + 64 * (q >> 2)) + (q & 3);   // node of value q
         const int m = morton8(n & 7, (n >> 3) & 7, n >> 6);
-        xs[(4 * (m & 63) + c) * kRowPad + wv * 8 + (m >> 6)] = mx > 0.f ? val[q] / mx : 0.f;
+        xs[(4 * (m & 63) + c) * kRowPad + wv * 8 + (m >> 6)] = mx > 0.f ? vv[q] / mx : 0.f;
       }
     }
   }
@@ -951,28 +961,27 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
     for (int q = 0; q < kEncE; ++q) g = smax[q][t] > g ? smax[q][t] : g;
     gpart[blockIdx.x * 4 + t] = g;
   }
-  // layers 0-1 folded: [32 rows x 256] x W01 [256 x 64]; wave w: rows 16 (w & 1),
-  // columns 32 (w >> 1) .. + 31
+  // layers 0-1 folded: [32 rows x 256] x W01 [256 x 64]; wave w: both row
+  // tiles, columns 16 w .. 16 w + 15 (one weight load feeds two MFMAs)
   const int lr = lane & 15, lk = lane >> 4;
-  const int rt = wv & 1, c0 = 32 * (wv >> 1);
+  const int c0 = 16 * wv;
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 8
   for (int k = 0; k < 256; k += 4) {
-    const float a = xs[(k + lk) * kRowPad + 16 * rt + lr];
-    const float bb0 = fold[(k + lk) * 64 + c0 + lr];
-    const float bb1 = fold[(k + lk) * 64 + c0 + 16 + lr];
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb0, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bb1, acc1, 0, 0, 0);
+    const float a0 = xs[(k + lk) * kRowPad + lr];
+    const float a1 = xs[(k + lk) * kRowPad + 16 + lr];
+    const float bb = fold[(k + lk) * 64 + c0 + lr];
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bb, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bb, acc1, 0, 0, 0);
   }
   __syncthreads();                          // every read of xs is done
   float* h1 = xs;                           // h1[el][p1 64 + o]
-  const float* b01 = fold + 256 * 64;
+  const float bias = fold[256 * 64 + c0 + lr];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int row = 16 * rt + 4 * lk + r;
-    const int base = (row >> 3) * 512 + (row & 7) * 64;
-    h1[base + c0 + lr] = acc0[r] + b01[c0 + lr];
-    h1[base + c0 + 16 + lr] = acc1[r] + b01[c0 + 16 + lr];
+    const int row0 = 4 * lk + r, row1 = 16 + 4 * lk + r;
+    h1[(row0 >> 3) * 512 + (row0 & 7) * 64 + c0 + lr] = acc0[r] + bias;
+    h1[(row1 >> 3) * 512 + (row1 & 7) * 64 + c0 + lr] = acc1[r] + bias;
   }
   __syncthreads();
   // layer 2: z[el][o] = b2[o] + sum_k h1[el][k] W2[k 32 + o]; wave w = element,
@@ -1024,12 +1033,25 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
   if (t < kEncE * 4) emax[t / 4][t % 4] = 0u;
   if (CHECK) {
     const int64_t e = e0 + wv;
-    const float* f[4] = {iu, iv, iw, ith};
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        fl[wv][c][lane + 64 * q] = e < n_elem ? f[c][e * 512 + lane + 64 * q] : 0.f;
+    const int64_t eb = (e < n_elem ? e : 0) * 512;
+    const float4* g0 = reinterpret_cast<const float4*>(iu + eb);
+    const float4* g1 = reinterpret_cast<const float4*>(iv + eb);
+    const float4* g2 = reinterpret_cast<const float4*>(iw + eb);
+    const float4* g3 = reinterpret_cast<const float4*>(ith + eb);
+    const float4 v00 = g0[lane], v01 = g0[lane + 64], v10 = g1[lane], v11 = g1[lane + 64];
+    const float4 v20 = g2[lane], v21 = g2[lane + 64], v30 = g3[lane], v31 = g3[lane + 64];
+    float4* l0 = reinterpret_cast<float4*>(fl[wv][0]);
+    float4* l1 = reinterpret_cast<float4*>(fl[wv][1]);
+    float4* l2 = reinterpret_cast<float4*>(fl[wv][2]);
+    float4* l3 = reinterpret_cast<float4*>(fl[wv][3]);
+    l0[lane] = v00;
+    l0[lane + 64] = v01;
+    l1[lane] = v10;
+    l1[lane + 64] = v11;
+    l2[lane] = v20;
+    l2[lane + 64] = v21;
+    l3[lane] = v30;
+    l3[lane + 64] = v31;
   }
   __syncthreads();
   // layer 3: h3[el][d 64 + o] = b3[o] + sum_i z[el][i] W3[i 512 + d 64 + o]
@@ -1039,6 +1061,7 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
     float a[kEncE];
 #pragma unroll
     for (int el = 0; el < kEncE; ++el) a[el] = b3[col & 63];
+#pragma unroll 8
     for (int i = 0; i < 32; ++i) {
       const float wi = w3[i * 512 + col];
 #pragma unroll
@@ -1048,25 +1071,31 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
     for (int el = 0; el < kEncE; ++el) h3[(col & 63) * kRowPad + el * 8 + (col >> 6)] = a[el];
   }
   __syncthreads();
-  // layers 4-5 folded: [32 rows x 64] x W45 [64 x 256]; wave w: rows 16 (w & 1),
-  // columns 128 (w >> 1) .. + 127
+  // layers 4-5 folded: [32 rows x 64] x W45 [64 x 256]; wave w: both row
+  // tiles, columns 64 w .. 64 w + 63 (one weight load feeds two MFMAs)
   const int lr = lane & 15, lk = lane >> 4;
-  const int rt = wv & 1, c0 = 128 * (wv >> 1);
+  const int c0 = 64 * wv;
   const float* w45 = fold + 256 * 64 + 64;
   const float* b45 = w45 + 64 * 256;
-  f32x4 acc[8];
+  f32x4 acc[2][4];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
   for (int k = 0; k < 64; k += 4) {
-    const float a = h3[(k + lk) * kRowPad + 16 * rt + lr];
+    const float a0 = h3[(k + lk) * kRowPad + lr];
+    const float a1 = h3[(k + lk) * kRowPad + 16 + lr];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-          a, w45[(k + lk) * 256 + c0 + 16 * j + lr], acc[j], 0, 0, 0);
+    for (int j = 0; j < 4; ++j) {
+      const float bb = w45[(k + lk) * 256 + c0 + 16 * j + lr];
+      acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bb, acc[0][j], 0, 0, 0);
+      acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bb, acc[1][j], 0, 0, 0);
+    }
   }
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int jj = 0; jj < 8; ++jj) {
+    const int j = jj & 3, rt = jj >> 2;
     const int col = c0 + 16 * j + lr, d4 = col >> 5, d5 = (col >> 2) & 7, c = col & 3;
     const float bias = b45[col];
 #pragma unroll
@@ -1075,7 +1104,7 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
       const int node = morton_node(64 * (row & 7) + 8 * d4 + d5);
       const int64_t e = e0 + el;
       const float sc = e < n_elem ? scale[e * 4 + c] : 0.f;
-      const float rec = sc * (acc[j][r] + bias);
+      const float rec = sc * (acc[rt][j][r] + bias);
       if (CHECK) {
         const float d = fabsf(fl[el][c][node] - rec);
         atomicMax(&emax[el][c], __float_as_uint(d));
@@ -1107,9 +1136,11 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int n = lane + 64 * q;
-          f[c][e * 512 + n] = is_raw ? raw[(o * 4 + c) * 512 + n] : fl[wv][c][n];
+        for (int q = 0; q < 2; ++q) {
+          const int n4 = lane + 64 * q;
+          reinterpret_cast<float4*>(f[c] + e * 512)[n4] =
+              is_raw ? reinterpret_cast<const float4*>(raw + (o * 4 + c) * 512)[n4]
+                     : reinterpret_cast<const float4*>(fl[wv][c])[n4];
         }
     }
   }
