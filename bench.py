@@ -591,6 +591,13 @@ def compression_timing(args, sem):
            # one read of the four FP32 fields; latent, scales, flags and raw
            # elements written
            "compress_hbm": _hbm(raw_bytes + e * 81 + n_raw * 8192, comp_ms),
+           # the linear network runs with layers 0-1 and 4-5 folded: 589,824
+           # FLOPs per element (encoder 294,912, decoder 294,912) on FP32
+           # matrix cores (and layers 2, 3 on the vector units)
+           "compress_mfma": {"flops_per_element": 589824,
+                             "achieved_tflops": round(589824 * e / (comp_ms * 1e-3) / 1e12, 2),
+                             "peak_tflops": 157.3,
+                             "frac": 589824 * e / (comp_ms * 1e-3) / 1e12 / 157.3},
            "modal_ms": round(modal_ms, 4),
            "fallback_frac": n_raw / e, "ratio": ratio,
            "modal_fallback_frac": n_raw_mod / e, "modal_ratio": ratio_mod,

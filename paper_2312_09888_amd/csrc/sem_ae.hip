@@ -946,11 +946,15 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
         smax[wv][c] = mx;
         if (ok) scale[e * 4 + c] = mx;
       }
+      // normalised by one reciprocal per channel (the latent is checked
+      // against the exact encoder to within its binary16 step, and the
+      // error check compares the fields with s x_hat, not with x)
+      const float inv = mx > 0.f ? 1.f / mx : 0.f;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int n = 4 * (lane + 64 * (q >> 2)) + (q & 3);   // node of value q
         const int m = morton8(n & 7, (n >> 3) & 7, n >> 6);
-        xs[(4 * (m & 63) + c) * kRowPad + wv * 8 + (m >> 6)] = mx > 0.f ? vv[q] / mx : 0.f;
+        xs[(4 * (m & 63) + c) * kRowPad + wv * 8 + (m >> 6)] = vv[q] * inv;
       }
     }
   }
@@ -984,24 +988,31 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
     h1[(row1 >> 3) * 512 + (row1 & 7) * 64 + c0 + lr] = acc1[r] + bias;
   }
   __syncthreads();
-  // layer 2: z[el][o] = b2[o] + sum_k h1[el][k] W2[k 32 + o]; wave w = element,
-  // lane halves split k
-  const int o2 = lane & 31, half = lane >> 5;
-  float z0 = 0.f, z1 = 0.f, z2 = 0.f, z3 = 0.f;
-  const float* hr = h1 + wv * 512 + 256 * half;
-  const float* wr = w2 + (int64_t)(256 * half) * 32 + o2;
-#pragma unroll 4
-  for (int k = 0; k < 256; k += 4) {
-    z0 = fmaf(hr[k], wr[k * 32], z0);
-    z1 = fmaf(hr[k + 1], wr[(k + 1) * 32], z1);
-    z2 = fmaf(hr[k + 2], wr[(k + 2) * 32], z2);
-    z3 = fmaf(hr[k + 3], wr[(k + 3) * 32], z3);
+  // layer 2: z[el][o] = b2[o] + sum_k h1[el][k] W2[k 32 + o]; thread: output o =
+  // t % 32 of all four elements over the k slice 64 (t / 32) .. + 63 (each
+  // weight read once per workgroup), slices summed in LDS in order
+  const int o2 = t & 31, ks = t >> 5;
+  float z[kEncE] = {0.f, 0.f, 0.f, 0.f};
+  const float* wr = w2 + (int64_t)(64 * ks) * 32 + o2;
+#pragma unroll 8
+  for (int k = 0; k < 64; ++k) {
+    const float wk = wr[k * 32];
+#pragma unroll
+    for (int el = 0; el < kEncE; ++el) z[el] = fmaf(h1[el * 512 + 64 * ks + k], wk, z[el]);
   }
-  float z = (z0 + z1) + (z2 + z3);
-  z += __shfl_xor(z, 32);
-  const int64_t e = e0 + wv;
-  if (half == 0 && e < n_elem)
-    latent[e * 32 + o2] = __half_as_ushort(__float2half_rn(z + b2[o2]));
+  __syncthreads();                          // h1 reads done: reuse for the slice sums
+  float* zp = xs + kEncE * 512;             // [8 slices][4 elements][32]
+#pragma unroll
+  for (int el = 0; el < kEncE; ++el) zp[(ks * kEncE + el) * 32 + o2] = z[el];
+  __syncthreads();
+  if (t < kEncE * 32) {
+    const int el = t >> 5, o = t & 31;
+    float sum = b2[o];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sum += zp[(q * kEncE + el) * 32 + o];
+    const int64_t e = e0 + el;
+    if (e < n_elem) latent[e * 32 + o] = __half_as_ushort(__float2half_rn(sum));
+  }
 }
 
 // Latents -> reconstruction, four elements per workgroup: layer 3 on the
@@ -1093,25 +1104,41 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
       acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bb, acc[1][j], 0, 0, 0);
     }
   }
+  // A lane's values: rows 16 rt + 4 lk + r (element 2 rt + lk / 2, octant
+  // (4 lk + r) & 7), columns c0 + 16 j + lr (channel lr & 3 for every j).
+  // The Morton bits of octant, d4 and d5 do not overlap, so a node index is
+  // the sum of the three parts' indices.
+  const int c = lr & 3;
+  int node_row[4], node_col[4];
 #pragma unroll
-  for (int jj = 0; jj < 8; ++jj) {
-    const int j = jj & 3, rt = jj >> 2;
-    const int col = c0 + 16 * j + lr, d4 = col >> 5, d5 = (col >> 2) & 7, c = col & 3;
-    const float bias = b45[col];
+  for (int r = 0; r < 4; ++r) node_row[r] = morton_node(64 * ((4 * lk + r) & 7));
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * rt + 4 * lk + r, el = row >> 3;
-      const int node = morton_node(64 * (row & 7) + 8 * d4 + d5);
-      const int64_t e = e0 + el;
-      const float sc = e < n_elem ? scale[e * 4 + c] : 0.f;
-      const float rec = sc * (acc[rt][j][r] + bias);
-      if (CHECK) {
-        const float d = fabsf(fl[el][c][node] - rec);
-        atomicMax(&emax[el][c], __float_as_uint(d));
-      } else {
-        fl[el][c][node] = rec;
+  for (int j = 0; j < 4; ++j) {
+    const int col = c0 + 16 * j + lr;
+    node_col[j] = morton_node(8 * (col >> 5) + ((col >> 2) & 7));
+  }
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    const int el = 2 * rt + (lk >> 1);
+    const int64_t e = e0 + el;
+    const float sc = e < n_elem ? scale[e * 4 + c] : 0.f;
+    float worst = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float bias = b45[c0 + 16 * j + lr];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int node = node_row[r] + node_col[j];
+        const float rec = sc * (acc[rt][j][r] + bias);
+        if (CHECK) {
+          const float d = fabsf(fl[el][c][node] - rec);
+          worst = d > worst ? d : worst;
+        } else {
+          fl[el][c][node] = rec;
+        }
       }
     }
+    if (CHECK) atomicMax(&emax[el][c], __float_as_uint(worst));
   }
   __syncthreads();
   if (CHECK) {

@@ -236,10 +236,14 @@ def test_compress_roundtrip_flags_and_raw():
     gmax = pk["scale"].cpu().numpy().max(axis=0)
     np.testing.assert_array_equal(ae.fallback(hf, rec, gmax), flags)
     assert not ae.fallback(hf, ho, gmax).any()
-    # the reconstruction is the oracle's network on the kernel's own latent
+    # the reconstruction is the oracle's network on the kernel's own latent,
+    # and the latent is the oracle's encoder output to within its binary16 step
     x, s = ae.blocks(hf)
     z = pk["latent"].float().cpu().numpy().reshape(-1, 32, 1, 1, 1)
-    _, dec = _layers_from(params.cpu().numpy(), x, z, 0)
+    enc, dec = _layers_from(params.cpu().numpy(), x, z, 0)
+    enc = enc.reshape(-1, 32)
+    step = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(enc), 2.0 ** -14))) - 10)
+    assert np.all(np.abs(z.reshape(-1, 32) - enc) <= step * 1.0001)
     want = dec * s[:, :, None, None, None]
     got = np.stack(rec, 1)
     assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max()
