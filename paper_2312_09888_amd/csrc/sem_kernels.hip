@@ -634,33 +634,63 @@ __device__ __forceinline__ uint32_t cell_word(const uint32_t* bits, int n0) {
 __device__ __forceinline__ int case_count_entry(int cs, uint8_t nt) {
   return (int)nt + ((cs != 0 && cs != 255) << 16);
 }
-// Element totals of the isovalues g .. g + m - 1 from per-thread packed
-// sums: wave sums into red[4 * NW], one barrier, threads t < m write.
-// red must not be read again before a later barrier.
-template <int NW>
-__device__ __forceinline__ void publish_counts(const int (&packed)[4], int m, int g, int t,
-                                               int32_t* red, int32_t* cnt, int64_t n_elem,
-                                               int64_t e, int64_t* active) {
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (s < m) {
-      int v = packed[s];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if ((t & 63) == 0) red[NW * s + (t >> 6)] = v;
-    }
-  }
-  __syncthreads();
-  if (t < m) {
-    int sum = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) sum += red[NW * t + w];
-    cnt[(int64_t)(g + t) * n_elem + e] = sum & 0xffff;
-    const int a = sum >> 16;
-    if (active && a) atomicAdd((unsigned long long*)&active[g + t], (unsigned long long)a);
-  }
+// Sum over the 16 lanes of each row of the wave, by DPP row shifts (lanes
+// shifted in from outside the row read 0): lane 15 of the row ends with the
+// row's sum (the others with partial sums).  Four VALU operations, no LDS.
+__device__ __forceinline__ uint32_t row_sum16(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  return v;
 }
 
+// Order-7 cell c = i + 7 j + 49 k has corner 0 at node i + 8 j + 64 k =
+// c + c / 7 + 8 (c / 49); the divisions by multiply and shift, exact for
+// c < 512 (the rounding errors stay below the gap to the next integer).
+__device__ __forceinline__ int cell_base7(int c) {
+  return c + ((c * 9363) >> 16) + 8 * ((c * 1338) >> 16);
+}
+
+// Case-table entry for packed counting: triangles + (1 << 8) for a
+// non-trivial case.
+__device__ __forceinline__ int case_count_entry8(int cs, uint8_t nt) {
+  return (int)nt + ((cs != 0 && cs != 255) << 8);
+}
+
+// Element counts of the isovalues g .. g + m - 1 (m <= 4) for a workgroup
+// of NW <= 4 waves with at most three cells per lane: pw[s >> 1] holds, in
+// its 16-bit half s & 1, the lane's triangles + (active cells << 8) of
+// isovalue s (at most 3 x 5 triangles per lane, so a row of 16 lanes stays
+// below 240 + (48 << 8)).  DPP row sums, the 4 NW row sums through s_rows
+// (8 NW words), one barrier, then wave 0 sums the rows of each isovalue.
+// s_rows must not be written again before a later barrier.
+template <int NW>
+__device__ __forceinline__ void publish_rows(uint32_t (&pw)[2], int m, int g, int t,
+                                             uint32_t* s_rows, int32_t* __restrict__ cnt,
+                                             int64_t n_elem, int64_t e,
+                                             int64_t* __restrict__ active) {
+  static_assert(NW >= 1 && NW <= 4, "at most 16 rows");
+  const int h = t >> 6, p = t & 63;
+  pw[0] = row_sum16(pw[0]);
+  if (m > 2) pw[1] = row_sum16(pw[1]);
+  if ((p & 15) == 15) {
+    s_rows[2 * (4 * h + (p >> 4))] = pw[0];
+    s_rows[2 * (4 * h + (p >> 4)) + 1] = pw[1];
+  }
+  __syncthreads();
+  if (h == 0) {
+    const int row = p & 15, s = p >> 4;   // lane: one row's field of isovalue s
+    const uint32_t f =
+        row < 4 * NW ? (s_rows[2 * row + (s >> 1)] >> (16 * (s & 1))) & 0xffffu : 0u;
+    const uint32_t sum = row_sum16((f & 255u) | ((f >> 8) << 16));
+    if (row == 15 && s < m) {
+      cnt[(int64_t)(g + s) * n_elem + e] = (int)(sum & 0xffffu);
+      const unsigned a = sum >> 16;
+      if (active && a) atomicAdd((unsigned long long*)&active[g + s], (unsigned long long)a);
+    }
+  }
+}
 // Where a Q kernel also counts each isovalue's triangles and active cells per
 // element (the count pass of the isosurface, fused).
 template <typename T>
@@ -776,7 +806,7 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   constexpr int P = Q::P, H0 = Q::H0;
   __shared__ PencilTiles<N, T, E> sm;
   __shared__ int32_t s_tab[COUNT ? 256 : 1];
-  __shared__ int32_t s_sum[COUNT && E == 1 ? 4 * Q::TH / 64 : 1];
+  __shared__ uint32_t s_rows[COUNT && E == 1 ? 2 * Q::TH / 64 * 4 : 1];
   __shared__ T s_part[E > 1 ? 2 * Q::TH : 1];   // per-thread (min, max) of Q
   __shared__ T s_emm[E > 1 && COUNT ? 2 * E : 1];
   const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
@@ -785,7 +815,10 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   const int nl = E == 1 ? Q::NP : ne * Q::NP;   // lines of elements that exist
   if constexpr (COUNT) {
     // case table, published by the barriers of the passes
-    for (int c = t; c < 256; c += Q::TH) s_tab[c] = case_count_entry(c, sink->ntri[c]);
+    // (the several-element tail packs active cells at bit 16, the
+    // one-element form at bit 8)
+    for (int c = t; c < 256; c += Q::TH)
+      s_tab[c] = E == 1 ? case_count_entry8(c, sink->ntri[c]) : case_count_entry(c, sink->ntri[c]);
   }
   T qv[H0], ov[H0];
   int bad = !pencil_qcrit<N, E>(x + base, y + base, z + base, u + base, v + base, w + base,
@@ -816,8 +849,9 @@ __device__ __forceinline__ void qcrit_pencil_elem(
     s_part[t] = mn;
     s_part[Q::TH + t] = mx;
   }
-  bad = __syncthreads_or(bad);   // also publishes the Q tile
-  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  // an inverted element (rare) is flagged by its own lanes: no block vote
+  if (bad && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  __syncthreads();               // publishes the Q tile
   if constexpr (E > 1) {
     pencil_multi_tail<N, T, COUNT, E>(e, t, ne, qv, sm.F, s_part, s_emm, s_tab, qmm, sink);
     return;
@@ -829,10 +863,11 @@ __device__ __forceinline__ void qcrit_pencil_elem(
       qmm[2 * e + 1] = mx;
     }
   }
-  if constexpr (COUNT) {
+  if constexpr (COUNT && E == 1) {
     // cells t, t + TH, ...; node words in F
     constexpr int NC = N * N * N, R = (NC + Q::TH - 1) / Q::TH, NW = Q::TH / 64;
     uint32_t* bits = reinterpret_cast<uint32_t*>(sm.F);
+    static_assert(R <= 3, "publish_rows takes at most three cells per lane");
     int n0[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -858,7 +893,7 @@ __device__ __forceinline__ void qcrit_pencil_elem(
       bool live = false;
       for (int s = 0; s < m; ++s)
         live |= (mx > sink->iso.v[g + s]) && !(mn > sink->iso.v[g + s]);
-      int packed[4] = {0, 0, 0, 0};
+      uint32_t pw[2] = {0u, 0u};
       if (live) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -866,10 +901,10 @@ __device__ __forceinline__ void qcrit_pencil_elem(
           const uint32_t word = cell_word<Q::RS, Q::SS>(bits, n0[r]);
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            if (s < m) packed[s] += s_tab[(word >> (8 * s)) & 255];
+            if (s < m) pw[s >> 1] += (uint32_t)s_tab[(word >> (8 * s)) & 255] << (16 * (s & 1));
         }
       }
-      publish_counts<NW>(packed, m, g, t, s_sum, sink->cnt, sink->n_elem, e, sink->active);
+      publish_rows<NW>(pw, m, g, t, s_rows, sink->cnt, sink->n_elem, e, sink->active);
     }
   }
 }
@@ -1505,17 +1540,6 @@ __device__ __forceinline__ int wave_sum_i32(const WaveXor& w, int v) {
   return v;
 }
 
-// Sum over the 16 lanes of each row of the wave, by DPP row shifts (lanes
-// shifted in from outside the row read 0): lane 15 of the row ends with the
-// row's sum (the others with partial sums).  Four VALU operations, no LDS.
-__device__ __forceinline__ uint32_t row_sum16(uint32_t v) {
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);   // row_shr:1
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);   // row_shr:2
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);   // row_shr:4
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);   // row_shr:8
-  return v;
-}
-
 // COUNT: also count every isovalue's triangles and active cells per element
 // from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
 template <bool COUNT>
@@ -1634,7 +1658,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
   int32_t* s_tab = reinterpret_cast<int32_t*>(s_T);
   const int node0 = h + 8 * j + 64 * k, node1 = 7 - h + 8 * j + 64 * k;
   if constexpr (COUNT) {
-    s_tab[t] = (int)nt_own + ((t != 0 && t != 255) << 8);
+    s_tab[t] = case_count_entry8(t, nt_own);
     s_bits[node0] = iso_bits4(qv[0], iso, 0, n_iso);
     s_bits[node1] = iso_bits4(qv[1], iso, 0, n_iso);
   }
@@ -1662,11 +1686,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
     constexpr int NC2 = NC - 256;
     const bool two = t < NC2;
     const int c1 = two ? t + 256 : t;
-    // cell c = i + 7 j + 49 k has corner 0 at node i + 8 j + 64 k =
-    // c + c / 7 + 8 (c / 49); the divisions by multiply and shift (exact for
-    // c < 512: the rounding errors stay below the gap to the next integer)
-    const int cb[2] = {t + ((t * 9363) >> 16) + 8 * ((t * 1338) >> 16),
-                       c1 + ((c1 * 9363) >> 16) + 8 * ((c1 * 1338) >> 16)};
+    const int cb[2] = {cell_base7(t), cell_base7(c1)};
     for (int g = 0; g < n_iso; g += 4) {
       const int m = n_iso - g < 4 ? n_iso - g : 4;
       if (g > 0) {   // every read of the previous words is behind the last barrier
@@ -1678,9 +1698,8 @@ __device__ __forceinline__ void qcount_dma7_elem(
       // trivial cases (NaN nodes count as below; mn is -inf then)
       bool live = false;
       for (int s = 0; s < m; ++s) live |= (mx > iso.v[g + s]) && !(mn > iso.v[g + s]);
-      // A lane's cells give, per isovalue s, triangles + (active << 8) in
-      // the 16-bit half s & 1 of word s >> 1 (at most 2 cells x 5 triangles
-      // per lane, so a row of 16 lanes stays below 160 + (32 << 8)).
+      // a lane's cells: per isovalue s, triangles + (active << 8) in the
+      // 16-bit half s & 1 of word s >> 1 (publish_rows)
       uint32_t pw[2] = {0u, 0u};
       if (live) {
 #pragma unroll
@@ -1697,24 +1716,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
           }
         }
       }
-      // row sums, then the 16 rows of the element's four waves in wave 0
-      pw[0] = row_sum16(pw[0]);
-      if (m > 2) pw[1] = row_sum16(pw[1]);
-      if ((p & 15) == 15) {
-        s_rows[2 * (4 * h + (p >> 4))] = pw[0];
-        s_rows[2 * (4 * h + (p >> 4)) + 1] = pw[1];
-      }
-      __syncthreads();
-      if (h == 0) {
-        const int row = p & 15, s = p >> 4;   // lane: one row's field of isovalue s
-        const uint32_t f = (s_rows[2 * row + (s >> 1)] >> (16 * (s & 1))) & 0xffffu;
-        const uint32_t sum = row_sum16((f & 255u) | ((f >> 8) << 16));
-        if (row == 15 && s < m) {
-          cnt[(int64_t)(g + s) * n_elem + e] = (int)(sum & 0xffffu);
-          const unsigned a = sum >> 16;
-          if (active && a) atomicAdd((unsigned long long*)&active[g + s], (unsigned long long)a);
-        }
-      }
+      publish_rows<4>(pw, m, g, t, s_rows, cnt, n_elem, e, active);
     }
   }
 }
@@ -2163,9 +2165,9 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
   __shared__ float s_d[2][3 * kMixDT];
   __shared__ float s_red[8];
   __shared__ int32_t s_tab[COUNT ? 256 : 1];
-  __shared__ int32_t s_sum[COUNT ? 16 : 1];
+  __shared__ uint32_t s_rows[COUNT ? 32 : 1];
   const int t = threadIdx.x, lane = t & 63;
-  if constexpr (COUNT) s_tab[t] = case_count_entry(t, sink.ntri[t]);
+  if constexpr (COUNT) s_tab[t] = case_count_entry8(t, sink.ntri[t]);
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int64_t base = (int64_t)blockIdx.x * 512;
   const float* src[6] = {x, y, z, u, v, w};
@@ -2225,8 +2227,9 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
       a[h][c][2] = fr * K.rz + fs * K.sz + ft * K.tz;
     }
   }
-  bad = __syncthreads_or(bad);
-  if (bad && t == 0 && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  // an inverted element (rare) is flagged by its own lanes: no block vote
+  if (bad && status) atomicOr(status, SEM_FLAG_BAD_JACOBIAN);
+  __syncthreads();
   if constexpr (!QC) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -2267,10 +2270,7 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
       constexpr int NC = 343;
       int n0[2];
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const int cc = t + 256 * r < NC ? t + 256 * r : t;
-        n0[r] = cc % 7 + 8 * ((cc / 7) % 7) + 64 * (cc / 49);
-      }
+      for (int r = 0; r < 2; ++r) n0[r] = cell_base7(t + 256 * r < NC ? t + 256 * r : t);
       const int64_t e = blockIdx.x;
       const int n_iso = sink.n_iso;
       for (int g = 0; g < n_iso; g += 4) {
@@ -2282,7 +2282,7 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
         }
         bool live = false;   // (NaN nodes count as below; mn is -inf then)
         for (int s = 0; s < m; ++s) live |= (mx > sink.iso.v[g + s]) && !(mn > sink.iso.v[g + s]);
-        int packed[4] = {0, 0, 0, 0};
+        uint32_t pw[2] = {0u, 0u};
         if (live) {
 #pragma unroll
           for (int r = 0; r < 2; ++r) {
@@ -2290,10 +2290,10 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
             const uint32_t word = cell_word<8, 64>(bits, n0[r]);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-              if (s < m) packed[s] += s_tab[(word >> (8 * s)) & 255];
+              if (s < m) pw[s >> 1] += (uint32_t)s_tab[(word >> (8 * s)) & 255] << (16 * (s & 1));
           }
         }
-        publish_counts<4>(packed, m, g, t, s_sum, sink.cnt, sink.n_elem, e, sink.active);
+        publish_rows<4>(pw, m, g, t, s_rows, sink.cnt, sink.n_elem, e, sink.active);
       }
     }
   }
