@@ -167,8 +167,9 @@ int sem_init(int device) {
     bytes += align256(sizeof(double) * ((n + 1) * (n + 1) + 2 * ne * ne));
   }
   for (int n = 1; n <= kMaxOrder; ++n) {
+    const int ne = (n + 2) / 2;
     off32[n] = bytes;
-    bytes += align256(sizeof(float) * (n + 1) * (n + 1));
+    bytes += align256(sizeof(float) * ((n + 1) * (n + 1) + 2 * ne * ne));
   }
   // the case table directly follows the 256 triangle counts: kernels copy
   // both as one 4 KiB block
@@ -182,8 +183,6 @@ int sem_init(int device) {
   for (int n = 1; n <= kMaxOrder; ++n) {
     double* d = reinterpret_cast<double*>(host.data() + off64[n]);
     gll_basis(n, nullptr, nullptr, d);
-    float* f = reinterpret_cast<float*>(host.data() + off32[n]);
-    for (int q = 0; q < (n + 1) * (n + 1); ++q) f[q] = (float)d[q];
     // even-odd halves of D (D[P-1-i][P-1-m] = -D[i][m] on the symmetric GLL
     // nodes), P = n + 1, H = P / 2 node pairs, NE = ceil(P / 2) rows:
     // A[i][m] = (D[i][m] + D[i][P-1-m]) / 2 for m < H and A[i][H] = D[i][H]
@@ -200,6 +199,9 @@ int sem_init(int device) {
       }
       if (p % 2) a[ne * i + hp] = d[p * i + hp];
     }
+    // FP32 copy of D and of its halves (each rounded from its FP64 value)
+    float* f = reinterpret_cast<float*>(host.data() + off32[n]);
+    for (int q = 0; q < p * p + 2 * ne * ne; ++q) f[q] = (float)d[q];
   }
   build_mc_table(host.data() + off_ntri, reinterpret_cast<int8_t*>(host.data() + off_tri));
   {
@@ -462,7 +464,8 @@ int sem_batch_plan(int n_snap, const sem_snapshot* snaps, sem_dtype dt, void* pl
       b.q = sn.q;
       b.om = sn.omega_mag;
       b.qmm = sn.q_minmax;
-      b.dmat = tab->d64[n];   // line sums run in FP64 for either precision
+      b.dmat = dt == SEM_F32 && f32_line_sums(n) ? (const void*)tab->d32[n]
+                                                 : (const void*)tab->d64[n];
       b.eo = tab->eo7;
       items += (sn.n_elem + chunk - 1) / chunk;
     }

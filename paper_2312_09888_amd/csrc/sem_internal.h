@@ -14,6 +14,12 @@ constexpr int kMaxBasisOrder = 15;          // host basis queries
 constexpr int kMaxOrder = SEM_MAX_ORDER;    // kernels
 constexpr int kMcMaxTri = SEM_MC_MAX_TRI;
 
+// FP32 fields: line sums of orders up to kF32SumOrder run in FP32 with the
+// FP32-rounded D and even-odd halves; higher orders sum in FP64 with the
+// FP64 tables.
+constexpr int kF32SumOrder = 8;
+constexpr bool f32_line_sums(int order) { return order <= kF32SumOrder; }
+
 // sem_basis.cpp
 bool gll_basis(int n, double* nodes, double* weights, double* dmat);
 // sem_mctable.cpp
@@ -21,7 +27,10 @@ void build_mc_table(uint8_t* ntri, int8_t* tri);
 
 // Device-resident constant tables of one GPU.
 struct DeviceTables {
-  const double* d64[kMaxOrder + 1];   // row-major (N+1)^2 per order
+  // D of each order, row-major (N+1)^2, followed by its even-odd halves
+  // A[NE][NE], B[NE][NE] (NE = ceil((N+1)/2)): FP64, and the same values
+  // rounded to FP32
+  const double* d64[kMaxOrder + 1];
   const float* d32[kMaxOrder + 1];
   const uint8_t* ntri;                // [256]
   const int8_t* tri;                  // [256][kMcMaxTri][3]
@@ -82,7 +91,7 @@ struct BatchSnap {
   void* q;
   void* om;
   void* qmm;
-  const void* dmat;     // FP64 D of this order
+  const void* dmat;     // D and its halves in the line sums' type (d64 or d32)
   const void* eo;       // even-odd halves of D (order 7)
 };
 constexpr int kBatchMaxSnap = 4096;

@@ -132,25 +132,31 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* scra
   return before + inc - v;
 }
 
-// 1-D contractions at node (i, j, k) of a tile in LDS, line-shifted.  The
-// sums run in FP64 with the FP64 D for either field precision: in FP32 the
-// rounding of D and of an FP32 running sum would cost up to 3e-5 normwise
-// in Q at N = 9, and FP64 FMAs issue at the unpacked FP32 rate.
+// Coefficient type of the line sums: FP64 with the FP64 D for FP64 fields;
+// for FP32 fields FP32 with the FP32-rounded D up to order kF32SumOrder
+// (within the FP32 bound there; FP32 FMAs need no conversions and half the
+// registers), FP64 above it.
 template <int N, typename T>
+using coef_t = typename std::conditional<std::is_same<T, float>::value && f32_line_sums(N),
+                                         float, double>::type;
+
+// 1-D contractions at node (i, j, k) of a tile in LDS, line-shifted, summed
+// in the coefficient type C.
+template <int N, typename T, typename C>
 __device__ __forceinline__ void ref_derivs(const T* __restrict__ f,
-                                           const double* __restrict__ d, int i, int j, int k,
+                                           const C* __restrict__ d, int i, int j, int k,
                                            T& fr, T& fs, T& ft) {
   constexpr int P = N + 1;
   const T* lr = f + (k * P + j) * P;   // line along i
   const T* ls = f + k * P * P + i;     // along j, stride P
   const T* lt = f + j * P + i;         // along k, stride P^2
-  const double r0 = lr[0], s0 = ls[0], t0 = lt[0];
-  double ar = 0.0, as = 0.0, at = 0.0;
+  const C r0 = lr[0], s0 = ls[0], t0 = lt[0];
+  C ar = C(0), as = C(0), at = C(0);
 #pragma unroll
   for (int m = 1; m < P; ++m) {
-    ar = fma(d[i * P + m], (double)lr[m] - r0, ar);
-    as = fma(d[j * P + m], (double)ls[m * P] - s0, as);
-    at = fma(d[k * P + m], (double)lt[m * P * P] - t0, at);
+    ar = fma(d[i * P + m], (C)lr[m] - r0, ar);
+    as = fma(d[j * P + m], (C)ls[m * P] - s0, as);
+    at = fma(d[k * P + m], (C)lt[m * P * P] - t0, at);
   }
   fr = (T)ar;
   fs = (T)as;
@@ -207,11 +213,11 @@ __device__ __forceinline__ bool adjugate_jacobian(double xr, double xs, double x
 
 template <int N, typename T>
 __global__ void __launch_bounds__(Shape<N>::kNodeThreads)
-derivs_tile(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+derivs_tile(const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
             const T* __restrict__ z, const T* __restrict__ f, T* __restrict__ gx,
             T* __restrict__ gy, T* __restrict__ gz, int32_t* __restrict__ status) {
   using S = Shape<N>;
-  __shared__ double sd[S::P * S::P];
+  __shared__ coef_t<N, T> sd[S::P * S::P];
   __shared__ T sf[4][S::NP];
   const int t = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * S::NP;
@@ -243,12 +249,12 @@ derivs_tile(const double* __restrict__ dmat, const T* __restrict__ x, const T* _
 
 template <int N, typename T>
 __device__ __forceinline__ void qcrit_tile_elem(
-    int64_t e, int t, const double* __restrict__ dmat, const T* __restrict__ x,
+    int64_t e, int t, const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x,
     const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
     const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
     T* __restrict__ qmm, int32_t* __restrict__ status) {
   using S = Shape<N>;
-  __shared__ double sd[S::P * S::P];
+  __shared__ coef_t<N, T> sd[S::P * S::P];
   __shared__ T sf[6][S::NP];
   __shared__ T red[2 * (S::kNodeThreads / 64)];
   const int64_t base = e * S::NP;
@@ -304,7 +310,7 @@ __device__ __forceinline__ void qcrit_tile_elem(
 
 template <int N, typename T>
 __global__ void __launch_bounds__(Shape<N>::kNodeThreads)
-qcrit_tile(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+qcrit_tile(const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
            const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
            const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
            T* __restrict__ qmm, int32_t* __restrict__ status) {
@@ -353,35 +359,39 @@ struct Pen {
 // constant address space: the index is wave-uniform, so every read is a
 // scalar load whatever stores precede it in the kernel.
 using const_f64 = const __attribute__((address_space(4))) double*;
+using const_f32 = const __attribute__((address_space(4))) float*;
 __device__ __forceinline__ double coef(const double* p, int idx) {
   return ((const_f64)p)[idx];
 }
+__device__ __forceinline__ float coef(const float* p, int idx) {
+  return ((const_f32)p)[idx];
+}
 
 // Line-shifted derivative of a P-point line: out[i] = sum_m D[i][m] (g_m - g_0),
-// summed in FP64 with the FP64 D for either field precision (as ref_derivs).
-template <int P, typename T>
-__device__ __forceinline__ T line_deriv(const double* __restrict__ d, int i, const T (&g)[P]) {
-  double acc = 0.0;
-  const double g0 = g[0];
+// summed in the coefficient type C (as ref_derivs).
+template <int P, typename T, typename C>
+__device__ __forceinline__ T line_deriv(const C* __restrict__ d, int i, const T (&g)[P]) {
+  C acc = C(0);
+  const C g0 = g[0];
 #pragma unroll
-  for (int m = 1; m < P; ++m) acc = fma(coef(d, i * P + m), (double)g[m] - g0, acc);
+  for (int m = 1; m < P; ++m) acc = fma(coef(d, i * P + m), (C)g[m] - g0, acc);
   return (T)acc;
 }
 
 // All P outputs of one line (line-shifted as line_deriv) through the
 // even-odd halves of D stored after D itself: an output pair (i, P-1-i)
 // costs P multiply-adds instead of 2 (P - 1).
-template <int P, typename T>
-__device__ __forceinline__ void line_deriv_all(const double* __restrict__ d, const T (&g)[P],
+template <int P, typename T, typename C>
+__device__ __forceinline__ void line_deriv_all(const C* __restrict__ d, const T (&g)[P],
                                                T (&out)[P]) {
   constexpr int H = P / 2, NE = (P + 1) / 2;
-  const double* a = d + P * P;
-  const double* b = a + NE * NE;
-  const double g0 = g[0];
-  double hv[P], e[NE], o[H > 0 ? H : 1];
-  hv[0] = 0.0;
+  const C* a = d + P * P;
+  const C* b = a + NE * NE;
+  const C g0 = g[0];
+  C hv[P], e[NE], o[H > 0 ? H : 1];
+  hv[0] = C(0);
 #pragma unroll
-  for (int m = 1; m < P; ++m) hv[m] = (double)g[m] - g0;
+  for (int m = 1; m < P; ++m) hv[m] = (C)g[m] - g0;
 #pragma unroll
   for (int m = 0; m < H; ++m) {
     e[m] = hv[m] + hv[P - 1 - m];
@@ -390,7 +400,7 @@ __device__ __forceinline__ void line_deriv_all(const double* __restrict__ d, con
   if constexpr (P % 2 == 1) e[H] = hv[H];
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
-    double pe = coef(a, NE * i) * e[0], ro = 0.0;
+    C pe = coef(a, NE * i) * e[0], ro = C(0);
 #pragma unroll
     for (int m = 1; m < NE; ++m) pe = fma(coef(a, NE * i + m), e[m], pe);
 #pragma unroll
@@ -417,7 +427,8 @@ __device__ __forceinline__ void pencil_load(const T* __restrict__ gf, int p, int
 }
 
 template <int N, int E = 1, typename T>
-__device__ __forceinline__ void pencil_pass(const T (&f)[N + 1], const double* __restrict__ d,
+__device__ __forceinline__ void pencil_pass(const T (&f)[N + 1],
+                                            const coef_t<N, T>* __restrict__ d,
                                             T* __restrict__ F, T* __restrict__ S,
                                             T* __restrict__ Tt, int h, int p,
                                             T (&fr)[Pen<N>::H0], T (&fs)[Pen<N>::H0],
@@ -485,7 +496,8 @@ struct PencilTiles {
 // needed afterwards).
 template <int N, int E = 1, typename T>
 __device__ __forceinline__ bool pencil_geometry(const T (&lx)[N + 1], const T (&ly)[N + 1],
-                                                const T (&lz)[N + 1], const double* __restrict__ d,
+                                                const T (&lz)[N + 1],
+                                                const coef_t<N, T>* __restrict__ d,
                                                 PencilTiles<N, T, E>& sm, T* FX, T* FY, T* FZ,
                                                 int h, int p, InvJac<T> (&kk)[Pen<N>::H0]) {
   constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
@@ -505,7 +517,7 @@ __device__ __forceinline__ bool pencil_geometry(const T (&lx)[N + 1], const T (&
 
 template <int N, typename T>
 __global__ void __launch_bounds__(Pen<N>::TH)
-derivs_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+derivs_pencil(const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
               const T* __restrict__ z, const T* __restrict__ f, T* __restrict__ gx,
               T* __restrict__ gy, T* __restrict__ gz, int32_t* __restrict__ status) {
   using Q = Pen<N>;
@@ -547,7 +559,7 @@ derivs_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T*
 template <int N, int E = 1, typename T>
 __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* gz,
                                              const T* gu, const T* gv, const T* gw,
-                                             const double* __restrict__ d,
+                                             const coef_t<N, T>* __restrict__ d,
                                              PencilTiles<N, T, E>& sm, T* FX, T* FY, T* FZ,
                                              int h, int p, int nl, T (&qv)[Pen<N>::H0],
                                              T (&om)[Pen<N>::H0]) {
@@ -797,7 +809,7 @@ __device__ __forceinline__ void pencil_multi_tail(int64_t e, int t, int ne,
 // One workgroup over the elements e .. e + ne - 1 (E of them at most).
 template <int N, typename T, bool COUNT = false, int E = 1>
 __device__ __forceinline__ void qcrit_pencil_elem(
-    int64_t e, int t, const double* __restrict__ dmat, const T* __restrict__ x,
+    int64_t e, int t, const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x,
     const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
     const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
     T* __restrict__ qmm, int32_t* __restrict__ status, const CountSink<T>* sink = nullptr,
@@ -932,7 +944,7 @@ constexpr int pencil_threads() {
 
 template <int N, typename T>
 __global__ void __launch_bounds__((pencil_threads<N, T>()))
-qcrit_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
+qcrit_pencil(const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x, const T* __restrict__ y,
              const T* __restrict__ z, const T* __restrict__ u, const T* __restrict__ v,
              const T* __restrict__ w, T* __restrict__ q, T* __restrict__ om,
              T* __restrict__ qmm, int32_t* __restrict__ status, int64_t n_elem) {
@@ -946,7 +958,7 @@ qcrit_pencil(const double* __restrict__ dmat, const T* __restrict__ x, const T* 
 // Q, |omega|, range and the per-(isovalue, element) counts in one pass.
 template <int N, typename T>
 __global__ void __launch_bounds__((pencil_threads<N, T>()))
-qcount_pencil(const double* __restrict__ dmat, const T* __restrict__ x,
+qcount_pencil(const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x,
               const T* __restrict__ y, const T* __restrict__ z, const T* __restrict__ u,
               const T* __restrict__ v, const T* __restrict__ w, T* __restrict__ q,
               T* __restrict__ om, T* __restrict__ qmm, int32_t* __restrict__ status,
@@ -2316,9 +2328,9 @@ constexpr int kBatchThreads = 256;
 constexpr int kBatchTile = 6144;   // LDS values for 6 fields x chunk x (N+1)^3
 
 template <int N, typename T>
-__device__ __forceinline__ int batch_chunk(const double* dmat, const T* const (&fp)[6], T* oq,
+__device__ __forceinline__ int batch_chunk(const coef_t<N, T>* dmat, const T* const (&fp)[6], T* oq,
                                            T* oom, T* oqmm, int64_t e0, int ne, T* tiles,
-                                           double* sd) {
+                                           coef_t<N, T>* sd) {
   constexpr int P = N + 1, P3 = P * P * P;
   constexpr int MAXQ = kBatchTile / 6 / kBatchThreads;   // node values per thread
   const int t = threadIdx.x;
@@ -2438,7 +2450,8 @@ qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ s
   int cur = s0 - 1;
   int64_t begin = 0, next_begin = 0, n_elem = 0;
   int chunk = 1;
-  const double *dmat = nullptr, *eo = nullptr;
+  const coef_t<N, T>* dmat = nullptr;
+  const double* eo = nullptr;
   const T *f0 = nullptr, *f1 = nullptr, *f2 = nullptr, *f3 = nullptr, *f4 = nullptr,
           *f5 = nullptr;
   T *oq = nullptr, *oom = nullptr, *oqmm = nullptr;
@@ -2456,7 +2469,7 @@ qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ s
       next_begin = uniform_i64(cur + 1 < s1 ? snaps[cur + 1].item_begin : total);
       n_elem = uniform_i64(sn.n_elem);
       chunk = __builtin_amdgcn_readfirstlane(sn.chunk);
-      dmat = uniform_ptr(static_cast<const double*>(sn.dmat));
+      dmat = uniform_ptr(static_cast<const coef_t<N, T>*>(sn.dmat));
       eo = uniform_ptr(static_cast<const double*>(sn.eo));
       f0 = uniform_ptr(static_cast<const T*>(sn.f[0]));
       f1 = uniform_ptr(static_cast<const T*>(sn.f[1]));
@@ -2475,7 +2488,7 @@ qcrit_batch(const BatchHeader* __restrict__ hdr, const BatchSnap* __restrict__ s
     asm volatile("" : "+v"(t));
     if constexpr (FORM == kBatchChunk) {
       __shared__ T tiles[kBatchTile];
-      __shared__ double sd[(kMaxOrder + 1) * (kMaxOrder + 1)];
+      __shared__ coef_t<N, T> sd[(N + 1) * (N + 1)];
       const int64_t left = n_elem - e0;
       const int ne = (int)(left < chunk ? left : chunk);
       const T* fp[6] = {f0, f1, f2, f3, f4, f5};
@@ -2679,26 +2692,25 @@ __global__ void tune_fill(int order, int64_t n_elem, T* x, T* y, T* z, T* u, T* 
     default: return hipErrorInvalidValue;          \
   }
 
-template <typename T>
-const double* dmat_of(const DeviceTables& tab, int order);
-template <>
-const double* dmat_of<double>(const DeviceTables& tab, int order) { return tab.d64[order]; }
-template <>
-const double* dmat_of<float>(const DeviceTables& tab, int order) { return tab.d64[order]; }
+// D and its even-odd halves in the line sums' type of (order, T).
+template <int N, typename T>
+const coef_t<N, T>* dmat_of(const DeviceTables& tab) {
+  if constexpr (std::is_same<coef_t<N, T>, float>::value) return tab.d32[N];
+  else return tab.d64[N];
+}
 
 template <typename T>
 hipError_t derivs_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
                     const void* y, const void* z, const void* f, void* gx, void* gy, void* gz,
                     int32_t* status, hipStream_t s) {
-  const double* d = dmat_of<T>(tab, order);
   SEM_ORDER_SWITCH(order, {
     if constexpr (N <= 7) {
-      hipLaunchKernelGGL((derivs_pencil<N, T>), dim3((unsigned)n_elem), dim3(Pen<N>::TH), 0, s, d,
+      hipLaunchKernelGGL((derivs_pencil<N, T>), dim3((unsigned)n_elem), dim3(Pen<N>::TH), 0, s, dmat_of<N, T>(tab),
                          (const T*)x, (const T*)y, (const T*)z, (const T*)f, (T*)gx, (T*)gy,
                          (T*)gz, status);
     } else {
       hipLaunchKernelGGL((derivs_tile<N, T>), dim3((unsigned)n_elem),
-                         dim3(Shape<N>::kNodeThreads), 0, s, d, (const T*)x, (const T*)y,
+                         dim3(Shape<N>::kNodeThreads), 0, s, dmat_of<N, T>(tab), (const T*)x, (const T*)y,
                          (const T*)z, (const T*)f, (T*)gx, (T*)gy, (T*)gz, status);
     }
   });
@@ -2709,7 +2721,6 @@ template <typename T>
 hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
                    const void* y, const void* z, const void* u, const void* v, const void* w,
                    void* q, void* om, void* qmm, int32_t* status, hipStream_t s) {
-  const double* d = dmat_of<T>(tab, order);
   const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
   bool done = false;
   if constexpr (std::is_same<T, double>::value) {
@@ -2729,12 +2740,12 @@ hipError_t qcrit_t(int order, const DeviceTables& tab, int64_t n_elem, const voi
       if constexpr (N <= 7 || !std::is_same<T, double>::value) {
         constexpr int E = (pencil_elems<N, T>());
         hipExtLaunchKernelGGL((qcrit_pencil<N, T>), dim3((unsigned)((n_elem + E - 1) / E)),
-                              dim3(pencil_threads<N, T>()), 0, s, pt.start, pt.stop, 0, d,
+                              dim3(pencil_threads<N, T>()), 0, s, pt.start, pt.stop, 0, dmat_of<N, T>(tab),
                               (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
                               (const T*)w, (T*)q, (T*)om, (T*)qmm, status, n_elem);
       } else {
         hipExtLaunchKernelGGL((qcrit_tile<N, T>), dim3((unsigned)n_elem),
-                              dim3(Shape<N>::kNodeThreads), 0, s, pt.start, pt.stop, 0, d,
+                              dim3(Shape<N>::kNodeThreads), 0, s, pt.start, pt.stop, 0, dmat_of<N, T>(tab),
                               (const T*)x, (const T*)y, (const T*)z, (const T*)u, (const T*)v,
                               (const T*)w, (T*)q, (T*)om, (T*)qmm, status);
       }
@@ -2889,7 +2900,6 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
   }
   out.per_iso = 1;
   const IsoList<T> iso = make_isolist<T>(n_iso, iso_host);
-  const double* d = dmat_of<T>(tab, order);
   if constexpr (std::is_same<T, double>::value) {
     if (order == 7) {
       if (active)
@@ -2923,7 +2933,7 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
         const PhaseTimer pt = phase_timer(SEM_PHASE_QCRIT);
         constexpr int E = (pencil_elems<N, T>());
         hipExtLaunchKernelGGL((qcount_pencil<N, T>), dim3((unsigned)((n_elem + E - 1) / E)),
-                              dim3(pencil_threads<N, T>()), 0, s, pt.start, pt.stop, 0, d,
+                              dim3(pencil_threads<N, T>()), 0, s, pt.start, pt.stop, 0, dmat_of<N, T>(tab),
                               (const T*)x, (const T*)y,
                               (const T*)z, (const T*)u, (const T*)v, (const T*)w, (T*)q,
                               (T*)om, (T*)qmm, status, sink);
