@@ -176,7 +176,11 @@ __device__ __forceinline__ bool invert_jacobian(T xr, T xs, T xt, T yr, T ys, T 
   const T c1 = yt * zr - yr * zt;
   const T c2 = yr * zs - ys * zr;
   const T det = xr * c0 + xs * c1 + xt * c2;
-  const T inv = T(1) / det;
+  // FP32: the hardware reciprocal (1 ulp) instead of the correctly rounded
+  // division sequence, far inside the FP32 bound of the derived fields
+  T inv;
+  if constexpr (std::is_same<T, float>::value) inv = __builtin_amdgcn_rcpf(det);
+  else inv = T(1) / det;
   k.rx = c0 * inv;
   k.ry = (xt * zs - xs * zt) * inv;
   k.rz = (xs * yt - xt * ys) * inv;
@@ -353,6 +357,11 @@ struct Pen {
   __device__ static constexpr int at(int i, int j, int k) { return i + RS * j + SS * k; }
   // element of line p (lines of consecutive elements follow each other)
   __device__ static constexpr int elem(int p) { return E == 1 ? 0 : p / NP; }
+  // half of thread t, wave-uniform and visibly 0 or 1 (so that the compiler
+  // resolves the node-range checks h * H0 + ii < P without branches)
+  __device__ static int half(int t) {
+    return __builtin_amdgcn_readfirstlane(t >= LT ? 1 : 0) != 0 ? 1 : 0;
+  }
 };
 
 // Coefficient tables (D, its even-odd halves) are read through the
@@ -389,22 +398,29 @@ __device__ __forceinline__ void line_deriv_all(const C* __restrict__ d, const T 
   const C* b = a + NE * NE;
   const C g0 = g[0];
   C hv[P], e[NE], o[H > 0 ? H : 1];
-  hv[0] = C(0);
 #pragma unroll
   for (int m = 1; m < P; ++m) hv[m] = (C)g[m] - g0;
+  // hv[0] = 0: e[0] = hv[P-1], o[0] = -hv[P-1] (written out, since 0 + x
+  // does not fold for a possibly negative zero x)
+  if constexpr (H > 0) {
+    e[0] = hv[P - 1];
+    o[0] = -hv[P - 1];
+  }
 #pragma unroll
-  for (int m = 0; m < H; ++m) {
+  for (int m = 1; m < H; ++m) {
     e[m] = hv[m] + hv[P - 1 - m];
     o[m] = hv[m] - hv[P - 1 - m];
   }
-  if constexpr (P % 2 == 1) e[H] = hv[H];
+  if constexpr (P % 2 == 1) e[H] = hv[H];   // P odd: H >= 1
 #pragma unroll
   for (int i = 0; i < NE; ++i) {
-    C pe = coef(a, NE * i) * e[0], ro = C(0);
+    C pe = coef(a, NE * i) * e[0];
 #pragma unroll
     for (int m = 1; m < NE; ++m) pe = fma(coef(a, NE * i + m), e[m], pe);
+    C ro = C(0);
+    if constexpr (H > 0) ro = coef(b, H * i) * o[0];
 #pragma unroll
-    for (int m = 0; m < H; ++m) ro = fma(coef(b, H * i + m), o[m], ro);
+    for (int m = 1; m < H; ++m) ro = fma(coef(b, H * i + m), o[m], ro);
     out[i] = (T)(ro + pe);
     if (P - 1 - i != i) out[P - 1 - i] = (T)(ro - pe);
   }
@@ -447,7 +463,9 @@ __device__ __forceinline__ void pencil_pass(const T (&f)[N + 1],
       const int i = h * H0 + ii;
       if (i < P) {
         fr[ii] = line_deriv<P>(d, i, f);
-        F[Q::at(i, j, k)] = f[i];
+        // f[i] by one select on the wave-uniform half (an index into the
+        // line would become a compare-and-select over all P values)
+        F[Q::at(i, j, k)] = h == 0 ? f[ii] : f[H0 + ii < P ? H0 + ii : P - 1];
       }
     }
   }
@@ -523,7 +541,7 @@ derivs_pencil(const coef_t<N, T>* __restrict__ dmat, const T* __restrict__ x, co
   using Q = Pen<N>;
   constexpr int P = Q::P, H0 = Q::H0;
   __shared__ PencilTiles<N, T> sm;
-  const int h = __builtin_amdgcn_readfirstlane(threadIdx.x / Q::LT);
+  const int h = Q::half(threadIdx.x);
   const int p = threadIdx.x % Q::LT;
   const int64_t base = (int64_t)blockIdx.x * (P * P * P);
   T lx[P], ly[P], lz[P], lf[P];
@@ -751,7 +769,7 @@ __device__ __forceinline__ void pencil_multi_tail(int64_t e, int t, int ne,
   if constexpr (COUNT) {
     constexpr int NC = N * N * N;
     uint32_t* bits = reinterpret_cast<uint32_t*>(F);
-    const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
+    const int h = Q::half(t);
     const int p = t % Q::LT;
     const bool valid = p < ne * Q::NP;
     const int n_iso = sink->n_iso;
@@ -821,7 +839,7 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   __shared__ uint32_t s_rows[COUNT && E == 1 ? 2 * Q::TH / 64 * 4 : 1];
   __shared__ T s_part[E > 1 ? 2 * Q::TH : 1];   // per-thread (min, max) of Q
   __shared__ T s_emm[E > 1 && COUNT ? 2 * E : 1];
-  const int h = __builtin_amdgcn_readfirstlane(t / Q::LT);
+  const int h = Q::half(t);
   const int p = t % Q::LT;
   const int64_t base = e * (P * P * P);
   const int nl = E == 1 ? Q::NP : ne * Q::NP;   // lines of elements that exist
