@@ -132,6 +132,13 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* scra
   return before + inc - v;
 }
 
+// A value the compiler can no longer trace to its source (no instruction).
+template <typename V>
+__device__ __forceinline__ V opaque(V x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
 // Coefficient type of the line sums: FP64 with the FP64 D for FP64 fields;
 // for FP32 fields FP32 with the FP32-rounded D up to order kF32SumOrder
 // (within the FP32 bound there; FP32 FMAs need no conversions and half the
@@ -464,8 +471,13 @@ __device__ __forceinline__ void pencil_pass(const T (&f)[N + 1],
       if (i < P) {
         fr[ii] = line_deriv<P>(d, i, f);
         // f[i] by one select on the wave-uniform half (an index into the
-        // line would become a compare-and-select over all P values)
-        F[Q::at(i, j, k)] = h == 0 ? f[ii] : f[H0 + ii < P ? H0 + ii : P - 1];
+        // line would become a compare-and-select over all P values); at odd
+        // P the two values are made opaque first, or the select of two
+        // loads is folded into one load at a selected index, which keeps
+        // the line in memory
+        const T f0 = f[ii], f1 = f[H0 + ii < P ? H0 + ii : P - 1];
+        if constexpr (P % 2 == 1) F[Q::at(i, j, k)] = h == 0 ? opaque(f0) : opaque(f1);
+        else F[Q::at(i, j, k)] = h == 0 ? f0 : f1;
       }
     }
   }
@@ -843,16 +855,28 @@ __device__ __forceinline__ void qcrit_pencil_elem(
   const int p = t % Q::LT;
   const int64_t base = e * (P * P * P);
   const int nl = E == 1 ? Q::NP : ne * Q::NP;   // lines of elements that exist
+  // triangle counts of the 256 cases: requested here, written to LDS after
+  // the passes (published by the barrier after the Q tile), so that the
+  // loads overlap the field loads instead of delaying them
+  constexpr int TR = COUNT ? (256 + Q::TH - 1) / Q::TH : 1;
+  uint8_t tab_v[TR];
   if constexpr (COUNT) {
-    // case table, published by the barriers of the passes
-    // (the several-element tail packs active cells at bit 16, the
-    // one-element form at bit 8)
-    for (int c = t; c < 256; c += Q::TH)
-      s_tab[c] = E == 1 ? case_count_entry8(c, sink->ntri[c]) : case_count_entry(c, sink->ntri[c]);
+#pragma unroll
+    for (int r = 0; r < TR; ++r)
+      if (t + r * Q::TH < 256) tab_v[r] = sink->ntri[t + r * Q::TH];
   }
   T qv[H0], ov[H0];
   int bad = !pencil_qcrit<N, E>(x + base, y + base, z + base, u + base, v + base, w + base,
                                 dmat, sm, sm.F, sm.F, sm.F, h, p, nl, qv, ov);
+  if constexpr (COUNT) {
+    // the several-element tail packs active cells at bit 16, the
+    // one-element form at bit 8
+#pragma unroll
+    for (int r = 0; r < TR; ++r) {
+      const int c = t + r * Q::TH;
+      if (c < 256) s_tab[c] = E == 1 ? case_count_entry8(c, tab_v[r]) : case_count_entry(c, tab_v[r]);
+    }
+  }
   const bool valid = p < nl;
   T mn = pos_inf<T>(), mx = neg_inf<T>();
   if (!valid) bad = 0;
@@ -2084,23 +2108,25 @@ __device__ __forceinline__ MixOps<M> mix_ops(const double* __restrict__ d, int l
     o.ac[q] = E(0.f);
   }
   const int i = lane & 15, g = lane >> 4;
-  if (i < 8) {
-    const double d0 = d[i * 8 + 2 * g], d1 = d[i * 8 + 2 * g + 1];
-    const E h0 = E((float)d0), h1 = E((float)d1);
-    if constexpr (M == kMixBF16x3) {
-      const E l0 = E((float)(d0 - (double)(float)h0));
-      const E l1 = E((float)(d1 - (double)(float)h1));
-      o.a[0] = h0; o.a[1] = l0; o.a[2] = h0;
-      o.a[3] = h1; o.a[4] = l1; o.a[5] = h1;
-    } else {
-      o.a[0] = h0;
-      o.a[1] = h1;
-      if constexpr (M == kMixFP16x3) {
-        o.ac[0] = E((float)((d0 - (double)(float)h0) * kF16LoScale));
-        o.ac[1] = h0;
-        o.ac[2] = E((float)((d1 - (double)(float)h1) * kF16LoScale));
-        o.ac[3] = h1;
-      }
+  // rows 8..15 are zero: their values are selected to zero after an
+  // unconditional load (row i & 7), so that no branch holds the caller's
+  // later loads behind this load's wait
+  const double r0 = d[(i & 7) * 8 + 2 * g], r1 = d[(i & 7) * 8 + 2 * g + 1];
+  const double d0 = i < 8 ? r0 : 0.0, d1 = i < 8 ? r1 : 0.0;
+  const E h0 = E((float)d0), h1 = E((float)d1);
+  if constexpr (M == kMixBF16x3) {
+    const E l0 = E((float)(d0 - (double)(float)h0));
+    const E l1 = E((float)(d1 - (double)(float)h1));
+    o.a[0] = h0; o.a[1] = l0; o.a[2] = h0;
+    o.a[3] = h1; o.a[4] = l1; o.a[5] = h1;
+  } else {
+    o.a[0] = h0;
+    o.a[1] = h1;
+    if constexpr (M == kMixFP16x3) {
+      o.ac[0] = E((float)((d0 - (double)(float)h0) * kF16LoScale));
+      o.ac[1] = h0;
+      o.ac[2] = E((float)((d1 - (double)(float)h1) * kF16LoScale));
+      o.ac[3] = h1;
     }
   }
   return o;
@@ -2197,17 +2223,27 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
   __shared__ int32_t s_tab[COUNT ? 256 : 1];
   __shared__ uint32_t s_rows[COUNT ? 32 : 1];
   const int t = threadIdx.x, lane = t & 63;
-  if constexpr (COUNT) s_tab[t] = case_count_entry8(t, sink.ntri[t]);
+  __builtin_assume(t >= 0 && t < 256);
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int64_t base = (int64_t)blockIdx.x * 512;
-  const float* src[6] = {x, y, z, u, v, w};
-#pragma unroll
-  for (int c = t; c < NF * 128; c += 256) {
-    const int fi = c >> 7, ch = c & 127;
-    const float4 val = *reinterpret_cast<const float4*>(src[fi] + base + 4 * ch);
-    *reinterpret_cast<float4*>(&s_in[fi][4 * ch]) = val;
-  }
-  const MixOps<M> ops = mix_ops<M>(dmat, lane);
+  // the first 128 threads stage the 16-byte chunks of x, z, v, the others
+  // those of y, u, w; every load is requested before the first LDS write (a
+  // field picked by an index into a pointer list became a compare-and-select
+  // chain that serialised the loads)
+  const MixOps<M> ops = mix_ops<M>(dmat, lane);   // its loads first: in flight with the tiles'
+  const bool hi = t >= 128;
+  const int64_t off = base + 4 * (t & 127);
+  const int slot = 4 * (t & 127);
+  const float4 c0 = *reinterpret_cast<const float4*>((hi ? y : x) + off);
+  const float4 c1 = *reinterpret_cast<const float4*>((hi ? u : z) + off);
+  float4 c2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  if constexpr (NF == 6) c2 = *reinterpret_cast<const float4*>((hi ? w : v) + off);
+  uint8_t nt_own = 0;
+  if constexpr (COUNT) nt_own = sink.ntri[t];
+  *reinterpret_cast<float4*>((hi ? s_in[1] : s_in[0]) + slot) = c0;
+  *reinterpret_cast<float4*>((hi ? s_in[3] : s_in[2]) + slot) = c1;
+  if constexpr (NF == 6) *reinterpret_cast<float4*>((hi ? s_in[5] : s_in[4]) + slot) = c2;
+  if constexpr (COUNT) s_tab[t] = case_count_entry8(t, nt_own);
   __syncthreads();
 
   // owners: nodes t and t + 256
