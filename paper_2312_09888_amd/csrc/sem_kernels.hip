@@ -200,6 +200,45 @@ __device__ __forceinline__ bool invert_jacobian(T xr, T xs, T xt, T yr, T ys, T 
   return det > T(0);
 }
 
+// 1 / x from the hardware estimate and two Newton steps (within an ulp or
+// two; the correctly rounded division adds range scaling and a final
+// correction); x outside [2^-1000, 2^1000] in magnitude, 0 and NaN take the
+// division (a branch that a wave skips unless one of its lanes needs it).
+__device__ __forceinline__ double recip_refined(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  const double a = fabs(x);
+  const bool out = !(a >= 0x1p-1000 && a <= 0x1p+1000);
+  if (__builtin_amdgcn_ballot_w64(out) != 0) {   // wave-uniform: skipped as a whole
+    double xx = x;
+    asm volatile("" : "+v"(xx));   // keeps the division from being hoisted out
+    if (out) r = 1.0 / xx;
+  }
+  return r;
+}
+
+// sqrt(x) from the hardware estimate of 1 / sqrt(x), one Goldschmidt step and
+// a Newton correction of the root (within an ulp or two); x outside
+// [2^-1000, 2^1000], 0 and NaN take the library root.
+__device__ __forceinline__ double sqrt_refined(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  double sq = x * r, hr = 0.5 * r;
+  const double e = fma(-hr, sq, 0.5);
+  sq = fma(sq, e, sq);
+  hr = fma(hr, e, hr);
+  sq = fma(fma(-sq, sq, x), hr, sq);
+  const bool out = !(x >= 0x1p-1000 && x <= 0x1p+1000);
+  if (__builtin_amdgcn_ballot_w64(out) != 0) {   // wave-uniform: skipped as a whole
+    double xx = x;
+    asm volatile("" : "+v"(xx));   // keeps the root from being hoisted out
+    if (out) sq = sqrt(xx);
+  }
+  return sq;
+}
+
 // The adjugate of J (det J times J^-1, same layout as InvJac) and 1 / det J.
 __device__ __forceinline__ bool adjugate_jacobian(double xr, double xs, double xt, double yr,
                                                   double ys, double yt, double zr, double zs,
@@ -208,7 +247,7 @@ __device__ __forceinline__ bool adjugate_jacobian(double xr, double xs, double x
   k.sx = yt * zr - yr * zt;
   k.tx = yr * zs - ys * zr;
   const double det = xr * k.rx + xs * k.sx + xt * k.tx;
-  inv = 1.0 / det;
+  inv = recip_refined(det);
   k.ry = xt * zs - xs * zt;
   k.rz = xs * yt - xt * ys;
   k.sy = xr * zt - xt * zr;
@@ -1681,7 +1720,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
     qv[ii] = -0.5 * (qv[ii] + a22 * a22 + 2.0 * (a02[ii] * a20 + a12[ii] * a21)) *
              (inv[ii] * inv[ii]);
     const double w1 = a21 - a12[ii], w2 = a02[ii] - a20;
-    ov[ii] = sqrt(ov[ii] + w1 * w1 + w2 * w2) * fabs(inv[ii]);
+    ov[ii] = sqrt_refined(ov[ii] + w1 * w1 + w2 * w2) * fabs(inv[ii]);
   }
   const int j = p & 7, k = p >> 3;
   // Q and |omega| go out through LDS tiles (free after the u and v passes):
