@@ -102,16 +102,32 @@ ae_scales(int64_t e_begin, const float* __restrict__ u, const float* __restrict_
 // bit patterns): one atomic per block and channel
 __global__ void __launch_bounds__(kT)
 gmax_k(const float* __restrict__ scale, int64_t n, uint32_t* __restrict__ gmax_bits) {
-  __shared__ float red[kT / 64];
+  // the four channels of an entry by one 16-byte load, reduced together
+  __shared__ float red[kT / 64][4];
+  float m[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT) {
+    const float4 x = reinterpret_cast<const float4*>(scale)[e];
+    m[0] = x.x > m[0] ? x.x : m[0];
+    m[1] = x.y > m[1] ? x.y : m[1];
+    m[2] = x.z > m[2] ? x.z : m[2];
+    m[3] = x.w > m[3] ? x.w : m[3];
+  }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    float m = 0.f;
-    for (int64_t e = (int64_t)blockIdx.x * kT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kT) {
-      const float x = scale[e * 4 + c];
-      m = x > m ? x : m;
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float o = __shfl_xor(m[c], off);
+      m[c] = o > m[c] ? o : m[c];
     }
-    m = block_max_pos(m, red);
-    if (threadIdx.x == 0) atomicMax(gmax_bits + c, __float_as_uint(m));
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int c = 0; c < 4; ++c) red[w][c] = m[c];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    float r = red[0][threadIdx.x];
+#pragma unroll
+    for (int i = 1; i < kT / 64; ++i) r = red[i][threadIdx.x] > r ? red[i][threadIdx.x] : r;
+    atomicMax(gmax_bits + threadIdx.x, __float_as_uint(r));
   }
 }
 
@@ -690,29 +706,48 @@ ae_check(int64_t e_begin, const float* __restrict__ u, const float* __restrict__
   if (threadIdx.x == 0) flag[e] = bad;
 }
 
-// raw[offs[e]] = the element's four channels (GLL layout) for flagged e
+// raw[offs[e]] = the element's four channels (GLL layout) for flagged e.
+// A workgroup takes kPackE consecutive elements: their flags go out as bytes
+// (one coalesced store), then wave w copies the flagged elements w, w + 4,
+// ... of the group (8 KiB each, 16-byte loads and stores).
+constexpr int kPackE = 64;
 __global__ void __launch_bounds__(kT)
-pack_raw(const float* __restrict__ u, const float* __restrict__ v, const float* __restrict__ w,
-         const float* __restrict__ th, const int32_t* __restrict__ flag,
-         const int64_t* __restrict__ offs, int64_t cap, float* __restrict__ raw,
-         uint8_t* __restrict__ flag_out, int32_t* __restrict__ status) {
-  const int64_t e = blockIdx.x;
-  const int fl = flag[e];
-  if (threadIdx.x == 0 && flag_out) flag_out[e] = (uint8_t)fl;
-  if (!fl) return;
-  const int64_t o = offs[e];
-  if (o >= cap) {
-    if (threadIdx.x == 0 && status) atomicOr(status, SEM_FLAG_RAW_OVERFLOW);
-    return;
+pack_raw(int64_t n_elem, const float* __restrict__ u, const float* __restrict__ v,
+         const float* __restrict__ w, const float* __restrict__ th,
+         const int32_t* __restrict__ flag, const int64_t* __restrict__ offs, int64_t cap,
+         float* __restrict__ raw, uint8_t* __restrict__ flag_out,
+         int32_t* __restrict__ status) {
+  __shared__ int32_t s_fl[kPackE];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t e0 = (int64_t)blockIdx.x * kPackE;
+  const int ne = n_elem - e0 < kPackE ? (int)(n_elem - e0) : kPackE;
+  if (t < ne) {
+    const int fl = flag[e0 + t];
+    s_fl[t] = fl;
+    if (flag_out) flag_out[e0 + t] = (uint8_t)fl;
   }
+  __syncthreads();
   const float* f[4] = {u, v, w, th};
-#pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int n = threadIdx.x + 256 * h;
-      raw[(o * 4 + c) * 512 + n] = f[c][e * 512 + n];
+  for (int q = wv; q < ne; q += kT / 64) {
+    if (!s_fl[q]) continue;
+    const int64_t e = e0 + q;
+    const int64_t o = offs[e];
+    if (o >= cap) {
+      if (lane == 0 && status) atomicOr(status, SEM_FLAG_RAW_OVERFLOW);
+      continue;
     }
+    float4 val[4][2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        val[c][h] = reinterpret_cast<const float4*>(f[c] + e * 512)[lane + 64 * h];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        reinterpret_cast<float4*>(raw + (o * 4 + c) * 512)[lane + 64 * h] = val[c][h];
+  }
 }
 
 __global__ void flags_u8_to_i32(const uint8_t* __restrict__ f8, int64_t n,
@@ -851,8 +886,8 @@ modal_k(const float* __restrict__ u, const float* __restrict__ v, const float* _
 
 constexpr int kFoldFloats = 256 * 64 + 64 + 64 * 256 + 256;
 constexpr int kEncE = 4;        // elements per workgroup
-constexpr int kRowPad = 48;     // k-major LDS rows for the 32 GEMM rows: the four
-                                // k rows of an MFMA step fall on disjoint bank halves
+constexpr int kRowPad = 49;     // k-major LDS rows for the 32 GEMM rows: an odd pitch
+                                // spreads the transposing stores over the banks
 
 __global__ void __launch_bounds__(kT)
 ae_fold(const float* __restrict__ prm, int64_t ow0, int64_t ob0, int64_t ow1, int64_t ob1,
@@ -1650,7 +1685,8 @@ hipError_t launch_ae_compress(int64_t n_elem, const float* const* f, const float
   if (e != hipSuccess) return e;
   if (n_raw) hipMemcpyAsync(n_raw, c.offs + n_elem, 8, hipMemcpyDeviceToDevice, s);
   if (n_elem > 0)
-    hipLaunchKernelGGL(pack_raw, dim3((unsigned)n_elem), dim3(kT), 0, s, f[0], f[1], f[2], f[3],
+    hipLaunchKernelGGL(pack_raw, dim3((unsigned)cdiv(n_elem, kPackE)), dim3(kT), 0, s, n_elem,
+                       f[0], f[1], f[2], f[3],
                        c.flag, c.offs, raw_cap, raw, flags, status);
   return hipGetLastError();
 }
