@@ -633,10 +633,13 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
                                              int h, int p, int nl, T (&qv)[Pen<N>::H0],
                                              T (&om)[Pen<N>::H0]) {
   constexpr int H0 = Pen<N>::H0, P = Pen<N>::P;
-  // N <= 7: all six lines are requested before any arithmetic; N = 8, 9:
-  // the velocity lines are requested just before their pass (ten values a
-  // line would otherwise hold 30 more registers through the geometry)
-  constexpr bool kEarly = N <= 7;
+  // N <= 7 and FP32: all six lines are requested before any arithmetic;
+  // FP64 at N = 8, 9: the velocity lines are requested just before their
+  // pass (their values would otherwise hold 60 more registers through the
+  // geometry). FP32 at N = 9 stays at 187 registers either way, and the
+  // early requests took its Q phase on the batch benchmark's order-9
+  // snapshots from 3.96 to 3.64 ms.
+  constexpr bool kEarly = N <= 7 || std::is_same<T, float>::value;
   T lx[P], ly[P], lz[P], lu[P], lv[P], lw[P];
   pencil_load<N>(gx, p, nl, lx);
   pencil_load<N>(gy, p, nl, ly);
