@@ -146,6 +146,19 @@ def test_qcrit_optional_outputs_and_bad_jacobian():
     assert relerr(host(q)[good], oq[good]) < 1e-10
 
 
+@pytest.mark.parametrize("scale", [2.0 ** -500, 2.0 ** 505])
+def test_qcrit_fp64_far_scales(scale):
+    """Order 7, FP64: the Taylor-Green velocity scaled so that the root's
+    argument in the kernel (|omega|^2 times det J^2) leaves [2^-1000, 2^1000]
+    at some or all nodes, where the kernel takes the library root instead of
+    its refined hardware estimate; Q and |omega| still within 1e-10
+    normwise (relative errors do not depend on the scale)."""
+    n = 7
+    x, y, z, u, v, w = W.tgv_config(n)
+    u, v, w = (scale * a for a in (u, v, w))
+    _check_qcrit(x, y, z, u, v, w, n, np.float64)
+
+
 def test_qcrit_linear_field_exact():
     n = 5
     x, y, z = warped_mesh(n, (2, 2, 2))
