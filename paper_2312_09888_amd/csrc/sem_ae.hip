@@ -948,6 +948,14 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
   __shared__ float smax[kEncE][4];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t e0 = (int64_t)blockIdx.x * kEncE;
+  // this lane's 64 weights of the folded layers 0-1 (rows k = 4 i + lk,
+  // column 16 wv + lr), requested with the field loads: the matrix-core
+  // loop below then waits on LDS only
+  const int lr = lane & 15, lk = lane >> 4;
+  const int c0 = 16 * wv;
+  float wb[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) wb[i] = fold[(4 * i + lk) * 64 + c0 + lr];
   {
     // wave wv: element e0 + wv, every value of its four channels by 16-byte
     // loads, all issued before the first use (elements past the end read
@@ -1001,17 +1009,15 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
     gpart[blockIdx.x * 4 + t] = g;
   }
   // layers 0-1 folded: [32 rows x 256] x W01 [256 x 64]; wave w: both row
-  // tiles, columns 16 w .. 16 w + 15 (one weight load feeds two MFMAs)
-  const int lr = lane & 15, lk = lane >> 4;
-  const int c0 = 16 * wv;
+  // tiles, columns 16 w .. 16 w + 15 (one weight feeds two MFMAs)
   f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-  for (int k = 0; k < 256; k += 4) {
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const int k = 4 * i;
     const float a0 = xs[(k + lk) * kRowPad + lr];
     const float a1 = xs[(k + lk) * kRowPad + 16 + lr];
-    const float bb = fold[(k + lk) * 64 + c0 + lr];
-    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bb, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bb, acc1, 0, 0, 0);
+    acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, wb[i], acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, wb[i], acc1, 0, 0, 0);
   }
   __syncthreads();                          // every read of xs is done
   float* h1 = xs;                           // h1[el][p1 64 + o]
@@ -1072,6 +1078,18 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
   __shared__ uint32_t emax[kEncE][4];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t e0 = (int64_t)blockIdx.x * kEncE;
+  // this lane's 64 weights of the folded layers 4-5 (rows k = 4 i + lk,
+  // columns 64 wv + 16 j + lr), requested first: the matrix-core loop below
+  // then waits on LDS only
+  const int lr = lane & 15, lk = lane >> 4;
+  const int c0 = 64 * wv;
+  const float* w45 = fold + 256 * 64 + 64;
+  const float* b45 = w45 + 64 * 256;
+  float wd[16][4];
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wd[i][j] = w45[(4 * i + lk) * 256 + c0 + 16 * j + lr];
   if (t < kEncE * 32) {
     const int64_t e = e0 + t / 32;
     zs[t / 32][t % 32] = e < n_elem ? __half2float(__ushort_as_half(latent[e * 32 + t % 32])) : 0.f;
@@ -1118,25 +1136,21 @@ ae_decode(int64_t n_elem, const uint16_t* __restrict__ latent, const float* __re
   }
   __syncthreads();
   // layers 4-5 folded: [32 rows x 64] x W45 [64 x 256]; wave w: both row
-  // tiles, columns 64 w .. 64 w + 63 (one weight load feeds two MFMAs)
-  const int lr = lane & 15, lk = lane >> 4;
-  const int c0 = 64 * wv;
-  const float* w45 = fold + 256 * 64 + 64;
-  const float* b45 = w45 + 64 * 256;
+  // tiles, columns 64 w .. 64 w + 63 (one weight feeds two MFMAs)
   f32x4 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-  for (int k = 0; k < 64; k += 4) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int k = 4 * i;
     const float a0 = h3[(k + lk) * kRowPad + lr];
     const float a1 = h3[(k + lk) * kRowPad + 16 + lr];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float bb = w45[(k + lk) * 256 + c0 + 16 * j + lr];
-      acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bb, acc[0][j], 0, 0, 0);
-      acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bb, acc[1][j], 0, 0, 0);
+      acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, wd[i][j], acc[0][j], 0, 0, 0);
+      acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, wd[i][j], acc[1][j], 0, 0, 0);
     }
   }
   // A lane's values: rows 16 rt + 4 lk + r (element 2 rt + lk / 2, octant
