@@ -392,6 +392,7 @@ def main():
         "eager_ms_per_step": round(ms_step, 5),
         "ms_per_step_with_phase_timing": round(ms_phased, 5),
         "two_call_ms": {"sem_qcrit": round(qc_ms, 5), "sem_isosurface": round(iso_ms, 5)},
+        "build": build_record(sem),
     }
 
     if args.batched == "on" and args.dtype == "f64":
@@ -413,6 +414,16 @@ def _pcts(ms):
     return {"median_ms": round(float(np.median(a)), 5),
             "p10_ms": round(float(np.percentile(a, 10)), 5),
             "p90_ms": round(float(np.percentile(a, 90)), 5)}
+
+
+def build_record(sem):
+    """The loaded library's build record (sem_build_info) and whether its
+    sources digest is that of the sources in this tree."""
+    from paper_2312_09888_amd import build as B
+    rec = sem.build_info()
+    rec["library"] = os.path.relpath(sem.lib()._name, ROOT)
+    rec["matches_tree_sources"] = rec.get("sources_sha256") == B.source_sha256()
+    return rec
 
 
 def copy_bandwidth(args, sem, dev, nbytes=CALIBRATION_BYTES, reps=20):
@@ -819,11 +830,24 @@ def c0_timing(args, sem, fields, q, isos, n):
     import workloads as W
     dev = q.device
     gid = torch.from_numpy(W.lattice_gid(W.CHANNEL_SHAPE, n)).to(dev)
+    n_glob = 1
+    for s_ax in W.CHANNEL_SHAPE:
+        n_glob *= s_ax * n + 1                  # lattice points of the box mesh
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    # the first build also allocates the workspace (and finds the node count
+    # from the ids, a device reduction and a host sync); a mesh's setup is
+    # timed on the second build, with the node count given
+    torch.cuda.synchronize()
+    t0 = time.time()
+    gs = sem.GatherScatter(gid)
+    torch.cuda.synchronize()
+    first_ms = (time.time() - t0) * 1e3
+    assert gs.n_global == n_glob
+    del gs
     torch.cuda.synchronize()
     e0.record()
-    gs = sem.GatherScatter(gid)
+    gs = sem.GatherScatter(gid, n_global=n_glob)
     e1.record()
     torch.cuda.synchronize()
     setup_ms = e0.elapsed_time(e1)
@@ -850,7 +874,8 @@ def c0_timing(args, sem, fields, q, isos, n):
     torch.cuda.synchronize()
     weld_ms = e0.elapsed_time(e1) / reps
     n_tri = int(r["tri_xyz"].shape[0])
-    log(args, f"C0: gather-scatter setup {setup_ms:.3f} ms, dsavg {avg_ms:.4f} ms, "
+    log(args, f"C0: gather-scatter setup {setup_ms:.3f} ms (first build, with its "
+              f"allocation, {first_ms:.1f} ms), dsavg {avg_ms:.4f} ms, "
               f"global keys + weld {weld_ms:.4f} ms: {n_tri} triangles -> "
               f"{int(verts.shape[0])} vertices")
     n_global = gs.n_global
@@ -858,7 +883,8 @@ def c0_timing(args, sem, fields, q, isos, n):
     del gid, gs, qa
     # dsavg: row pointers, column list, field in and out (FP64)
     dbytes = 8 * (n_global + 1) + 24 * n_nodes
-    return {"gs_setup_ms": round(setup_ms, 4), "dsavg_ms": round(avg_ms, 5),
+    return {"gs_setup_ms": round(setup_ms, 4), "gs_setup_first_ms": round(first_ms, 3),
+            "dsavg_ms": round(avg_ms, 5),
             "keys_weld_ms": round(weld_ms, 5), "triangles": n_tri,
             "welded_vertices": int(verts.shape[0]), "n_global": n_global,
             "dsavg_hbm": _hbm(dbytes, avg_ms)}

@@ -91,6 +91,14 @@ enum {
 /* Human-readable text for a SEM_* return code (static storage). */
 const char* sem_status_str(int status);
 
+/* Build record of this library, for matching a loaded binary to its
+ * sources (static storage, never NULL):
+ *   "sources_sha256=<64 hex digits>;arch=gfx950;hip=<hipcc's HIP version>"
+ * where the digest covers the library's source files as compiled: every
+ * file of the kernel source directory (.hip, .cpp, .h) in name order, each
+ * as its file name then its bytes, then this header the same way. */
+const char* sem_build_info(void);
+
 /* ---------------------------------------------------------------------
  * Host-side basis and table queries (no GPU needed).
  * ------------------------------------------------------------------- */

@@ -17,5 +17,5 @@ from ._lib import (  # noqa: F401
     ae_param_count, ae_blocks, ae_forward, ae_grad, ae_adam, sym_eig, ae_pca_init, ae_train,
     ae_compress, ae_decompress, modal_compress, compressed_bytes, stream_copy,
     extract_noalloc_into, SEM_NOALLOC_MAX_COUNTS, IsoBatchPlan, isosurface_batch,
-    isosurface_batch_into, SEM_JOB_Q, SEM_JOB_OMEGA, SEM_JOB_SCALAR,
+    isosurface_batch_into, SEM_JOB_Q, SEM_JOB_OMEGA, SEM_JOB_SCALAR, build_info,
 )

@@ -37,7 +37,7 @@ SEM_PHASE_QCRIT, SEM_PHASE_COUNT, SEM_PHASE_SCAN, SEM_PHASE_EMIT = 0, 1, 2, 3
 SEM_NUM_PHASES = 4
 
 EXPORTS = (
-    "sem_status_str", "sem_gll", "sem_mc_table", "sem_init", "sem_finalize",
+    "sem_status_str", "sem_build_info", "sem_gll", "sem_mc_table", "sem_init", "sem_finalize",
     "sem_derivs", "sem_qcrit", "sem_isosurface_workspace_bytes", "sem_isosurface",
     "sem_extract_workspace_bytes", "sem_extract", "sem_extract_noalloc",
     "sem_phase_name", "sem_timing_begin", "sem_timing_end", "sem_stream_copy",
@@ -98,6 +98,8 @@ def lib():
         vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
         L.sem_status_str.restype = ctypes.c_char_p
         L.sem_status_str.argtypes = [i32]
+        L.sem_build_info.restype = ctypes.c_char_p
+        L.sem_build_info.argtypes = []
         L.sem_gll.restype = i32
         L.sem_gll.argtypes = [i32, vp, vp, vp]
         L.sem_mc_table.restype = i32
@@ -199,6 +201,13 @@ def lib():
 
 def status_str(code):
     return lib().sem_status_str(int(code)).decode()
+
+
+def build_info():
+    """The loaded library's build record (sem_build_info) as a dict:
+    sources_sha256, arch, hip."""
+    text = lib().sem_build_info().decode()
+    return dict(item.split("=", 1) for item in text.split(";"))
 
 
 def _check(code, where):

@@ -6,6 +6,7 @@ runs it from the command line.
 """
 
 import concurrent.futures
+import hashlib
 import os
 import shutil
 import subprocess
@@ -33,9 +34,32 @@ COMMON = [
 ]
 
 
-def _compile(src):
+def source_sha256():
+    """SHA-256 of the library's sources as they are now: every file of csrc/
+    (.hip, .cpp, .h) in name order, each as its name then its bytes, then
+    include/sem.h the same way.  The build stores it in the library
+    (sem_build_info), so a loaded library can be matched to the tree."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    paths = [os.path.join(CSRC, f) for f in files] + [os.path.join(ROOT, "include", "sem.h")]
+    for path in paths:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _hip_version():
+    res = subprocess.run([HIPCC, "--version"], capture_output=True, text=True)
+    for line in res.stdout.splitlines():
+        if line.startswith("HIP version:"):
+            return line.split(":", 1)[1].strip()
+    return "unknown"
+
+
+def _compile(src, defines=()):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + COMMON + list(defines) + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd.insert(1, "-xhip")
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -49,8 +73,12 @@ def build(verbose=False):
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(OBJ, exist_ok=True)
+    # the build record compiled into sem_api.cpp (sem_build_info)
+    record = [f'-DSEM_SOURCES_SHA256="{source_sha256()}"',
+              f'-DSEM_HIP_VERSION="{_hip_version()}"']
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda src: _compile(src, record if src == "sem_api.cpp" else ()),
+                              SOURCES))
     if verbose:
         for (obj, err) in results:
             if err.strip():

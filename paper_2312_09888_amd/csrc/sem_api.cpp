@@ -129,6 +129,11 @@ using namespace sem;
 
 extern "C" {
 
+const char* sem_build_info(void) {
+  // both strings are compiler definitions from the build script
+  return "sources_sha256=" SEM_SOURCES_SHA256 ";arch=gfx950;hip=" SEM_HIP_VERSION;
+}
+
 const char* sem_status_str(int status) {
   switch (status) {
     case SEM_OK: return "ok";

@@ -62,6 +62,14 @@ def test_status_strings():
     assert sem.status_str(123) == "unknown status"
 
 
+def test_build_record_matches_the_sources():
+    from paper_2312_09888_amd import build as B
+    rec = sem.build_info()
+    assert rec["arch"] == "gfx950" and rec["hip"]
+    # the library in the tree was built from the sources in the tree
+    assert rec["sources_sha256"] == B.source_sha256()
+
+
 def test_gll_rejects_bad_order():
     L = sem.lib()
     assert L.sem_gll(0, None, None, None) == _lib.SEM_ERR_ORDER

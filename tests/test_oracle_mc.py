@@ -284,6 +284,39 @@ def test_sphere_is_closed_genus_zero_outward(n):
     assert abs(vol / exact - 1.0) < {2: 0.3, 4: 0.1, 7: 0.04}[n]
 
 
+def _plane_pin(n=3):
+    """Vertices of a linear field's isosurfaces on an affine box mesh (straight
+    edges): linear interpolation along an edge is exact for a linear field,
+    so every vertex lies on the plane a.p + b = c and between its edge's
+    endpoints (the vertex rule; the plane is the closed form)."""
+    x, y, z = W.box_mesh((3, 2, 2), n, ((0.0, 1.9), (-0.7, 0.6), (0.3, 1.5)))
+    a = np.array([0.7, -1.3, 0.4])
+    b = 0.2
+    f = a[0] * x + a[1] * y + a[2] * z + b
+    isos = [float(np.quantile(f, q)) for q in (0.21, 0.5, 0.83)]
+    r = mc.extract(x, y, z, f, isos, edge_keys=True)
+    p = r["tri_xyz"].reshape(-1, 3)
+    cvals = np.repeat(np.repeat(isos, r["tri_count"]), 3)
+    assert p.shape[0] > 100
+    resid = np.abs(p @ a + b - cvals)
+    scale = np.abs(a).sum() * np.abs(p).max() + abs(b)
+    assert resid.max() <= 1e-13 * scale, resid.max()
+    # between the endpoints of its edge (keys: element, low node, axis)
+    keys = r["edge_key"].astype(np.int64).reshape(-1)
+    axis = keys % 3
+    node = keys // 3
+    pp = n + 1
+    hi = node + np.array([1, pp, pp * pp])[axis]
+    for c, coord in enumerate((x, y, z)):
+        lo_c, hi_c = coord.reshape(-1)[node], coord.reshape(-1)[hi]
+        assert np.all(p[:, c] >= np.minimum(lo_c, hi_c) - 1e-12)
+        assert np.all(p[:, c] <= np.maximum(lo_c, hi_c) + 1e-12)
+
+
+def test_vertices_of_linear_field_lie_on_its_plane():
+    _plane_pin()
+
+
 def test_sphere_area_converges():
     radius = 0.9
     errs = []

@@ -237,6 +237,16 @@ def test_non_strict_comparison_is_caught():
 # C0 averaging and welding (oracle/c0.py)
 # --------------------------------------------------------------------------
 
+def test_vertex_measured_from_the_high_end_is_caught():
+    import test_oracle_mc as T
+
+    def from_high(x0, x1, f0, f1, c):
+        t = (c - f0) / (f1 - f0)
+        return x1 + t * (x0 - x1)              # t taken from the high corner
+    with patched(mc, "edge_vertex", from_high):
+        _fails(T._plane_pin)
+
+
 def test_c0_sum_without_division_is_caught():
     import test_oracle_c0 as T
     from oracle import c0
