@@ -1604,36 +1604,46 @@ __device__ __forceinline__ void dma_pass4(const double* __restrict__ raw,
 // computation past later barriers, which would keep its inputs live).
 __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
 
-// Butterfly reductions over a wave through ds_bpermute, with the partner
-// addresses ((lane ^ 2^k) * 4) computed once per thread: one LDS permute
-// per 32 bits and one VALU operation per step.
-struct WaveXor {
-  int a[6];
-};
-__device__ __forceinline__ WaveXor wave_xor_addrs(int lane) {
-  WaveXor w;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) w.a[k] = (lane ^ (1 << k)) << 2;
-  return w;
-}
-__device__ __forceinline__ double bperm_f64(int addr, double v) {
+// One DPP step on an FP64 value (its two 32-bit halves moved by the same
+// control); lanes the row mask leaves out read `fill`.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  // every lane reads a lane of its own row: no fill value needed
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)u);
-  const uint32_t hi = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(u >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-// (no NaN reaches these: callers map NaN to -inf first)
-__device__ __forceinline__ void wave_minmax_f64(const WaveXor& w, double& mn, double& mx) {
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    mn = fmin(mn, bperm_f64(w.a[k], mn));
-    mx = fmax(mx, bperm_f64(w.a[k], mx));
-  }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v, double fill) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v), f = __builtin_bit_cast(uint64_t, fill);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(
+      (int)(uint32_t)f, (int)(uint32_t)u, CTRL, ROWS, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+      (int)(uint32_t)(f >> 32), (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ int wave_sum_i32(const WaveXor& w, int v) {
-#pragma unroll
-  for (int k = 0; k < 6; ++k) v += __builtin_amdgcn_ds_bpermute(w.a[k], v);
-  return v;
+
+// Minimum and maximum over the wave, left in lane 63 (other lanes hold
+// partial results), by DPP moves only: within quads (quad_perm [1,0,3,2],
+// [2,3,0,1]), half rows (row_half_mirror), rows (row_mirror), then row 0's
+// and row 2's lane 15 into rows 1 and 3 (row_bcast:15) and lane 31 into
+// rows 2 and 3 (row_bcast:31).  No NaN reaches it: callers map NaN to -inf.
+__device__ __forceinline__ void wave_minmax_f64(double& mn, double& mx) {
+  const double pinf = pos_inf<double>(), ninf = neg_inf<double>();
+  mn = fmin(mn, dpp_f64<0xb1>(mn));
+  mx = fmax(mx, dpp_f64<0xb1>(mx));
+  mn = fmin(mn, dpp_f64<0x4e>(mn));
+  mx = fmax(mx, dpp_f64<0x4e>(mx));
+  mn = fmin(mn, dpp_f64<0x141>(mn));
+  mx = fmax(mx, dpp_f64<0x141>(mx));
+  mn = fmin(mn, dpp_f64<0x140>(mn));
+  mx = fmax(mx, dpp_f64<0x140>(mx));
+  mn = fmin(mn, dpp_f64<0x142, 0xa>(mn, pinf));
+  mx = fmax(mx, dpp_f64<0x142, 0xa>(mx, ninf));
+  mn = fmin(mn, dpp_f64<0x143, 0xc>(mn, pinf));
+  mx = fmax(mx, dpp_f64<0x143, 0xc>(mx, ninf));
 }
 
 // COUNT: also count every isovalue's triangles and active cells per element
@@ -1739,9 +1749,8 @@ __device__ __forceinline__ void qcount_dma7_elem(
     mn = c < mn ? c : mn;
     mx = c > mx ? c : mx;
   }
-  const WaveXor wx = wave_xor_addrs(p);
-  wave_minmax_f64(wx, mn, mx);
-  if (p == 0) {
+  wave_minmax_f64(mn, mx);
+  if (p == 63) {
     s_red[h] = mn;
     s_red[4 + h] = mx;
   }
