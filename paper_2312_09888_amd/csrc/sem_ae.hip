@@ -1697,7 +1697,10 @@ hipError_t launch_ae_compress(int64_t n_elem, const float* const* f, const float
   }
   e = launch_exclusive_scan(c.flag, n_elem, c.partial, c.offs, s);
   if (e != hipSuccess) return e;
-  if (n_raw) hipMemcpyAsync(n_raw, c.offs + n_elem, 8, hipMemcpyDeviceToDevice, s);
+  if (n_raw) {
+    e = hipMemcpyAsync(n_raw, c.offs + n_elem, 8, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
   if (n_elem > 0)
     hipLaunchKernelGGL(pack_raw, dim3((unsigned)cdiv(n_elem, kPackE)), dim3(kT), 0, s, n_elem,
                        f[0], f[1], f[2], f[3],

@@ -46,23 +46,60 @@ __device__ __forceinline__ float neg_inf<float>() { return -__builtin_huge_valf(
 template <typename T>
 __device__ __forceinline__ T pos_inf() { return -neg_inf<T>(); }
 
-template <typename T>
-__device__ __forceinline__ T wave_min(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    T o = __shfl_xor(v, off);
-    v = o < v ? o : v;
+// One DPP move of a 32- or 64-bit value (a 64-bit value as its two halves
+// under the same control).  With every row enabled each lane reads a lane of
+// its own row; lanes of rows that ROWS leaves out keep `fill`.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
   }
-  return v;
 }
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    T o = __shfl_xor(v, off);
-    v = o > v ? o : v;
+template <int CTRL, int ROWS, typename T>
+__device__ __forceinline__ T dpp_move(T v, T fill) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill),
+                                                             __builtin_bit_cast(int, v), CTRL,
+                                                             ROWS, 0xf, false));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v), f = __builtin_bit_cast(uint64_t, fill);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(
+        (int)(uint32_t)f, (int)(uint32_t)u, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+        (int)(uint32_t)(f >> 32), (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
   }
-  return v;
+}
+
+// Minimum and maximum over the wave, left in lane 63 (other lanes hold
+// partial results), by DPP moves only: within quads (quad_perm [1,0,3,2],
+// [2,3,0,1]), half rows (row_half_mirror), rows (row_mirror), then lane 15
+// of rows 0 and 2 into rows 1 and 3 (row_bcast:15) and lane 31 into rows 2
+// and 3 (row_bcast:31).  No NaN may reach it: callers map NaN to -inf.
+template <typename T>
+__device__ __forceinline__ void wave_minmax(T& mn, T& mx) {
+  const T pinf = pos_inf<T>(), ninf = neg_inf<T>();
+  mn = fmin(mn, dpp_move<0xb1>(mn));
+  mx = fmax(mx, dpp_move<0xb1>(mx));
+  mn = fmin(mn, dpp_move<0x4e>(mn));
+  mx = fmax(mx, dpp_move<0x4e>(mx));
+  mn = fmin(mn, dpp_move<0x141>(mn));
+  mx = fmax(mx, dpp_move<0x141>(mx));
+  mn = fmin(mn, dpp_move<0x140>(mn));
+  mx = fmax(mx, dpp_move<0x140>(mx));
+  mn = fmin(mn, dpp_move<0x142, 0xa>(mn, pinf));
+  mx = fmax(mx, dpp_move<0x142, 0xa>(mx, ninf));
+  mn = fmin(mn, dpp_move<0x143, 0xc>(mn, pinf));
+  mx = fmax(mx, dpp_move<0x143, 0xc>(mx, ninf));
 }
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -75,10 +112,9 @@ __device__ __forceinline__ T wave_sum(T v) {
 template <typename T, int THREADS>
 __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* scratch /*2*THREADS/64*/) {
   constexpr int W = THREADS / 64;
-  mn = wave_min(mn);
-  mx = wave_max(mx);
+  wave_minmax(mn, mx);
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
+  if ((threadIdx.x & 63) == 63) {
     scratch[w] = mn;
     scratch[W + w] = mx;
   }
@@ -807,9 +843,8 @@ __device__ __forceinline__ void pencil_multi_tail(int64_t e, int t, int ne,
       a = part[idx] < a ? part[idx] : a;
       b = part[Q::TH + idx] > b ? part[Q::TH + idx] : b;
     }
-    a = wave_min(a);
-    b = wave_max(b);
-    if (lane == 0) {
+    wave_minmax(a, b);
+    if (lane == 63) {
       if (qmm) {
         qmm[2 * (e + el)] = a;
         qmm[2 * (e + el) + 1] = b;
@@ -1604,48 +1639,6 @@ __device__ __forceinline__ void dma_pass4(const double* __restrict__ raw,
 // computation past later barriers, which would keep its inputs live).
 __device__ __forceinline__ void pin(double& x) { asm volatile("" : "+v"(x)); }
 
-// One DPP step on an FP64 value (its two 32-bit halves moved by the same
-// control); lanes the row mask leaves out read `fill`.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  // every lane reads a lane of its own row: no fill value needed
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-  const uint32_t hi =
-      (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_f64(double v, double fill) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v), f = __builtin_bit_cast(uint64_t, fill);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(
-      (int)(uint32_t)f, (int)(uint32_t)u, CTRL, ROWS, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
-      (int)(uint32_t)(f >> 32), (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xf, false);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Minimum and maximum over the wave, left in lane 63 (other lanes hold
-// partial results), by DPP moves only: within quads (quad_perm [1,0,3,2],
-// [2,3,0,1]), half rows (row_half_mirror), rows (row_mirror), then row 0's
-// and row 2's lane 15 into rows 1 and 3 (row_bcast:15) and lane 31 into
-// rows 2 and 3 (row_bcast:31).  No NaN reaches it: callers map NaN to -inf.
-__device__ __forceinline__ void wave_minmax_f64(double& mn, double& mx) {
-  const double pinf = pos_inf<double>(), ninf = neg_inf<double>();
-  mn = fmin(mn, dpp_f64<0xb1>(mn));
-  mx = fmax(mx, dpp_f64<0xb1>(mx));
-  mn = fmin(mn, dpp_f64<0x4e>(mn));
-  mx = fmax(mx, dpp_f64<0x4e>(mx));
-  mn = fmin(mn, dpp_f64<0x141>(mn));
-  mx = fmax(mx, dpp_f64<0x141>(mx));
-  mn = fmin(mn, dpp_f64<0x140>(mn));
-  mx = fmax(mx, dpp_f64<0x140>(mx));
-  mn = fmin(mn, dpp_f64<0x142, 0xa>(mn, pinf));
-  mx = fmax(mx, dpp_f64<0x142, 0xa>(mx, ninf));
-  mn = fmin(mn, dpp_f64<0x143, 0xc>(mn, pinf));
-  mx = fmax(mx, dpp_f64<0x143, 0xc>(mx, ninf));
-}
-
 // COUNT: also count every isovalue's triangles and active cells per element
 // from the Q tile (sem_extract); otherwise Q, |omega| and the range only.
 template <bool COUNT>
@@ -1749,7 +1742,7 @@ __device__ __forceinline__ void qcount_dma7_elem(
     mn = c < mn ? c : mn;
     mx = c > mx ? c : mx;
   }
-  wave_minmax_f64(mn, mx);
+  wave_minmax(mn, mx);
   if (p == 63) {
     s_red[h] = mn;
     s_red[4 + h] = mx;
@@ -2503,9 +2496,8 @@ __device__ __forceinline__ int batch_chunk(const coef_t<N, T>* dmat, const T* co
         mn = v < mn ? v : mn;
         mx = v > mx ? v : mx;
       }
-      mn = wave_min(mn);
-      mx = wave_max(mx);
-      if (lane == 0) {
+      wave_minmax(mn, mx);
+      if (lane == 63) {
         oqmm[2 * (e0 + wv)] = mn;
         oqmm[2 * (e0 + wv) + 1] = mx;
       }
