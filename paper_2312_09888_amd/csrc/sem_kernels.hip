@@ -1472,6 +1472,11 @@ scan_partials(int64_t* __restrict__ partial, int64_t nb) {
   if (threadIdx.x == 0) partial[nb] = running;
 }
 
+// Tiles' exclusive offsets.  FOLD: partial holds the tiles' sums, not yet
+// scanned (nb <= kScanFold), and each workgroup adds up the sums of the
+// tiles before it, which saves the one-workgroup scan of the partials.
+constexpr int64_t kScanFold = 1024;
+template <bool FOLD>
 __global__ void __launch_bounds__(kScanThreads)
 scan_apply(const int32_t* __restrict__ cnt, int64_t count, const int64_t* __restrict__ partial,
            int64_t nb, int64_t* __restrict__ offs) {
@@ -1484,21 +1489,31 @@ scan_apply(const int32_t* __restrict__ cnt, int64_t count, const int64_t* __rest
     v[r] = (start + r < count) ? cnt[start + r] : 0;
     s += v[r];
   }
+  int64_t base;
+  if constexpr (FOLD) {
+    int64_t b = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) b += partial[i];
+    base = block_sum<kScanThreads>(b, sred);
+  } else {
+    base = partial[blockIdx.x];
+  }
   int64_t total;
-  int64_t run = partial[blockIdx.x] + block_exclusive_scan<kScanThreads>(s, sred, &total);
+  int64_t run = base + block_exclusive_scan<kScanThreads>(s, sred, &total);
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r) {
     if (start + r < count) offs[start + r] = run;
     run += v[r];
   }
-  if (blockIdx.x == nb - 1 && threadIdx.x == 0) offs[count] = partial[nb];
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) offs[count] = FOLD ? base + total : partial[nb];
 }
 
+// Per-isovalue totals and the overflow flag, from the exclusive offsets
+// (thread s < n_iso takes isovalue s).
 template <typename T>
-__global__ void iso_totals(const int64_t* __restrict__ offs, int64_t n_elem, int n_iso,
-                           int64_t* __restrict__ tri_count, IsoOut<T> out,
-                           int32_t* __restrict__ status) {
-  const int s = threadIdx.x;
+__device__ __forceinline__ void write_totals(int s, const int64_t* __restrict__ offs,
+                                             int64_t n_elem, int n_iso,
+                                             int64_t* __restrict__ tri_count,
+                                             const IsoOut<T>& out, int32_t* __restrict__ status) {
   if (s < n_iso) {
     const int64_t c = offs[(int64_t)(s + 1) * n_elem] - offs[(int64_t)s * n_elem];
     tri_count[s] = c;
@@ -1506,6 +1521,13 @@ __global__ void iso_totals(const int64_t* __restrict__ offs, int64_t n_elem, int
   }
   if (s == 0 && status && !out.per_iso && offs[(int64_t)n_iso * n_elem] > out.cap[0])
     atomicOr(status, SEM_FLAG_TRI_OVERFLOW);
+}
+
+template <typename T>
+__global__ void iso_totals(const int64_t* __restrict__ offs, int64_t n_elem, int n_iso,
+                           int64_t* __restrict__ tri_count, IsoOut<T> out,
+                           int32_t* __restrict__ status) {
+  write_totals<T>(threadIdx.x, offs, n_elem, n_iso, tri_count, out, status);
 }
 
 __global__ void fill_i64(int64_t* __restrict__ p, int n, int64_t value) {
@@ -1960,7 +1982,11 @@ emit_direct(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
             const T* __restrict__ z, const T* __restrict__ field, int n_iso,
             IsoList<T> iso, IsoOut<T> out, const uint8_t* __restrict__ ntri_tab,
             const int32_t* __restrict__ cnt, const int64_t* __restrict__ offs,
-            uint64_t* __restrict__ keys) {
+            uint64_t* __restrict__ keys, int64_t* __restrict__ tri_count,
+            int32_t* __restrict__ status) {
+  // the last workgroup also writes the totals (in place of a kernel of its own)
+  if (blockIdx.x == gridDim.x - 1)
+    write_totals<T>(threadIdx.x, offs, n_elem, n_iso, tri_count, out, status);
   emit_elem<N, T>(blockIdx.x, threadIdx.x, n_elem, x, y, z, field, n_iso, iso, out, ntri_tab,
                   cnt, offs, keys);
 }
@@ -2900,6 +2926,25 @@ IsoList<T> make_isolist(int n_iso, const double* iso_host) {
 }
 
 // Scan of the per-(isovalue, element) counts, totals, then emission.
+// Exclusive scan of count int32 values into offs[0..count]: tile sums,
+// then the tiles' offsets (folded into the apply kernel when there are at
+// most kScanFold tiles, else through a one-workgroup scan of the sums).
+// `start` and `stop` (may be null) stamp the first and the last kernel.
+void scan_kernels(const int32_t* cnt, int64_t count, int64_t* partial, int64_t* offs,
+                  hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  const int64_t nb = scan_blocks(count);
+  hipExtLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, start,
+                        nullptr, 0, cnt, count, partial);
+  if (nb <= kScanFold) {
+    hipExtLaunchKernelGGL(scan_apply<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s,
+                          nullptr, stop, 0, cnt, count, (const int64_t*)partial, nb, offs);
+  } else {
+    hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, partial, nb);
+    hipExtLaunchKernelGGL(scan_apply<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s,
+                          nullptr, stop, 0, cnt, count, (const int64_t*)partial, nb, offs);
+  }
+}
+
 template <typename T>
 hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, const void* x,
                          const void* y, const void* z, const void* field, int n_iso,
@@ -2907,18 +2952,16 @@ hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, con
                          int64_t* tri_count, const IsoWorkspace& ws, int32_t* status,
                          hipStream_t s) {
   const int64_t count = (int64_t)n_iso * n_elem;
-  const int64_t nb = scan_blocks(count);
   const PhaseTimer ps = phase_timer(SEM_PHASE_SCAN);
-  hipExtLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ps.start,
-                        nullptr, 0, ws.cnt, count, ws.partial);
-  hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, ws.partial, nb);
-  hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.cnt, count,
-                     ws.partial, nb, ws.offs);
-  hipExtLaunchKernelGGL((iso_totals<T>), dim3(1), dim3(SEM_MAX_ISO), 0, s, nullptr, ps.stop, 0,
-                        ws.offs, n_elem, n_iso, tri_count, out, status);
+  scan_kernels(ws.cnt, count, ws.partial, ws.offs, s, ps.start, ps.stop);
   phase_done(ps);
   bool any_cap = false;
   for (int q = 0; q < (out.per_iso ? n_iso : 1); ++q) any_cap = any_cap || out.cap[q] > 0;
+  // the totals: a kernel of their own, unless the emission kernel for odd
+  // orders writes them
+  if (!any_cap || order % 2 == 0)
+    hipLaunchKernelGGL((iso_totals<T>), dim3(1), dim3(SEM_MAX_ISO), 0, s, (const int64_t*)ws.offs,
+                       n_elem, n_iso, tri_count, out, status);
   if (!any_cap) return hipGetLastError();
   const PhaseTimer pe = phase_timer(SEM_PHASE_EMIT);
   SEM_ORDER_SWITCH(order, {
@@ -2926,7 +2969,8 @@ hipError_t iso_scan_emit(int order, const DeviceTables& tab, int64_t n_elem, con
       hipExtLaunchKernelGGL((emit_direct<N, T>), dim3((unsigned)n_elem), dim3(128), 0, s,
                             pe.start, pe.stop, 0, n_elem, (const T*)x, (const T*)y,
                             (const T*)z, (const T*)field, n_iso, iso, out, tab.ntri,
-                            (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys);
+                            (const int32_t*)ws.cnt, (const int64_t*)ws.offs, keys, tri_count,
+                            status);
     } else {
       hipExtLaunchKernelGGL((iso_emit<N, T>), dim3((unsigned)n_elem),
                             dim3(Shape<N>::kCellThreads), 0, s, pe.start, pe.stop, 0, n_elem,
@@ -3274,12 +3318,7 @@ hipError_t launch_iso_batch(sem_dtype dt, const DeviceTables& tab, const void* p
       // one exclusive scan over every count slot, then the per-(job,
       // isovalue) totals
       const PhaseTimer ps = phase_timer(SEM_PHASE_SCAN);
-      const int64_t nb = scan_blocks(n_slots);
-      hipExtLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ps.start,
-                            nullptr, 0, ws.cnt, n_slots, ws.partial);
-      hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, ws.partial, nb);
-      hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, ws.cnt,
-                         n_slots, ws.partial, nb, ws.offs);
+      scan_kernels(ws.cnt, n_slots, ws.partial, ws.offs, s, ps.start, nullptr);
       const unsigned tb = (unsigned)((4 * (int64_t)n_job + 255) / 256);
       hipExtLaunchKernelGGL(iso_batch_totals, dim3(tb > 0 ? tb : 1), dim3(256), 0, s, nullptr,
                             ps.stop, 0, hdr, jobs, (const int64_t*)ws.offs, tri_offset,
@@ -3308,12 +3347,7 @@ hipError_t launch_tune_fill(sem_dtype dt, int order, int64_t n_elem, void* const
 
 hipError_t launch_exclusive_scan(const int32_t* cnt, int64_t count, int64_t* partial,
                                  int64_t* offs, hipStream_t s) {
-  const int64_t nb = scan_blocks(count);
-  hipLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cnt, count,
-                     partial);
-  hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, partial, nb);
-  hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, cnt, count,
-                     partial, nb, offs);
+  scan_kernels(cnt, count, partial, offs, s, nullptr, nullptr);
   return hipGetLastError();
 }
 
