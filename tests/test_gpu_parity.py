@@ -255,6 +255,42 @@ def test_isosurface_overflow_and_exact_counts():
             np.testing.assert_array_equal(host(tri)[:cap], o["tri_xyz"][:cap])
 
 
+@pytest.mark.parametrize("n_elem", [65536, 65537])
+def test_isosurface_scan_tile_boundary(n_elem):
+    # 64 isovalues x n_elem counts make 1,024 scan tiles of 4,096 (the tile
+    # offsets folded into the apply kernel) or 1,025 (a separate scan of the
+    # tile sums); order-1 elements, one cell each, random node values
+    rng = np.random.default_rng(n_elem)
+    o = np.array([0.0, 1.0])
+    kk, jj, ii = np.meshgrid(o, o, o, indexing="ij")
+    e = np.arange(n_elem, dtype=np.float64)[:, None, None, None]
+    x = ii[None] + 2.0 * (e % 256)
+    y = jj[None] + 2.0 * (e // 256)
+    z = np.broadcast_to(kk[None], (n_elem, 2, 2, 2)).copy()
+    f = rng.uniform(-1.0, 1.0, size=(n_elem, 2, 2, 2))
+    isos = [float(c) for c in np.linspace(-0.9, 0.9, 64)]
+    st = status_word()
+    r = sem.isosurface(*(dev(a) for a in (x, y, z, f)), isos, status=st)
+    assert int(st.item()) == 0
+    ntri, _ = mc.case_table()
+    per = np.stack([ntri[mc.classify(f, c).reshape(n_elem, -1)[:, 0]].astype(np.int64)
+                    for c in isos])                       # (isovalue, element)
+    np.testing.assert_array_equal(host(r["tri_count"]), per.sum(axis=1))
+    # the soup is isovalue-major: triangles of elements at tile edges
+    first = np.concatenate([[0], np.cumsum(per.ravel())])
+    scale = float(np.abs(x).max())
+    for s, el in ((0, 0), (0, 4095), (0, 4096), (15, 65535), (31, 12345), (63, n_elem - 1),
+                  (63, n_elem - 2)):
+        k = s * n_elem + el
+        c = int(per[s, el])
+        got = host(r["tri_xyz"][int(first[k]):int(first[k]) + c])
+        want = mc.extract(x[el:el + 1], y[el:el + 1], z[el:el + 1], f[el:el + 1],
+                          [isos[s]])["tri_xyz"]
+        assert got.shape == want.shape
+        if c:
+            assert np.abs(got - want).max() <= TOL[np.float64] * scale
+
+
 def test_isosurface_empty_input():
     e = torch.empty((0, 8, 8, 8), dtype=torch.float64, device=DEV)
     cnt = torch.full((2,), 99, dtype=torch.int64, device=DEV)
