@@ -275,6 +275,13 @@ __device__ __forceinline__ double sqrt_refined(double x) {
   return sq;
 }
 
+// Root of |omega|^2: FP32 takes the hardware square root (v_sqrt_f32, within
+// 1 ulp; the correctly rounded form adds range scaling and a correction of
+// the last bit, a dozen instructions per node), FP64 the refined estimate
+// above.
+__device__ __forceinline__ float vort_root(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double vort_root(double x) { return sqrt_refined(x); }
+
 // The adjugate of J (det J times J^-1, same layout as InvJac) and 1 / det J.
 __device__ __forceinline__ bool adjugate_jacobian(double xr, double xs, double xt, double yr,
                                                   double ys, double yt, double zr, double zs,
@@ -378,7 +385,7 @@ __device__ __forceinline__ void qcrit_tile_elem(
     const T w1 = a[2][1] - a[1][2], w2 = a[0][2] - a[2][0], w3 = a[1][0] - a[0][1];
     qv = T(-0.5) * tr2;
     if (q) q[base + t] = qv;
-    if (om) om[base + t] = sqrt(w1 * w1 + w2 * w2 + w3 * w3);
+    if (om) om[base + t] = vort_root(w1 * w1 + w2 * w2 + w3 * w3);
     if (qv != qv) qv = neg_inf<T>();
   }
   bad = __syncthreads_or(bad);
@@ -724,7 +731,7 @@ __device__ __forceinline__ bool pencil_qcrit(const T* gx, const T* gy, const T* 
     const T a22 = fr[ii] * K.rz + fs[ii] * K.sz + ft[ii] * K.tz;
     qv[ii] = T(-0.5) * (qv[ii] + a22 * a22 + T(2) * (a02[ii] * a20 + a12[ii] * a21));
     const T w1 = a21 - a12[ii], w2 = a02[ii] - a20;
-    om[ii] = sqrt(om[ii] + w1 * w1 + w2 * w2);
+    om[ii] = vort_root(om[ii] + w1 * w1 + w2 * w2);
   }
   return ok;
 }
@@ -2388,7 +2395,7 @@ mixed7(const double* __restrict__ dmat, const float* __restrict__ x,
       const float qv = -0.5f * tr2;
       const int64_t o = base + t + 256 * h;
       if (o0) o0[o] = qv;
-      if (o1) o1[o] = sqrtf(w1 * w1 + w2 * w2 + w3 * w3);
+      if (o1) o1[o] = vort_root(w1 * w1 + w2 * w2 + w3 * w3);
       qn[h] = qv;
       if constexpr (COUNT) bits[t + 256 * h] = iso_bits4<float>(qv, sink.iso, 0, sink.n_iso);
       const float c = qv != qv ? neg_inf<float>() : qv;
@@ -2500,7 +2507,7 @@ __device__ __forceinline__ int batch_chunk(const coef_t<N, T>* dmat, const T* co
     const T qv = T(-0.5) * tr2;
     const int64_t o = e0 * P3 + q;
     if (oq) oq[o] = qv;
-    if (oom) oom[o] = sqrt(w1 * w1 + w2 * w2 + w3 * w3);
+    if (oom) oom[o] = vort_root(w1 * w1 + w2 * w2 + w3 * w3);
     qkeep[r] = qv != qv ? neg_inf<T>() : qv;
     // one node at a time: no overlap of the unrolled iterations (which
     // would multiply the live registers)
