@@ -148,9 +148,10 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the element-parallel extraction needs no communication; see the "
-              "sharding design).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the element-parallel extraction needs no communication between "
+              "GPUs; each would take its own share of the elements).  Run with "
+              "--gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
