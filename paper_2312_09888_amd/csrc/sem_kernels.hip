@@ -1938,8 +1938,9 @@ __device__ __forceinline__ void emit_elem(int64_t e, int t, int64_t n_elem,
   const int64_t base = e * NP;
   // the triangle counts (256 B) and the tiles arrive by direct loads before
   // the one wait below; the case table (3.75 KiB) is read through the caches
-  // in the vertex loop, which leaves LDS room for a seventh workgroup per
-  // CU at FP64 (emission 0.319 -> 0.307 ms on the channel snapshot)
+  // in the vertex loop, which takes the FP64 workgroup from 24.3 to 20.4 KB
+  // of LDS, six to eight per CU (emission 0.319 -> 0.307 ms on the channel
+  // snapshot)
   if (h == 0 && p < 16)
     lds_load16(reinterpret_cast<const double*>(ntri_tab) + 2 * p,
                reinterpret_cast<double*>(s_tab));
