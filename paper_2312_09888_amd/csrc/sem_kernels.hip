@@ -772,6 +772,17 @@ __device__ __forceinline__ uint32_t row_sum16(uint32_t v) {
   return v;
 }
 
+// Sum over the wave, left in lane 63 (other lanes hold partial sums): the
+// row sums above, then lane 15 of rows 0 and 2 added into rows 1 and 3
+// (row_bcast:15) and lane 31 into rows 2 and 3 (row_bcast:31); lanes of the
+// rows a row mask leaves out add 0.  Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_sum_to63(uint32_t v) {
+  v = row_sum16(v);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
 // Order-7 cell c = i + 7 j + 49 k has corner 0 at node i + 8 j + 64 k =
 // c + c / 7 + 8 (c / 49); the divisions by multiply and shift, exact for
 // c < 512 (the rounding errors stay below the gap to the next integer).
@@ -906,8 +917,8 @@ __device__ __forceinline__ void pencil_multi_tail(int64_t e, int t, int ne,
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           if (s < m) {
-            const int sum = wave_sum(packed[s]);
-            if (lane == 0) {
+            const int sum = (int)wave_sum_to63((uint32_t)packed[s]);
+            if (lane == 63) {
               sink->cnt[(int64_t)(g + s) * sink->n_elem + e + el] = sum & 0xffff;
               const int a = sum >> 16;
               if (sink->active && a)
@@ -1375,9 +1386,8 @@ iso_count(int64_t n_elem, const T* __restrict__ field, const T* __restrict__ mm,
       packed = s_ntri[cs] + ((cs != 0 && cs != 255) << 16);
       if (cdump) cdump[t] = (uint8_t)cs;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
-    if ((t & 63) == 0) sred[t >> 6] = packed;
+    packed = (int)wave_sum_to63((uint32_t)packed);
+    if ((t & 63) == 63) sred[t >> 6] = packed;
     __syncthreads();
     if (t == 0) {
       int sum = 0;
@@ -2090,9 +2100,8 @@ __device__ __forceinline__ void count_elem(int64_t e, int t, int64_t n_elem,
       if (t == 0) cnt[(int64_t)s * n_elem + e] = 0;
       continue;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) packed += __shfl_xor(packed, off);
-    if (lane == 0) s_sum[h] = packed;
+    packed = (int)wave_sum_to63((uint32_t)packed);
+    if (lane == 63) s_sum[h] = packed;
     __syncthreads();
     if (t == 0) {
       const int sum = s_sum[0] + s_sum[1];
