@@ -50,13 +50,40 @@ __device__ __forceinline__ float half_round(float v) {
   return __half2float(__float2half_rn(v));
 }
 
+// One DPP move of a 32-bit value; lanes of rows that ROWS leaves out read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_or_zero(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+}
+
+// Maximum of non-negative, non-NaN values over the wave, in every lane: DPP
+// moves within quads (quad_perm [1,0,3,2], [2,3,0,1]), half rows
+// (row_half_mirror) and rows (row_mirror), then lane 15 of rows 0 and 2 into
+// rows 1 and 3 (row_bcast:15) and lane 31 into rows 2 and 3 (row_bcast:31)
+// leave it in lane 63 (0 is neutral for the rows a mask leaves out), which
+// is read back as a scalar.  Every lane of the wave must be active.
+__device__ __forceinline__ float wave_max_pos(float v) {
+  v = fmaxf(v, dpp_or_zero<0xb1, 0xf>(v));
+  v = fmaxf(v, dpp_or_zero<0x4e, 0xf>(v));
+  v = fmaxf(v, dpp_or_zero<0x141, 0xf>(v));
+  v = fmaxf(v, dpp_or_zero<0x140, 0xf>(v));
+  v = fmaxf(v, dpp_or_zero<0x142, 0xa>(v));
+  v = fmaxf(v, dpp_or_zero<0x143, 0xc>(v));
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
 template <typename T>
 __device__ __forceinline__ T block_max_pos(T v, T* red) {
   // max of non-negative values over a 256-thread block
+  if constexpr (std::is_same<T, float>::value) {
+    v = wave_max_pos(v);
+  } else {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const T o = __shfl_xor(v, off);
-    v = o > v ? o : v;
+    for (int off = 32; off > 0; off >>= 1) {
+      const T o = __shfl_xor(v, off);
+      v = o > v ? o : v;
+    }
   }
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -113,12 +140,7 @@ gmax_k(const float* __restrict__ scale, int64_t n, uint32_t* __restrict__ gmax_b
     m[3] = x.w > m[3] ? x.w : m[3];
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float o = __shfl_xor(m[c], off);
-      m[c] = o > m[c] ? o : m[c];
-    }
+  for (int c = 0; c < 4; ++c) m[c] = wave_max_pos(m[c]);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
     for (int c = 0; c < 4; ++c) red[w][c] = m[c];
@@ -980,11 +1002,7 @@ ae_encode(int64_t n_elem, const float* __restrict__ u, const float* __restrict__
         const float a = fabsf(vv[q]);
         mx = a > mx ? a : mx;
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const float o = __shfl_xor(mx, off);
-        mx = o > mx ? o : mx;
-      }
+      mx = wave_max_pos(mx);
       if (lane == 0) {
         smax[wv][c] = mx;
         if (ok) scale[e * 4 + c] = mx;
