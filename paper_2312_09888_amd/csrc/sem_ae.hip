@@ -1659,7 +1659,7 @@ CompressWs compress_layout(void* base, int64_t n_elem) {
   };
   c.flag = reinterpret_cast<int32_t*>(take((size_t)(n_elem + 1) * 4));
   c.offs = reinterpret_cast<int64_t*>(take((size_t)(n_elem + 1) * 8));
-  c.partial = reinterpret_cast<int64_t*>(take((size_t)(scan_blocks(n_elem + 1) + 1) * 8));
+  c.partial = reinterpret_cast<int64_t*>(take((size_t)(scan_partials_capacity(n_elem) + 1) * 8));
   c.gmax = reinterpret_cast<uint32_t*>(take(16));
   c.fold = reinterpret_cast<float*>(take((size_t)kFoldFloats * 4));
   c.gpart = reinterpret_cast<float*>(take((size_t)(cdiv(n_elem, kEncE) + 1) * 4 * 4));

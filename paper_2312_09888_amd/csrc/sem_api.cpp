@@ -91,7 +91,7 @@ IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso) {
   const int64_t count = (int64_t)n_iso * n_elem;
   const size_t b_cnt = align256((size_t)count * sizeof(int32_t));
   const size_t b_offs = align256((size_t)(count + 1) * sizeof(int64_t));
-  const size_t b_part = align256((size_t)(scan_blocks(count) + 1) * sizeof(int64_t));
+  const size_t b_part = align256((size_t)(scan_partials_capacity(count) + 1) * sizeof(int64_t));
   IsoWorkspace ws;
   char* p = static_cast<char*>(base);
   ws.cnt = reinterpret_cast<int32_t*>(p);

@@ -206,7 +206,7 @@ GsLayout gs_layout(void* base, int64_t n_nodes, int64_t n_global) {
   GsLayout l;
   const size_t b_cnt = al256((size_t)n_global * sizeof(int32_t));
   const size_t b_row = al256((size_t)(n_global + 1) * sizeof(int64_t));
-  const size_t b_par = al256((size_t)(scan_blocks(n_global) + 1) * sizeof(int64_t));
+  const size_t b_par = al256((size_t)(scan_partials_capacity(n_global) + 1) * sizeof(int64_t));
   const size_t b_col = al256((size_t)n_nodes * sizeof(int64_t));
   char* p = static_cast<char*>(base);
   l.cnt = reinterpret_cast<int32_t*>(p);
@@ -263,7 +263,7 @@ WeldLayout weld_layout(void* base, int64_t n_ref) {
   const size_t b_key = al256((size_t)cap * sizeof(uint64_t));
   const size_t b_slot = al256((size_t)n_ref * sizeof(int32_t));
   const size_t b_offs = al256((size_t)(n_ref + 1) * sizeof(int64_t));
-  const size_t b_par = al256((size_t)(scan_blocks(n_ref) + 1) * sizeof(int64_t));
+  const size_t b_par = al256((size_t)(scan_partials_capacity(n_ref) + 1) * sizeof(int64_t));
   char* p = static_cast<char*>(base);
   size_t o = 0;
   w.key = reinterpret_cast<uint64_t*>(p ? p + o : nullptr);

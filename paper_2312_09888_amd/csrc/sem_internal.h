@@ -64,7 +64,26 @@ struct IsoWorkspace {
   size_t bytes;
 };
 IsoWorkspace iso_workspace_layout(void* base, int64_t n_elem, int n_iso);
+
+// Exclusive-scan tiling, shared by the kernels and every workspace that
+// holds the tile sums: tiles of 1,024 counts up to kScanSmall counts (more
+// workgroups, a shorter chain per tile), of 4,096 above.
+constexpr int64_t kScanSmall = int64_t(1) << 20;
+constexpr int64_t scan_tile(int64_t count) { return count <= kScanSmall ? 1024 : 4096; }
+constexpr int64_t scan_tiles(int64_t count) {
+  return count <= 0 ? 1 : (count + scan_tile(count) - 1) / scan_tile(count);
+}
+// Tile sums a scan of `count` values writes (scan_tiles(count)).
 int64_t scan_blocks(int64_t count);
+// Tile sums to reserve for a scan of `count` values: at least
+// scan_tiles(count), and never fewer for a larger count (the tile count
+// itself drops where the tile grows), so that workspace sizes grow with
+// the problem.
+constexpr int64_t scan_partials_capacity(int64_t count) {
+  return count <= kScanSmall ? scan_tiles(count)
+                             : (scan_tiles(count) > kScanSmall / 1024 ? scan_tiles(count)
+                                                                      : kScanSmall / 1024);
+}
 
 // Exclusive prefix of count int32 values into offs[0..count] (offs[count] =
 // total); partial holds scan_blocks(count) + 1 int64.

@@ -1457,16 +1457,16 @@ iso_emit(int64_t n_elem, const T* __restrict__ x, const T* __restrict__ y,
 // ---------------------------------------------------------------------------
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;
 
+// Tile sums; a tile is kScanThreads x ITEMS counts (scan_tile).
+template <int ITEMS>
 __global__ void __launch_bounds__(kScanThreads)
 scan_reduce(const int32_t* __restrict__ cnt, int64_t count, int64_t* __restrict__ partial) {
   __shared__ int64_t sred[kScanThreads / 64];
-  const int64_t start = (int64_t)blockIdx.x * kScanTile;
+  const int64_t start = (int64_t)blockIdx.x * (kScanThreads * ITEMS);
   int64_t s = 0;
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t idx = start + r * kScanThreads + threadIdx.x;
     if (idx < count) s += cnt[idx];
   }
@@ -1493,16 +1493,17 @@ scan_partials(int64_t* __restrict__ partial, int64_t nb) {
 // scanned (nb <= kScanFold), and each workgroup adds up the sums of the
 // tiles before it, which saves the one-workgroup scan of the partials.
 constexpr int64_t kScanFold = 1024;
-template <bool FOLD>
+template <bool FOLD, int ITEMS>
 __global__ void __launch_bounds__(kScanThreads)
 scan_apply(const int32_t* __restrict__ cnt, int64_t count, const int64_t* __restrict__ partial,
            int64_t nb, int64_t* __restrict__ offs) {
   __shared__ int64_t sred[kScanThreads / 64];
-  const int64_t start = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  int32_t v[kScanItems];
+  const int64_t start =
+      (int64_t)blockIdx.x * (kScanThreads * ITEMS) + (int64_t)threadIdx.x * ITEMS;
+  int32_t v[ITEMS];
   int64_t s = 0;
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     v[r] = (start + r < count) ? cnt[start + r] : 0;
     s += v[r];
   }
@@ -1517,7 +1518,7 @@ scan_apply(const int32_t* __restrict__ cnt, int64_t count, const int64_t* __rest
   int64_t total;
   int64_t run = base + block_exclusive_scan<kScanThreads>(s, sred, &total);
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     if (start + r < count) offs[start + r] = run;
     run += v[r];
   }
@@ -2946,20 +2947,31 @@ IsoList<T> make_isolist(int n_iso, const double* iso_host) {
 // Exclusive scan of count int32 values into offs[0..count]: tile sums,
 // then the tiles' offsets (folded into the apply kernel when there are at
 // most kScanFold tiles, else through a one-workgroup scan of the sums).
-// `start` and `stop` (may be null) stamp the first and the last kernel.
-void scan_kernels(const int32_t* cnt, int64_t count, int64_t* partial, int64_t* offs,
-                  hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+// Tiles of 1,024 counts up to kScanSmall counts (always folded), else of
+// 4,096 (scan_tile).  `start` and `stop` (may be null) stamp the first and
+// the last kernel.
+template <int ITEMS>
+void scan_kernels_t(const int32_t* cnt, int64_t count, int64_t* partial, int64_t* offs,
+                    hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  static_assert(kScanThreads * ITEMS == 1024 || kScanThreads * ITEMS == 4096, "scan_tile");
   const int64_t nb = scan_blocks(count);
-  hipExtLaunchKernelGGL(scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, start,
+  hipExtLaunchKernelGGL(scan_reduce<ITEMS>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, start,
                         nullptr, 0, cnt, count, partial);
   if (nb <= kScanFold) {
-    hipExtLaunchKernelGGL(scan_apply<true>, dim3((unsigned)nb), dim3(kScanThreads), 0, s,
-                          nullptr, stop, 0, cnt, count, (const int64_t*)partial, nb, offs);
+    hipExtLaunchKernelGGL((scan_apply<true, ITEMS>), dim3((unsigned)nb), dim3(kScanThreads), 0,
+                          s, nullptr, stop, 0, cnt, count, (const int64_t*)partial, nb, offs);
   } else {
     hipLaunchKernelGGL(scan_partials, dim3(1), dim3(1024), 0, s, partial, nb);
-    hipExtLaunchKernelGGL(scan_apply<false>, dim3((unsigned)nb), dim3(kScanThreads), 0, s,
-                          nullptr, stop, 0, cnt, count, (const int64_t*)partial, nb, offs);
+    hipExtLaunchKernelGGL((scan_apply<false, ITEMS>), dim3((unsigned)nb), dim3(kScanThreads), 0,
+                          s, nullptr, stop, 0, cnt, count, (const int64_t*)partial, nb, offs);
   }
+}
+void scan_kernels(const int32_t* cnt, int64_t count, int64_t* partial, int64_t* offs,
+                  hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+  if (scan_tile(count) == 1024)
+    scan_kernels_t<1024 / kScanThreads>(cnt, count, partial, offs, s, start, stop);
+  else
+    scan_kernels_t<4096 / kScanThreads>(cnt, count, partial, offs, s, start, stop);
 }
 
 template <typename T>
@@ -3139,7 +3151,7 @@ hipError_t extract_t(int order, sem_dtype dt, const DeviceTables& tab, int64_t n
 
 }  // namespace
 
-int64_t scan_blocks(int64_t count) { return count <= 0 ? 1 : (count + kScanTile - 1) / kScanTile; }
+int64_t scan_blocks(int64_t count) { return scan_tiles(count); }
 
 size_t batch_plan_bytes(int n_snap) {
   return 256 + (((size_t)n_snap * sizeof(BatchSnap) + 255) & ~size_t(255));

@@ -9,11 +9,13 @@ namespace sem {
 // counts, int64 offsets (one more than the counts) and int64 scan partials,
 // each 256-byte aligned, as iso_workspace_layout places them.
 constexpr int64_t kNoallocCounts = SEM_NOALLOC_MAX_COUNTS;
-constexpr size_t kNoallocScanTile = 4096;   // counts per scan block (kScanTile)
 constexpr size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
+// every count up to kNoallocCounts takes the 1,024-count tiles, so the
+// largest count has the most tile sums
+static_assert(kNoallocCounts <= kScanSmall, "one tile size for every count the scratch takes");
 constexpr size_t kNoallocBytes =
     align_up(sizeof(int32_t) * kNoallocCounts) + align_up(sizeof(int64_t) * (kNoallocCounts + 1)) +
-    align_up(sizeof(int64_t) * ((kNoallocCounts + kNoallocScanTile - 1) / kNoallocScanTile + 1));
+    align_up(sizeof(int64_t) * (scan_partials_capacity(kNoallocCounts) + 1));
 
 }  // namespace sem
 
