@@ -101,10 +101,19 @@ __device__ __forceinline__ void wave_minmax(T& mn, T& mx) {
   mn = fmin(mn, dpp_move<0x143, 0xc>(mn, pinf));
   mx = fmax(mx, dpp_move<0x143, 0xc>(mx, ninf));
 }
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+// Inclusive sum of a 64-bit value over the lanes up to this one (lane 63:
+// the wave's sum), by DPP moves of both halves: row shifts right by 1, 2,
+// 4, 8 (lanes without a source add 0), then lane 15 of rows 0 and 2 into
+// rows 1 and 3 (row_bcast:15) and lane 31 into rows 2 and 3
+// (row_bcast:31).  Every lane of the wave must be active.
+__device__ __forceinline__ int64_t wave_inclusive_sum(int64_t v) {
+  const int64_t z = 0;
+  v += dpp_move<0x111, 0xf>(v, z);
+  v += dpp_move<0x112, 0xf>(v, z);
+  v += dpp_move<0x114, 0xf>(v, z);
+  v += dpp_move<0x118, 0xf>(v, z);
+  v += dpp_move<0x142, 0xa>(v, z);
+  v += dpp_move<0x143, 0xc>(v, z);
   return v;
 }
 
@@ -133,8 +142,8 @@ __device__ __forceinline__ void block_minmax(T& mn, T& mx, T* scratch /*2*THREAD
 template <int THREADS>
 __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* scratch /*THREADS/64*/) {
   constexpr int W = THREADS / 64;
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = v;
+  v = wave_inclusive_sum(v);
+  if ((threadIdx.x & 63) == 63) scratch[threadIdx.x >> 6] = v;
   __syncthreads();
   int64_t s = 0;
 #pragma unroll
@@ -149,12 +158,7 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* scra
                                                         int64_t* total) {
   constexpr int W = THREADS / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int64_t inc = v;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    int64_t o = __shfl_up(inc, off);
-    if (lane >= off) inc += o;
-  }
+  const int64_t inc = wave_inclusive_sum(v);
   if (lane == 63) scratch[w] = inc;
   __syncthreads();
   int64_t before = 0, all = 0;
