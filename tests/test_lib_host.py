@@ -143,6 +143,20 @@ def test_workspace_size_grows_with_problem():
     assert sem.workspace_bytes(10, 7, 0) == 0
 
 
+def test_workspace_size_never_shrinks_across_the_scan_tile_change():
+    # the scan's tiles grow from 1,024 to 4,096 counts above 2^20 counts, so
+    # the tile count drops there; the workspaces reserve tile sums that never
+    # shrink, so a workspace sized for a problem also fits every smaller one
+    for n_iso in (1, 4):
+        lo = (1 << 20) // n_iso - 3
+        sizes = [sem.workspace_bytes(e, 7, n_iso) for e in range(lo, lo + 8)]
+        assert sizes == sorted(sizes)
+        sizes = [sem.extract_workspace_bytes(e, 7, n_iso) for e in range(lo, lo + 8)]
+        assert sizes == sorted(sizes)
+    big = [sem.workspace_bytes(e, 7, 1) for e in ((1 << 22) - 1, 1 << 22, (1 << 22) + 1)]
+    assert big == sorted(big)
+
+
 def _no_gpu():
     try:
         import torch
